@@ -1,0 +1,190 @@
+"""Pins of the oracle's FIRE 2.0 loop (Algorithm 2, semi-implicit Euler with
+mixing after the kick as in Algorithm 4; Table 1 parameter semantics; the stop
+criteria of Sec. 3.4) against closed forms on quadratic wells, where the
+dynamics reduce to the textbook symplectic-Euler map of a harmonic oscillator.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_02038_amd import inputs
+
+OPEN = inputs.Box((-1e3, -1e3, -1e3), (2e3, 2e3, 2e3), (0, 0, 0))
+
+
+def well(k):
+    return inputs.harmonic_potential(k)
+
+
+def params(**over):
+    p = inputs.fire_params(0.1, 1.0, tmax=10.0, alpha0=0.1, delaystep=5, dtgrow=1.1, dtshrink=0.5)
+    p.update(over)
+    return p
+
+
+def run(x0, k, max_steps, **over):
+    pos = np.array([x0], dtype=float)
+    return oracle.fire_minimize(pos, OPEN, well(k), params(**over), 0.0, max_steps, trace=True)
+
+
+def test_first_two_steps_of_1d_well_are_symplectic_euler():
+    k, dt, x0 = 2.0, 0.1, 1.5
+    r1 = run([x0, 0, 0], (k, 0, 0), 1, dt_start=dt)
+    assert r1["pos"][0, 0] == pytest.approx(x0 * (1 - k * dt * dt), rel=1e-15)
+    r2 = run([x0, 0, 0], (k, 0, 0), 2, dt_start=dt)
+    x2 = x0 * (1 - 3 * k * dt ** 2 + k * k * dt ** 4)
+    assert r2["pos"][0, 0] == pytest.approx(x2, rel=1e-14)
+    tr = r2["trace"]
+    assert tr[1, 7] == -1 and tr[1, 4] == 0.0  # i = 1: P = 0 goes to the P <= 0 branch
+    assert tr[2, 7] == 1 and tr[2, 8] == 1  # i = 2: P > 0, N_P>0 = 1
+    assert tr[2, 5] == dt and tr[2, 6] == 0.1  # still inside the delay
+
+
+def test_half_step_back_after_overshoot():
+    """k dt^2 = 1.44 overshoots at i = 1; at i = 2 P < 0, so x goes back by
+    dt v / 2 before v is zeroed, and the kick uses the force at the
+    uncorrected position."""
+    x0 = 1.0
+    r = run([x0, 0, 0], (1.0, 0, 0), 2, dt_start=1.2)
+    assert r["trace"][2, 7] == -1
+    # x1 = -0.44; back: -0.44 + 0.6 * 1.2 = 0.28; v = 1.2 * 0.44; x2 = 0.28 + 1.2 v
+    assert r["pos"][0, 0] == pytest.approx(0.28 + 1.2 * 1.2 * 0.44, rel=1e-14)
+    r = run([x0, 0, 0], (1.0, 0, 0), 2, dt_start=1.2, halfstepback=0)
+    assert r["pos"][0, 0] == pytest.approx(-0.44 + 1.2 * 1.2 * 0.44, rel=1e-14)
+
+
+def test_2d_anisotropic_well_mixing_by_hand():
+    k = np.array([1.0, 10.0])
+    x0 = np.array([1.0, 0.4])
+    dt, a0 = 0.05, 0.1
+    r = run([x0[0], x0[1], 0], (k[0], k[1], 0), 2, dt_start=dt, alpha0=a0)
+    # i = 1: v = 0, kick v = dt F0, mixing of a vector parallel to F is a no-op
+    f0 = -k * x0
+    v1 = dt * f0
+    x1 = x0 + dt * v1
+    # i = 2: P = F1.v1 > 0, N_P>0 = 1 <= delay: dt, alpha unchanged
+    f1 = -k * x1
+    assert float(f1 @ v1) > 0
+    v = v1 + dt * f1
+    v = (1 - a0) * v + a0 * np.linalg.norm(v) * f1 / np.linalg.norm(f1)
+    x2 = x1 + dt * v
+    assert np.allclose(r["pos"][0, :2], x2, rtol=1e-14, atol=0)
+    # the mixing is not a no-op here
+    assert abs(x2[1] - (x1 + dt * (v1 + dt * f1))[1]) > 1e-6
+
+
+def test_dt_and_alpha_schedules_after_the_delay():
+    """On a soft well P stays > 0: from step N_delay + 1 on, dt grows by
+    dtgrow up to tmax * dt_start and alpha shrinks by alphashrink."""
+    dt0 = 0.01
+    r = run([1.0, 0, 0], (1e-3, 0, 0), 60, dt_start=dt0, tmax=3.0)
+    tr = r["trace"]
+    assert np.all(tr[2:, 7] == 1)
+    for i in range(2, 61):
+        npos = i - 1  # P > 0 from i = 2
+        m = max(0, npos - 5)
+        dt_ref, a_ref = dt0, 0.1
+        for _ in range(m):
+            dt_ref = min(dt_ref * 1.1, 3.0 * dt0)
+            a_ref *= 0.99
+        assert tr[i, 5] == pytest.approx(dt_ref, rel=1e-14)
+        assert tr[i, 6] == pytest.approx(a_ref, rel=1e-14)
+    assert tr[60, 5] == 3.0 * dt0  # capped
+
+
+def test_vdfmax_zero_stops_at_first_iteration():
+    r = run([1.0, 0, 0], (1.0, 0, 0), 10, vdfmax=0)
+    assert r["stop"] == "maxvdotf" and r["iterations"] == 0 and r["force_evals"] == 1
+
+
+def test_initialdelay_off_shrinks_dt_at_first_iteration():
+    r = run([1.0, 0, 0], (1.0, 0, 0), 1, initialdelay=0)
+    assert r["trace"][1, 5] == 0.05 and r["trace"][1, 6] == 0.1
+    r = run([1.0, 0, 0], (1.0, 0, 0), 1, initialdelay=1)
+    assert r["trace"][1, 5] == 0.1
+
+
+def test_dt_floor_blocks_shrink_but_alpha_resets():
+    r = run([1.0, 0, 0], (1.0, 0, 0), 1, initialdelay=0, tmin=0.6, alpha0=0.2)
+    assert r["trace"][1, 5] == 0.1 and r["trace"][1, 6] == 0.2
+
+
+def test_consecutive_uphill_counter_and_stop():
+    """A stiff well with dt far beyond stability makes every step uphill:
+    the run ends with MAXVDOTF after vdfmax + 1 consecutive P <= 0 steps."""
+    r = run([1.0, 0, 0], (1.0, 0, 0), 1000, dt_start=5.0, vdfmax=7, tmin=1.0, initialdelay=0)
+    assert r["stop"] == "maxvdotf"
+    assert r["n_neg"] == 8
+    assert np.all(r["trace"][1:, 7] == -1)
+
+
+def test_converges_exactly_on_anisotropic_well():
+    k = (1.0, 10.0, 3.0)
+    pos = np.array([[1.0, -0.5, 0.7], [-0.2, 0.3, 0.9]])
+    tol = 1e-10
+    r = oracle.fire_minimize(pos, OPEN, well(k), params(dt_start=0.05), tol, 100000)
+    assert r["stop"] == "converged"
+    assert r["fmax"] < tol
+    assert np.abs(r["pos"]).max() < tol / min(k)
+    assert r["force_evals"] == r["iterations"] + 1
+
+
+def test_perfect_crystal_converges_without_iterating():
+    s = inputs.lj_box(4, nvac=0, noise=0.0)
+    r = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 1e-8, 10)
+    assert r["stop"] == "converged" and r["iterations"] == 0 and r["force_evals"] == 1
+
+
+def test_max_steps_stop():
+    r = run([1.0, 0, 0], (1.0, 0, 0), 1)
+    assert r["stop"] == "max_steps" and r["iterations"] == 1 and r["force_evals"] == 2
+
+
+def test_f2norm_criterion_is_stricter():
+    s = inputs.lj_small()
+    fm = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 1e-6, 5000)
+    f2 = oracle.fire_minimize(s.pos, s.box, s.potential, dict(s.fire, criterion="f2norm"), 1e-6, 5000)
+    assert fm["stop"] == f2["stop"] == "converged"
+    assert f2["f2norm"] < 1e-6 and fm["fmax"] < 1e-6
+    assert f2["iterations"] >= fm["iterations"]
+    assert fm["f2norm"] >= fm["fmax"]
+
+
+def test_original_fire_shrinks_at_first_step():
+    """Algorithm 1 has no initial delay: P = 0 at i = 1 halves dt at once."""
+    k, dt, x0 = 2.0, 0.1, 1.5
+    r = run([x0, 0, 0], (k, 0, 0), 1, dt_start=dt, variant="fire1")
+    assert r["pos"][0, 0] == pytest.approx(x0 * (1 - k * (dt / 2) ** 2), rel=1e-15)
+
+
+def test_explicit_euler_moves_one_evaluation_late():
+    """Algorithm 3 drifts with the old velocity: x1 = x0, x2 = x0 (1 - k dt^2)."""
+    k, dt, x0 = 2.0, 0.1, 1.5
+    r1 = run([x0, 0, 0], (k, 0, 0), 1, dt_start=dt, integrator="eulerexplicit")
+    assert r1["pos"][0, 0] == x0
+    r2 = run([x0, 0, 0], (k, 0, 0), 2, dt_start=dt, integrator="eulerexplicit")
+    assert r2["pos"][0, 0] == pytest.approx(x0 * (1 - k * dt * dt), rel=1e-15)
+
+
+def test_velocity_verlet_first_step():
+    """Algorithm 6 from rest: x1 = x0 (1 - k dt^2 / 2) and
+    v1 = -dt k (x0 + x1) / 2."""
+    k, dt, x0 = 2.0, 0.1, 1.5
+    r = oracle.fire_minimize(np.array([[x0, 0, 0]]), OPEN, well((k, 0, 0)),
+                             params(dt_start=dt, integrator="verlet"), 0.0, 1, want_velocity=True)
+    x1 = x0 * (1 - 0.5 * k * dt * dt)
+    assert r["pos"][0, 0] == pytest.approx(x1, rel=1e-15)
+    assert r["velocity"][0, 0] == pytest.approx(-0.5 * dt * k * (x0 + x1), rel=1e-14)
+
+
+def test_lj_small_relaxes_below_tolerance():
+    s = inputs.lj_small()
+    e0, _ = oracle.energy_forces(s.pos, s.box, s.potential)
+    r = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, s.tol, 20000)
+    assert r["stop"] == "converged" and r["fmax"] < s.tol
+    assert r["energy"] < e0
+    e1, f1 = oracle.energy_forces(r["pos"], s.box, s.potential)
+    assert e1 == r["energy"]
+    assert np.abs(f1.sum(0)).max() < 1e-12
