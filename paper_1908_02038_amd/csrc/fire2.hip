@@ -1,0 +1,1907 @@
+// fire2.hip -- single-system FIRE 2.0 hot path for MI355X (gfx950) and the C ABI.
+//
+// Per iteration (one force evaluation, the paper's unit of cost):
+//   k_update   FIRE 2.0 velocity/position step (Algorithm 2 branch outcome,
+//              half-step-back, semi-implicit Euler kick + mixing + drift of
+//              Algorithm 4; Algorithms 3/6 as options)
+//   k_*_density / k_*_force
+//              pair terms over a cell-sorted full neighbour list; the force
+//              epilogue reduces E, P = F.v, |F|^2, |v|^2, max |F_i|^2,
+//              max |v_i|^2 per block (wave64 shuffles -> LDS)
+//   k_control  fixed-order second reduction stage + the scalar FIRE 2.0
+//              logic (counters, dt/alpha, stop tests, mixing coefficients)
+// K iterations are captured in a hipGraph and replayed; every kernel exits at
+// once when the control record says the run is stopped or paused, and the
+// host only polls a 32-byte status word between replays.
+//
+// Layout in HBM, sorted by cell: pos double4 (x, y, z, w = F'(rho) for the
+// EAM form), v and F as three FP64 planes, atom_id (sorted slot -> caller
+// index), neighbour list int32 column-major [k][slot].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fire2.h"
+#include "fire2_internal.h"
+
+namespace fire {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-level reduction of NS sums followed by NM maxima; result valid in
+// thread 0.  Order is fixed by the thread layout, so results are
+// reproducible run to run.
+template <int NS, int NM>
+__device__ __forceinline__ void block_reduce(double (&v)[NS + NM]) {
+  __shared__ double red[kBlock / 64][NS + NM];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) v[k] = wave_sum(v[k]);
+#pragma unroll
+  for (int k = NS; k < NS + NM; ++k) v[k] = wave_max(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NS + NM; ++k) red[w][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) v[k] += red[q][k];
+#pragma unroll
+      for (int k = NS; k < NS + NM; ++k) v[k] = fmax(v[k], red[q][k]);
+    }
+  }
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD works
+// on one contiguous run of (spatially sorted) atoms and its L2 holds their
+// neighbours.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
+  return x * per + min(x, rem) + idx;
+}
+
+__device__ __forceinline__ void min_image(double& dx, double& dy, double& dz, const BoxDev& b) {
+  if (b.per[0]) dx -= b.L[0] * rint(dx * b.invL[0]);
+  if (b.per[1]) dy -= b.L[1] * rint(dy * b.invL[1]);
+  if (b.per[2]) dz -= b.L[2] * rint(dz * b.invL[2]);
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates plus two Newton steps.
+__device__ __forceinline__ double rcp_d(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+__device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsqrt_f(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  return y * fmaf(-0.5f * x * y, y, 1.5f);
+}
+
+__device__ __forceinline__ bool ctrl_running(const Ctrl* c) {
+  return __builtin_nontemporal_load(&c->status) == ST_RUNNING;
+}
+
+// ----------------------------------------------------------- stage in/out
+
+__global__ void k_stage_in(const double* __restrict__ src, int n, int ncap, double4* __restrict__ pos,
+                           double* __restrict__ vel, double* __restrict__ frc, int* __restrict__ id,
+                           int* __restrict__ flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = src[3 * i], y = src[3 * i + 1], z = src[3 * i + 2];
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) atomicOr(flags, ERR_NONFINITE);
+  pos[i] = make_double4(x, y, z, 0.0);
+  vel[i] = vel[ncap + i] = vel[2 * ncap + i] = 0.0;
+  frc[i] = frc[ncap + i] = frc[2 * ncap + i] = 0.0;
+  id[i] = i;
+}
+
+// Sorted-order vector (3 planes) from a caller-order AoS vector.
+__global__ void k_gather_vec(const double* __restrict__ src, int n, int ncap, const int* __restrict__ id,
+                             double* __restrict__ dst) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int a = id[s];
+  dst[s] = src[3 * a];
+  dst[ncap + s] = src[3 * a + 1];
+  dst[2 * ncap + s] = src[3 * a + 2];
+}
+
+__global__ void k_scatter_vec(const double* __restrict__ src, int n, int ncap, const int* __restrict__ id,
+                              double* __restrict__ dst) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int a = id[s];
+  dst[3 * a] = src[s];
+  dst[3 * a + 1] = src[ncap + s];
+  dst[3 * a + 2] = src[2 * ncap + s];
+}
+
+__global__ void k_stage_out_pos(const double4* __restrict__ pos, int n, const int* __restrict__ id, BoxDev box,
+                                double* __restrict__ dst) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  double4 p = pos[s];
+  double r[3] = {p.x, p.y, p.z};
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (box.per[d]) {
+      double t = r[d] - box.lo[d];
+      t -= box.L[d] * floor(t * box.invL[d]);
+      if (t >= box.L[d]) t -= box.L[d];
+      if (t < 0.0) t = 0.0;
+      r[d] = box.lo[d] + t;
+    }
+  int a = id[s];
+  dst[3 * a] = r[0];
+  dst[3 * a + 1] = r[1];
+  dst[3 * a + 2] = r[2];
+}
+
+// ------------------------------------------------------- cell-list build
+
+struct Grid {
+  int n[3];
+  int ncell;
+  double lo[3], inv[3];
+  int lo_off[3], hi_off[3];  // stencil offsets per axis
+};
+
+// Bounding box partials (min x,y,z then max x,y,z) per block.
+__global__ void k_bbox(const double4* __restrict__ pos, int n, double* __restrict__ part) {
+  __shared__ double sm[6][kBlock];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[6];
+  if (i < n) {
+    double4 p = pos[i];
+    v[0] = v[3] = p.x;
+    v[1] = v[4] = p.y;
+    v[2] = v[5] = p.z;
+  } else {
+    v[0] = v[1] = v[2] = INFINITY;
+    v[3] = v[4] = v[5] = -INFINITY;
+  }
+  for (int k = 0; k < 6; ++k) sm[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] = fmin(sm[k][threadIdx.x], sm[k][threadIdx.x + s]);
+      for (int k = 3; k < 6; ++k) sm[k][threadIdx.x] = fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 6; ++k) part[6 * blockIdx.x + k] = sm[k][0];
+}
+
+__device__ __forceinline__ int cell_coord(double x, const Grid& g, int d) {
+  int c = (int)floor((x - g.lo[d]) * g.inv[d]);
+  return min(max(c, 0), g.n[d] - 1);
+}
+
+// Wrap periodic coordinates into the box and count atoms per cell.
+__global__ void k_cell_count(double4* __restrict__ pos, int n, BoxDev box, Grid g, int* __restrict__ cell_of,
+                             int* __restrict__ count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double4 p = pos[i];
+  double r[3] = {p.x, p.y, p.z};
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (box.per[d]) {
+      double t = r[d] - box.lo[d];
+      t -= box.L[d] * floor(t * box.invL[d]);
+      if (t >= box.L[d]) t -= box.L[d];
+      if (t < 0.0) t = 0.0;
+      r[d] = box.lo[d] + t;
+    }
+  pos[i] = make_double4(r[0], r[1], r[2], p.w);
+  int c = cell_coord(r[0], g, 0) + g.n[0] * (cell_coord(r[1], g, 1) + g.n[1] * cell_coord(r[2], g, 2));
+  cell_of[i] = c;
+  atomicAdd(&count[c], 1);
+}
+
+// Exclusive scan of count[0..m) into start[0..m], one block.
+__global__ void k_scan(const int* __restrict__ count, int m, int* __restrict__ start) {
+  __shared__ int sm[1024];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < m; base += 1024) {
+    int i = base + threadIdx.x;
+    int v = i < m ? count[i] : 0;
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      int t = (int)threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
+      __syncthreads();
+      sm[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < m) start[i] = carry + sm[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += sm[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) start[m] = carry;
+}
+
+__global__ void k_cell_fill(const int* __restrict__ cell_of, int n, const int* __restrict__ start,
+                            int* __restrict__ cursor, int* __restrict__ order) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = cell_of[i];
+  order[start[c] + atomicAdd(&cursor[c], 1)] = i;
+}
+
+// Deterministic order inside each cell: by caller atom index.
+__global__ void k_cell_sort(const int* __restrict__ start, int ncell, const int* __restrict__ id,
+                            int* __restrict__ order) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  int b = start[c], e = start[c + 1];
+  for (int a = b + 1; a < e; ++a) {
+    int v = order[a], key = id[v], k = a - 1;
+    while (k >= b && id[order[k]] > key) {
+      order[k + 1] = order[k];
+      --k;
+    }
+    order[k + 1] = v;
+  }
+}
+
+__global__ void k_permute(const int* __restrict__ order, int n, int ncap, const double4* __restrict__ pos,
+                          const double* __restrict__ vel, const double* __restrict__ frc,
+                          const int* __restrict__ id, double4* __restrict__ pos2, double* __restrict__ vel2,
+                          double* __restrict__ frc2, int* __restrict__ id2) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int o = order[s];
+  pos2[s] = pos[o];
+  id2[s] = id[o];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    vel2[d * ncap + s] = vel[d * ncap + o];
+    frc2[d * ncap + s] = frc[d * ncap + o];
+  }
+}
+
+// Neighbour search over the cell stencil: count (FILL = false) or write the
+// full list (FILL = true) of atoms within rcs of each atom, cells in fixed
+// order, atoms of a cell in slot order.
+template <bool FILL>
+__global__ void k_nbr(const double4* __restrict__ pos, int n, BoxDev box, Grid g, const int* __restrict__ start,
+                      double rcs2, int stride, int kcap, int* __restrict__ nnbr, int* __restrict__ nbr,
+                      int* __restrict__ maxcount, int* __restrict__ flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double4 pi = pos[i];
+  int c[3] = {cell_coord(pi.x, g, 0), cell_coord(pi.y, g, 1), cell_coord(pi.z, g, 2)};
+  int cnt = 0;
+  bool overlap = false;
+  for (int oz = g.lo_off[2]; oz <= g.hi_off[2]; ++oz) {
+    int cz = c[2] + oz;
+    if (box.per[2]) cz = (cz + g.n[2]) % g.n[2];
+    else if (cz < 0 || cz >= g.n[2]) continue;
+    for (int oy = g.lo_off[1]; oy <= g.hi_off[1]; ++oy) {
+      int cy = c[1] + oy;
+      if (box.per[1]) cy = (cy + g.n[1]) % g.n[1];
+      else if (cy < 0 || cy >= g.n[1]) continue;
+      for (int ox = g.lo_off[0]; ox <= g.hi_off[0]; ++ox) {
+        int cx = c[0] + ox;
+        if (box.per[0]) cx = (cx + g.n[0]) % g.n[0];
+        else if (cx < 0 || cx >= g.n[0]) continue;
+        int cell = cx + g.n[0] * (cy + g.n[1] * cz);
+        for (int j = start[cell], e = start[cell + 1]; j < e; ++j) {
+          if (j == i) continue;
+          double4 pj = pos[j];
+          double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+          min_image(dx, dy, dz, box);
+          double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) overlap = true;
+          if (r2 < rcs2) {
+            if (FILL && cnt < kcap) nbr[(size_t)cnt * stride + i] = j;
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  if (overlap) atomicOr(flags, ERR_OVERLAP);
+  if (!FILL) {
+    nnbr[i] = cnt;
+    atomicMax(maxcount, cnt);
+  }
+}
+
+// ----------------------------------------------------------- FIRE update
+
+// One integration step of every atom with the coefficients the control
+// kernel prepared:
+//   P <= 0 (neg):  x -= hsb v;  v = 0                      (Algorithm 2)
+//   mix_first:     v = cv v + cf F                         (Algorithm 1)
+//   v += kick1 F;  [v = cv v + cf F];  x += dtx v;  v += kick2 F
+// semi-implicit Euler: kick1 = dt/m, kick2 = 0 (Algorithm 4); explicit Euler:
+// kick1 = 0, kick2 = dt/m (Algorithm 3); velocity Verlet: kick1 = dt/2m and
+// the second half kick in the force epilogue (Algorithm 6).
+__global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, double* __restrict__ vel,
+                                                   const double* __restrict__ frc, int n, int ncap,
+                                                   const Ctrl* __restrict__ ctrl) {
+  if (!ctrl_running(ctrl)) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int neg = ctrl->neg, mix_first = ctrl->mix_first;
+  const double hsb = ctrl->hsb, k1 = ctrl->kick1, k2 = ctrl->kick2, cv = ctrl->cv, cf = ctrl->cf,
+               dtx = ctrl->dtx;
+  double4 p = pos[i];
+  double v[3] = {vel[i], vel[ncap + i], vel[2 * ncap + i]};
+  const double f[3] = {frc[i], frc[ncap + i], frc[2 * ncap + i]};
+  double x[3] = {p.x, p.y, p.z};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double vd = v[d], xd = x[d];
+    if (neg) {
+      xd -= hsb * vd;
+      vd = 0.0;
+    }
+    if (mix_first) vd = cv * vd + cf * f[d];
+    vd = vd + k1 * f[d];
+    if (!mix_first) vd = cv * vd + cf * f[d];
+    xd = xd + dtx * vd;
+    vd = vd + k2 * f[d];
+    v[d] = vd;
+    x[d] = xd;
+  }
+  pos[i] = make_double4(x[0], x[1], x[2], p.w);
+  vel[i] = v[0];
+  vel[ncap + i] = v[1];
+  vel[2 * ncap + i] = v[2];
+}
+
+// Force-pass epilogue of one atom: store F, apply the velocity-Verlet second
+// half kick, and fold E, P, |F|^2, |v|^2, max |F_i|^2, max |v_i|^2 into the
+// block's reduction record.
+__device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, double fy, double fz, double e,
+                                               double* __restrict__ frc, double* __restrict__ vel, int ncap,
+                                               double kick3, double* __restrict__ part, int rec) {
+  double r[6] = {0, 0, 0, 0, 0, 0};
+  if (valid) {
+    frc[i] = fx;
+    frc[ncap + i] = fy;
+    frc[2 * ncap + i] = fz;
+    double vx = vel[i], vy = vel[ncap + i], vz = vel[2 * ncap + i];
+    if (kick3 != 0.0) {
+      vx += kick3 * fx;
+      vy += kick3 * fy;
+      vz += kick3 * fz;
+      vel[i] = vx;
+      vel[ncap + i] = vy;
+      vel[2 * ncap + i] = vz;
+    }
+    double f2 = fx * fx + fy * fy + fz * fz, v2 = vx * vx + vy * vy + vz * vz;
+    r[0] = e;
+    r[1] = fx * vx + fy * vy + fz * vz;
+    r[2] = f2;
+    r[3] = v2;
+    r[4] = f2;
+    r[5] = v2;
+  }
+  block_reduce<4, 2>(r);
+  if (threadIdx.x == 0) {
+    double* o = part + (size_t)kRed * rec;
+    o[R_E] = r[0];
+    o[R_P] = r[1];
+    o[R_F2] = r[2];
+    o[R_V2] = r[3];
+    o[R_FMAX2] = r[4];
+    o[R_VMAX2] = r[5];
+  }
+}
+
+// ------------------------------------------------------------ pair kernels
+
+// Energy-shifted LJ.  Separations and the r^2 < rc^2 test in FP64; the pair
+// terms and per-atom accumulation in T (double, or float for the mixed path).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                     const int* __restrict__ nnbr, int n, int stride, int ncap,
+                                                     BoxDev box, PotDev pot, double* __restrict__ frc,
+                                                     double* __restrict__ vel, double* __restrict__ part,
+                                                     Ctrl* __restrict__ ctrl) {
+  if (!ctrl_running(ctrl)) return;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  T ax = 0, ay = 0, az = 0, ae = 0;
+  if (valid) {
+    const double4 pi = pos[i];
+    const int cnt = nnbr[i];
+    const T eps24 = (T)(24.0 * pot.eps), eps4 = (T)(4.0 * pot.eps), sig2 = (T)pot.sig2, sh = (T)pot.shift;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = nbr[(size_t)k * stride + i];
+      const double4 pj = pos[j];
+      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+      min_image(dx, dy, dz, box);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < pot.rc2) {
+        T ir2;
+        if constexpr (sizeof(T) == 8) ir2 = rcp_d(r2);
+        else ir2 = rcp_f((float)r2);
+        const T s2 = sig2 * ir2, s6 = s2 * s2 * s2;
+        const T fr = eps24 * s6 * ((T)2 * s6 - (T)1) * ir2;
+        ax += fr * (T)dx;
+        ay += fr * (T)dy;
+        az += fr * (T)dz;
+        ae += (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh);
+      }
+    }
+  }
+  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, ctrl->kick3, part, b);
+}
+
+// Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
+// F'(rho_i) = -xi / (2 sqrt(rho_i)) in pos[i].w and sums F(rho_i) per block.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                          const int* __restrict__ nnbr, int n, int stride,
+                                                          BoxDev box, PotDev pot, double* __restrict__ part_emb,
+                                                          const Ctrl* __restrict__ ctrl) {
+  if (!ctrl_running(ctrl)) return;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * blockDim.x + threadIdx.x;
+  double emb = 0.0;
+  if (i < n) {
+    const double4 pi = pos[i];
+    const int cnt = nnbr[i];
+    const T qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in, inv_w = (T)pot.inv_w;
+    T rho = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = nbr[(size_t)k * stride + i];
+      const double4 pj = pos[j];
+      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+      min_image(dx, dy, dz, box);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < pot.rc2) {
+        T r;
+        if constexpr (sizeof(T) == 8) r = sqrt(r2);
+        else r = sqrtf((float)r2);
+        const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
+        const T S = (1 - s) * (1 - s) * (1 + 2 * s);
+        rho += exp(-qr0 * (r - r0)) * S;
+      }
+    }
+    double fp = 0.0;
+    if (rho > 0) {
+      const double sq = sqrt((double)rho);
+      fp = -0.5 * pot.xi / sq;
+      emb = -pot.xi * sq;
+    }
+    pos[i].w = fp;
+  }
+  double r[1] = {emb};
+  block_reduce<1, 0>(r);
+  if (threadIdx.x == 0) part_emb[b] = r[0];
+}
+
+// Gupta force pass: F_i = -sum_j [c phi_t'(r) + (F'_i + F'_j) rho_t'(r)] d/r,
+// e_i = w_e sum_j phi_t(r).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                        const int* __restrict__ nnbr, int n, int stride, int ncap,
+                                                        BoxDev box, PotDev pot, double* __restrict__ frc,
+                                                        double* __restrict__ vel, double* __restrict__ part,
+                                                        Ctrl* __restrict__ ctrl) {
+  if (!ctrl_running(ctrl)) return;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  T ax = 0, ay = 0, az = 0, ae = 0;
+  if (valid) {
+    const double4 pi = pos[i];
+    const int cnt = nnbr[i];
+    const T A = (T)pot.A, pr0 = (T)pot.pr0, qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in,
+            inv_w = (T)pot.inv_w, cpair = (T)pot.cpair, epair = (T)pot.epair, fpi = (T)pi.w;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = nbr[(size_t)k * stride + i];
+      const double4 pj = pos[j];
+      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+      min_image(dx, dy, dz, box);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < pot.rc2) {
+        T ir;
+        if constexpr (sizeof(T) == 8) ir = rsqrt_d(r2);
+        else ir = rsqrt_f((float)r2);
+        const T r = (T)r2 * ir;
+        const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
+        const T S = (1 - s) * (1 - s) * (1 + 2 * s);
+        const T dS = (T)(-6) * s * (1 - s) * inv_w;
+        const T ph = A * exp(-pr0 * (r - r0));
+        const T rh = exp(-qr0 * (r - r0));
+        const T dph = ph * (dS - pr0 * S);
+        const T drh = rh * (dS - qr0 * S);
+        const T dEdr = cpair * dph + (fpi + (T)pj.w) * drh;
+        const T fr = -dEdr * ir;
+        ax += fr * (T)dx;
+        ay += fr * (T)dy;
+        az += fr * (T)dz;
+        ae += epair * ph * S;
+      }
+    }
+  }
+  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, ctrl->kick3, part, b);
+}
+
+// Quadratic test well E = 1/2 sum k_d x_d^2 (no pairs).
+__global__ __launch_bounds__(kBlock) void k_harmonic_force(const double4* __restrict__ pos, int n, int ncap,
+                                                           PotDev pot, double* __restrict__ frc,
+                                                           double* __restrict__ vel, double* __restrict__ part,
+                                                           Ctrl* __restrict__ ctrl) {
+  if (!ctrl_running(ctrl)) return;
+  const int b = blockIdx.x;
+  const int i = b * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  double fx = 0, fy = 0, fz = 0, e = 0;
+  if (valid) {
+    double4 p = pos[i];
+    fx = -pot.k[0] * p.x;
+    fy = -pot.k[1] * p.y;
+    fz = -pot.k[2] * p.z;
+    e = 0.5 * (pot.k[0] * p.x * p.x + pot.k[1] * p.y * p.y + pot.k[2] * p.z * p.z);
+  }
+  force_epilogue(i, valid, fx, fy, fz, e, frc, vel, ncap, ctrl->kick3, part, b);
+}
+
+// --------------------------------------------------------- FIRE control
+
+// Second reduction stage (fixed order) and the scalar FIRE logic, one block.
+// eval_only: record E and the force norms of a single evaluation, no FIRE step.
+__global__ __launch_bounds__(1024) void k_control(Ctrl* __restrict__ c, const double* __restrict__ part,
+                                                  const double* __restrict__ part_emb, int nrec, int eval_only,
+                                                  double* __restrict__ trace) {
+  if (c->status != ST_RUNNING) return;
+  double r[6] = {0, 0, 0, 0, 0, 0};
+  for (int q = threadIdx.x; q < nrec; q += blockDim.x) {
+    const double* o = part + (size_t)kRed * q;
+    r[0] += o[R_E] + (part_emb ? part_emb[q] : 0.0);
+    r[1] += o[R_P];
+    r[2] += o[R_F2];
+    r[3] += o[R_V2];
+    r[4] = fmax(r[4], o[R_FMAX2]);
+    r[5] = fmax(r[5], o[R_VMAX2]);
+  }
+  // block_reduce assumes kBlock threads; do the 1024-thread tree here
+  __shared__ double sm[16][6];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k = 0; k < 4; ++k) r[k] = wave_sum(r[k]);
+  for (int k = 4; k < 6; ++k) r[k] = wave_max(r[k]);
+  if (lane == 0)
+    for (int k = 0; k < 6; ++k) sm[w][k] = r[k];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+    for (int k = 0; k < 4; ++k) r[k] += sm[q][k];
+    for (int k = 4; k < 6; ++k) r[k] = fmax(r[k], sm[q][k]);
+  }
+  const double E = r[0], P = r[1], F2 = r[2], V2 = r[3], fm = sqrt(r[4]), vm = sqrt(r[5]);
+  c->energy = E;
+  c->P = P;
+  c->F2 = F2;
+  c->v2 = V2;
+  c->fmax = fm;
+  c->f2norm = sqrt(F2);
+  c->vmax = vm;
+  c->evals += 1;
+  const long long it = c->iter;
+  if (c->precision) c->iter_low += (it > 0);
+  if (c->error & ERR_OVERLAP) {
+    c->status = FIRE_E_OVERLAP;
+    return;
+  }
+  if (!isfinite(E) || !isfinite(F2) || (c->error & ERR_NONFINITE)) {
+    c->status = FIRE_E_NONFINITE;
+    return;
+  }
+  if (eval_only) return;
+  if (trace && it < c->trace_cap) {
+    double* t = trace + (size_t)FIRE_TRACE_COLS * it;
+    t[0] = (double)it;
+    t[1] = E;
+    t[2] = fm;
+    t[3] = sqrt(F2);
+    t[4] = c->P_used;
+    t[5] = c->dt;
+    t[6] = c->alpha;
+    t[7] = (double)c->branch;
+    t[8] = (double)c->npos;
+  }
+  const double crit = c->criterion == FIRE_CRIT_FMAX ? fm : sqrt(F2);
+  if (crit < c->tol) {
+    c->status = FIRE_STOP_CONVERGED;
+    return;
+  }
+  if (it >= c->max_steps) {
+    c->status = FIRE_STOP_MAX_STEPS;
+    return;
+  }
+  int pause = 0;
+  if (c->precision && c->mode == FIRE_MIXED && crit < c->switch_tol) {
+    c->precision = 0;
+    pause |= PAUSE_PRECISION;
+  }
+  // ---- start of iteration i = it + 1: the branch of Algorithm 2 (or 1)
+  const long long i = it + 1;
+  double dt = c->dt, alpha = c->alpha;
+  const double alpha_mix = alpha;  // Algorithm 1 mixes before alpha decays
+  int neg;
+  if (P > 0.0) {
+    neg = 0;
+    c->npos += 1;
+    c->nneg = 0;
+    if (c->npos > c->delaystep) {
+      dt = fmin(dt * c->dtgrow, c->dtmax);
+      alpha *= c->alphashrink;
+    }
+  } else {
+    neg = 1;
+    c->npos = 0;
+    if (c->variant == FIRE_VARIANT_FIRE2) {
+      c->nneg += 1;
+      if (c->nneg > c->vdfmax) {
+        c->status = FIRE_STOP_MAXVDOTF;
+        return;
+      }
+      if (!(c->initialdelay && i < c->delaystep)) {
+        if (dt * c->dtshrink >= c->dtmin) dt *= c->dtshrink;
+        alpha = c->alpha0;
+      }
+    } else {
+      dt *= c->dtshrink;
+      alpha = c->alpha0;
+    }
+  }
+  const double dtf = dt * c->f2a;
+  const double fn = sqrt(F2);
+  const double Pe = neg ? 0.0 : P, V2e = neg ? 0.0 : V2, vme = neg ? 0.0 : vm;
+  double k1, k2, k3, cv, cf;
+  int mix_first = 0;
+  if (c->integrator == FIRE_INT_EULER_EXPLICIT) {
+    k1 = 0.0;
+    k2 = dtf;
+    k3 = 0.0;
+  } else if (c->integrator == FIRE_INT_VERLET) {
+    k1 = 0.5 * dtf;
+    k2 = 0.0;
+    k3 = 0.5 * dtf;
+  } else {
+    k1 = dtf;
+    k2 = 0.0;
+    k3 = 0.0;
+  }
+  if (c->variant == FIRE_VARIANT_FIRE2) {
+    // |v| of the velocity being mixed, from the reductions: |v + k1 F|^2
+    const double vn = sqrt(fmax(V2e + 2.0 * k1 * Pe + k1 * k1 * F2, 0.0));
+    cv = 1.0 - alpha;
+    cf = fn > 0.0 ? alpha * vn / fn : 0.0;
+  } else {
+    mix_first = 1;
+    cv = neg ? 1.0 : 1.0 - alpha_mix;
+    cf = (neg || !(fn > 0.0)) ? 0.0 : alpha_mix * sqrt(V2) / fn;
+  }
+  const double hsb = (neg && c->variant == FIRE_VARIANT_FIRE2 && c->halfstepback) ? 0.5 * dt : 0.0;
+  // bound on any atom's displacement in this update, for the list skin
+  const double fme = fm;
+  double vb = vme;
+  if (mix_first) vb = cv * vb + cf * fme;
+  vb += k1 * fme;
+  if (!mix_first) vb = cv * vb + cf * fme;
+  const double step = hsb * vm + dt * vb;
+  if (step > c->skin_half) {
+    pause |= PAUSE_BIG_STEP;
+  } else if (c->disp + step > c->skin_half) {
+    pause |= PAUSE_REBUILD;
+    c->disp = step;
+  } else {
+    c->disp += step;
+  }
+  c->dt = dt;
+  c->alpha = alpha;
+  c->branch = neg ? -1 : 1;
+  c->P_used = P;
+  c->neg = neg;
+  c->mix_first = mix_first;
+  c->hsb = hsb;
+  c->kick1 = k1;
+  c->kick2 = k2;
+  c->kick3 = k3;
+  c->cv = cv;
+  c->cf = cf;
+  c->dtx = dt;
+  c->iter = i;
+  if (pause) {
+    c->pause = pause;
+    c->status = ST_PAUSED;
+  }
+}
+
+// ------------------------------------------------------- Hessian * u (FP64)
+
+// Gupta HVP prologue: rho_i, F'_i, F''_i and s_i = sum_j rho'(r) dh.(u_i - u_j).
+__global__ __launch_bounds__(kBlock) void k_gupta_hvp_pre(const double4* __restrict__ pos,
+                                                          const int* __restrict__ nbr, const int* __restrict__ nnbr,
+                                                          int n, int stride, int ncap, BoxDev box, PotDev pot,
+                                                          const double* __restrict__ u, double* __restrict__ aux) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 pi = pos[i];
+  const double ui[3] = {u[i], u[ncap + i], u[2 * ncap + i]};
+  double rho = 0.0, s = 0.0;
+  for (int k = 0, cnt = nnbr[i]; k < cnt; ++k) {
+    const int j = nbr[(size_t)k * stride + i];
+    const double4 pj = pos[j];
+    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    min_image(dx, dy, dz, box);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < pot.rc2) {
+      const double r = sqrt(r2), ir = 1.0 / r;
+      const double t = fmin(fmax((r - pot.r_in) * pot.inv_w, 0.0), 1.0);
+      const double S = (1 - t) * (1 - t) * (1 + 2 * t), dS = -6.0 * t * (1 - t) * pot.inv_w;
+      const double rh = exp(-pot.qr0 * (r - pot.r0));
+      rho += rh * S;
+      const double drh = rh * (dS - pot.qr0 * S);
+      const double w = (dx * (ui[0] - u[j]) + dy * (ui[1] - u[ncap + j]) + dz * (ui[2] - u[2 * ncap + j])) * ir;
+      s += drh * w;
+    }
+  }
+  double f1 = 0.0, f2 = 0.0;
+  if (rho > 0.0) {
+    const double sq = sqrt(rho);
+    f1 = -0.5 * pot.xi / sq;
+    f2 = 0.25 * pot.xi / (rho * sq);
+  }
+  aux[i] = f1;
+  aux[ncap + i] = f2;
+  aux[2 * ncap + i] = s;
+}
+
+// Hu_i = sum_j [B(g1, g2) w + (F''_i s_i + F''_j s_j) rho' dh], w = u_i - u_j,
+// with B(g1, g2) w = g2 (dh.w) dh + (g1 / r)(w - (dh.w) dh).
+__global__ __launch_bounds__(kBlock) void k_hvp(const double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                const int* __restrict__ nnbr, int n, int stride, int ncap,
+                                                BoxDev box, PotDev pot, const double* __restrict__ u,
+                                                const double* __restrict__ aux, double* __restrict__ hu) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ui[3] = {u[i], u[ncap + i], u[2 * ncap + i]};
+  if (pot.kind == FIRE_POT_HARMONIC) {
+    for (int d = 0; d < 3; ++d) hu[d * ncap + i] = pot.k[d] * ui[d];
+    return;
+  }
+  const double4 pi = pos[i];
+  double acc[3] = {0, 0, 0};
+  const bool gupta = pot.kind == FIRE_POT_GUPTA;
+  const double f1i = gupta ? aux[i] : 0.0, f2i = gupta ? aux[ncap + i] : 0.0, si = gupta ? aux[2 * ncap + i] : 0.0;
+  for (int k = 0, cnt = nnbr[i]; k < cnt; ++k) {
+    const int j = nbr[(size_t)k * stride + i];
+    const double4 pj = pos[j];
+    double d[3] = {pi.x - pj.x, pi.y - pj.y, pi.z - pj.z};
+    min_image(d[0], d[1], d[2], box);
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(r2 < pot.rc2)) continue;
+    const double r = sqrt(r2), ir = 1.0 / r;
+    const double w[3] = {ui[0] - u[j], ui[1] - u[ncap + j], ui[2] - u[2 * ncap + j]};
+    const double dw = (d[0] * w[0] + d[1] * w[1] + d[2] * w[2]) * ir;  // dh.w
+    double g1, g2, extra = 0.0;
+    if (!gupta) {
+      const double s2 = pot.sig2 / r2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+      g1 = 4.0 * pot.eps * (-12.0 * s12 + 6.0 * s6) * ir;
+      g2 = 4.0 * pot.eps * (156.0 * s12 - 42.0 * s6) / r2;
+    } else {
+      const double t = fmin(fmax((r - pot.r_in) * pot.inv_w, 0.0), 1.0);
+      const bool in_taper = t > 0.0 && t < 1.0;
+      const double S = (1 - t) * (1 - t) * (1 + 2 * t), dS = -6.0 * t * (1 - t) * pot.inv_w;
+      const double d2S = in_taper ? -6.0 * (1 - 2 * t) * pot.inv_w * pot.inv_w : 0.0;
+      const double ph = pot.A * exp(-pot.pr0 * (r - pot.r0)), rh = exp(-pot.qr0 * (r - pot.r0));
+      const double dph = ph * (dS - pot.pr0 * S), d2ph = ph * (pot.pr0 * pot.pr0 * S - 2.0 * pot.pr0 * dS + d2S);
+      const double drh = rh * (dS - pot.qr0 * S), d2rh = rh * (pot.qr0 * pot.qr0 * S - 2.0 * pot.qr0 * dS + d2S);
+      const double f1 = f1i + aux[j];
+      g1 = pot.cpair * dph + f1 * drh;
+      g2 = pot.cpair * d2ph + f1 * d2rh;
+      extra = (f2i * si + aux[ncap + j] * aux[2 * ncap + j]) * drh;
+    }
+    for (int q = 0; q < 3; ++q) {
+      const double dh = d[q] * ir;
+      acc[q] += g2 * dw * dh + g1 * ir * (w[q] - dw * dh) + extra * dh;
+    }
+  }
+  hu[i] = acc[0];
+  hu[ncap + i] = acc[1];
+  hu[2 * ncap + i] = acc[2];
+}
+
+// ------------------------------------------------ vector kernels (Lanczos)
+
+// Per-block partial dot products of two 3-plane vectors (fixed order).
+__global__ __launch_bounds__(kBlock) void k_dot(const double* __restrict__ a, const double* __restrict__ b, int n,
+                                                int ncap, double* __restrict__ part) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double r[1] = {0.0};
+  if (i < n) r[0] = a[i] * b[i] + a[ncap + i] * b[ncap + i] + a[2 * ncap + i] * b[2 * ncap + i];
+  block_reduce<1, 0>(r);
+  if (threadIdx.x == 0) part[blockIdx.x] = r[0];
+}
+
+// Sum of per-block partials into out[slot] (one block, fixed order).
+__global__ __launch_bounds__(kBlock) void k_sum_parts(const double* __restrict__ part, int m, double* __restrict__ out) {
+  double r[1] = {0.0};
+  for (int q = threadIdx.x; q < m; q += blockDim.x) r[0] += part[q];
+  block_reduce<1, 0>(r);
+  if (threadIdx.x == 0) *out = r[0];
+}
+
+// y = a * y + b * x (3 planes), coefficients read from device scalars
+// (ca, cb may be NULL -> 1) times host factors.
+__global__ __launch_bounds__(kBlock) void k_axpby(double* __restrict__ y, const double* __restrict__ x, int n,
+                                                  int ncap, double fa, double fb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int d = 0; d < 3; ++d) y[d * ncap + i] = fa * y[d * ncap + i] + fb * x[d * ncap + i];
+}
+
+// Per-block partial sums of each plane (for removing the mean translation).
+__global__ __launch_bounds__(kBlock) void k_plane_sums(const double* __restrict__ a, int n, int ncap,
+                                                       double* __restrict__ part) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double r[3] = {0, 0, 0};
+  if (i < n) {
+    r[0] = a[i];
+    r[1] = a[ncap + i];
+    r[2] = a[2 * ncap + i];
+  }
+  block_reduce<3, 0>(r);
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 3; ++d) part[3 * blockIdx.x + d] = r[d];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sub_plane(double* __restrict__ a, int n, int ncap, double mx, double my,
+                                                      double mz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  a[i] -= mx;
+  a[ncap + i] -= my;
+  a[2 * ncap + i] -= mz;
+}
+
+}  // namespace fire
+
+// =================================================================== host
+
+using namespace fire;
+
+namespace {
+
+const char* hip_err_str(hipError_t e) { return hipGetErrorString(e); }
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+inline int nblocks(long long n, int b = kBlock) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+struct fire_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;      // default work stream
+  hipStream_t cap_stream = nullptr;  // graph capture stream
+  fire_params params{};
+  std::string err;
+
+  // ---- single-system workspace
+  int n = 0, ncap = 0;
+  double4 *pos = nullptr, *pos2 = nullptr;
+  double *vel = nullptr, *vel2 = nullptr, *frc = nullptr, *frc2 = nullptr;
+  int *id = nullptr, *id2 = nullptr, *cell_of = nullptr, *order = nullptr;
+  double* stage = nullptr;  // AoS staging [ncap][3]
+  int ccap = 0;
+  int *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr;
+  int kcap = 0;
+  int *nbr = nullptr, *nnbr = nullptr;
+  double *part = nullptr, *part_emb = nullptr, *bbox_part = nullptr;
+  double* aux = nullptr;  // HVP / Lanczos planes
+  int aux_planes = 0;
+  Ctrl* ctrl = nullptr;
+  int* flags = nullptr;       // device: [0] error bits, [1] max neighbour count
+  int* h_flags = nullptr;     // pinned
+  Ctrl* h_ctrl = nullptr;     // pinned
+  int* h_status = nullptr;    // pinned, 2 slots x 8 ints
+  double* h_zero = nullptr;   // pinned scalar for small uploads
+  double* trace = nullptr;
+  long long trace_cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+
+  // current system description
+  BoxDev box{};
+  PotDev pot{};
+  Grid grid{};
+  double rcs = 0.0, skin = 0.0;
+  bool have_list = false;
+
+  // captured iteration graphs: [precision]
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int graph_k = 0;
+  long long graph_key[2] = {-1, -1};
+  long long layout_version = 0;
+
+  // batched workspace is owned by batched.hip
+  void* batched = nullptr;
+};
+
+extern "C" void fire_batched_release(void* ws);
+extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
+                                const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
+                                double tol, long long max_steps, fire_result* out);
+
+namespace {
+
+int set_err(fire_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return set_err(ctx, e_ == hipErrorOutOfMemory ? FIRE_E_OOM : FIRE_E_DEVICE,                 \
+                     std::string(#call) + ": " + hip_err_str(e_));                                 \
+  } while (0)
+
+void free_single(fire_ctx* c) {
+  hipFree(c->pos); hipFree(c->pos2); hipFree(c->vel); hipFree(c->vel2); hipFree(c->frc); hipFree(c->frc2);
+  hipFree(c->id); hipFree(c->id2); hipFree(c->cell_of); hipFree(c->order); hipFree(c->stage);
+  hipFree(c->part); hipFree(c->part_emb); hipFree(c->bbox_part);
+  c->pos = c->pos2 = nullptr;
+  c->vel = c->vel2 = c->frc = c->frc2 = nullptr;
+  c->id = c->id2 = c->cell_of = c->order = nullptr;
+  c->stage = c->part = c->part_emb = c->bbox_part = nullptr;
+  c->ncap = 0;
+}
+
+void drop_graphs(fire_ctx* c) {
+  for (int p = 0; p < 2; ++p) {
+    if (c->gexec[p]) hipGraphExecDestroy(c->gexec[p]);
+    c->gexec[p] = nullptr;
+    c->graph_key[p] = -1;
+  }
+}
+
+int ensure_atoms(fire_ctx* ctx, int n) {
+  if (n <= ctx->ncap) return FIRE_OK;
+  drop_graphs(ctx);
+  free_single(ctx);
+  int cap = std::max(n, 64);
+  int nb = nblocks(cap);
+  HIPCHK(dalloc(&ctx->pos, cap));
+  HIPCHK(dalloc(&ctx->pos2, cap));
+  HIPCHK(dalloc(&ctx->vel, 3 * (size_t)cap));
+  HIPCHK(dalloc(&ctx->vel2, 3 * (size_t)cap));
+  HIPCHK(dalloc(&ctx->frc, 3 * (size_t)cap));
+  HIPCHK(dalloc(&ctx->frc2, 3 * (size_t)cap));
+  HIPCHK(dalloc(&ctx->id, cap));
+  HIPCHK(dalloc(&ctx->id2, cap));
+  HIPCHK(dalloc(&ctx->cell_of, cap));
+  HIPCHK(dalloc(&ctx->order, cap));
+  HIPCHK(dalloc(&ctx->stage, 3 * (size_t)cap));
+  HIPCHK(dalloc(&ctx->part, (size_t)kRed * nb));
+  HIPCHK(dalloc(&ctx->part_emb, nb));
+  HIPCHK(dalloc(&ctx->bbox_part, 6 * (size_t)nb));
+  ctx->ncap = cap;
+  ctx->layout_version++;
+  if (ctx->kcap) {  // neighbour list is sized by ncap
+    hipFree(ctx->nbr);
+    hipFree(ctx->nnbr);
+    ctx->nbr = nullptr;
+    ctx->nnbr = nullptr;
+    ctx->kcap = 0;
+  }
+  if (ctx->aux_planes) {
+    hipFree(ctx->aux);
+    ctx->aux = nullptr;
+    ctx->aux_planes = 0;
+  }
+  return FIRE_OK;
+}
+
+int ensure_aux(fire_ctx* ctx, int planes) {
+  if (planes <= ctx->aux_planes) return FIRE_OK;
+  hipFree(ctx->aux);
+  ctx->aux = nullptr;
+  HIPCHK(dalloc(&ctx->aux, (size_t)planes * ctx->ncap));
+  ctx->aux_planes = planes;
+  return FIRE_OK;
+}
+
+int prepare_system(fire_ctx* ctx, const fire_box* b, const fire_potential* p) {
+  if (!b || !p) return set_err(ctx, FIRE_E_ARG, "box and potential are required");
+  if (p->kind != FIRE_POT_LJ && p->kind != FIRE_POT_GUPTA && p->kind != FIRE_POT_HARMONIC)
+    return set_err(ctx, FIRE_E_ARG, "unknown potential kind");
+  PotDev& d = ctx->pot;
+  d = PotDev{};
+  d.kind = p->kind;
+  d.conv = p->convention;
+  if (p->kind == FIRE_POT_LJ) {
+    if (!(p->rc > 0) || !(p->sigma > 0)) return set_err(ctx, FIRE_E_ARG, "LJ needs rc > 0 and sigma > 0");
+    d.rc = p->rc;
+    d.eps = p->eps;
+    d.sig2 = p->sigma * p->sigma;
+    double s6 = std::pow(p->sigma / p->rc, 6.0);
+    d.shift = 4.0 * p->eps * (s6 * s6 - s6);
+  } else if (p->kind == FIRE_POT_GUPTA) {
+    if (!(p->r_out > p->r_in) || !(p->r0 > 0))
+      return set_err(ctx, FIRE_E_ARG, "Gupta needs r_out > r_in and r0 > 0");
+    if (p->convention != FIRE_GUPTA_RGL && p->convention != FIRE_GUPTA_HALF)
+      return set_err(ctx, FIRE_E_ARG, "unknown Gupta convention");
+    d.rc = p->r_out;
+    d.A = p->A;
+    d.pr0 = p->p / p->r0;
+    d.qr0 = 2.0 * p->q / p->r0;
+    d.xi = p->xi;
+    d.r0 = p->r0;
+    d.r_in = p->r_in;
+    d.inv_w = 1.0 / (p->r_out - p->r_in);
+    d.cpair = p->convention == FIRE_GUPTA_RGL ? 2.0 : 1.0;
+    d.epair = p->convention == FIRE_GUPTA_RGL ? 1.0 : 0.5;
+  } else {
+    for (int k = 0; k < 3; ++k) d.k[k] = p->k[k];
+  }
+  d.rc2 = d.rc * d.rc;
+  BoxDev& bx = ctx->box;
+  double skin = ctx->params.skin > 0 ? ctx->params.skin : 0.12 * d.rc;
+  for (int k = 0; k < 3; ++k) {
+    bx.per[k] = b->periodic[k] ? 1 : 0;
+    bx.lo[k] = b->lo[k];
+    bx.L[k] = b->len[k];
+    bx.invL[k] = b->len[k] > 0 ? 1.0 / b->len[k] : 0.0;
+    if (bx.per[k]) {
+      if (!(b->len[k] > 0) || !std::isfinite(b->len[k])) return set_err(ctx, FIRE_E_BOX, "periodic length must be > 0");
+      if (p->kind != FIRE_POT_HARMONIC) {
+        if (!(d.rc < 0.5 * b->len[k]))
+          return set_err(ctx, FIRE_E_BOX, "cutoff must be < len/2 on periodic axes (minimum image)");
+        skin = std::min(skin, 0.9 * (0.5 * b->len[k] - d.rc));
+      }
+    }
+  }
+  if (p->kind == FIRE_POT_HARMONIC) skin = 0.0;
+  ctx->skin = skin;
+  ctx->rcs = d.rc + skin;
+  return FIRE_OK;
+}
+
+// Cell grid from the box (periodic axes) or the current bounding box (free axes).
+int make_grid(fire_ctx* ctx, int n) {
+  Grid& g = ctx->grid;
+  double bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
+  bool any_free = !(ctx->box.per[0] && ctx->box.per[1] && ctx->box.per[2]);
+  if (any_free) {
+    int nb = nblocks(n);
+    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->pos, n, ctx->bbox_part);
+    std::vector<double> h(6 * (size_t)nb);
+    HIPCHK(hipMemcpyAsync(h.data(), ctx->bbox_part, h.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 3; ++k) {
+      bmin[k] = INFINITY;
+      bmax[k] = -INFINITY;
+    }
+    for (int q = 0; q < nb; ++q)
+      for (int k = 0; k < 3; ++k) {
+        bmin[k] = std::min(bmin[k], h[6 * q + k]);
+        bmax[k] = std::max(bmax[k], h[6 * q + 3 + k]);
+      }
+  }
+  const double rcs = ctx->rcs;
+  long long ncell = 1;
+  for (int k = 0; k < 3; ++k) {
+    double lo, ext;
+    if (ctx->box.per[k]) {
+      lo = ctx->box.lo[k];
+      ext = ctx->box.L[k];
+    } else {
+      lo = bmin[k];
+      ext = bmax[k] - bmin[k];
+    }
+    int nc = rcs > 0 ? (int)std::floor(ext / rcs) : 1;
+    nc = std::max(1, std::min(nc, 1024));
+    g.n[k] = nc;
+    g.lo[k] = lo;
+    g.inv[k] = ext > 0 ? nc / ext : 0.0;
+    if (ctx->box.per[k]) {
+      g.lo_off[k] = nc >= 3 ? -1 : 0;
+      g.hi_off[k] = nc >= 2 ? 1 : 0;
+    } else {
+      g.lo_off[k] = -1;
+      g.hi_off[k] = 1;
+    }
+    ncell *= nc;
+  }
+  if (ncell > (1LL << 26)) return set_err(ctx, FIRE_E_ARG, "cell grid too large");
+  g.ncell = (int)ncell;
+  if (g.ncell + 1 > ctx->ccap) {
+    hipFree(ctx->cell_count);
+    hipFree(ctx->cell_start);
+    hipFree(ctx->cell_cursor);
+    int cap = g.ncell + 1;
+    HIPCHK(dalloc(&ctx->cell_count, cap));
+    HIPCHK(dalloc(&ctx->cell_start, cap));
+    HIPCHK(dalloc(&ctx->cell_cursor, cap));
+    ctx->ccap = cap;
+  }
+  return FIRE_OK;
+}
+
+int read_flags(fire_ctx* ctx) {
+  HIPCHK(hipMemcpyAsync(ctx->h_flags, ctx->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FIRE_OK;
+}
+
+// Sort atoms by cell and build the neighbour list of the current positions.
+int rebuild(fire_ctx* ctx) {
+  const int n = ctx->n;
+  if (ctx->pot.kind == FIRE_POT_HARMONIC) {  // no pairs, no list
+    ctx->have_list = true;
+    return FIRE_OK;
+  }
+  int rc = make_grid(ctx, n);
+  if (rc) return rc;
+  const Grid& g = ctx->grid;
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipMemsetAsync(ctx->cell_count, 0, sizeof(int) * (g.ncell + 1), s));
+  HIPCHK(hipMemsetAsync(ctx->cell_cursor, 0, sizeof(int) * (g.ncell + 1), s));
+  HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
+  const int nb = nblocks(n);
+  hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g, ctx->cell_of,
+                     ctx->cell_count);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctx->cell_count, g.ncell, ctx->cell_start);
+  hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(kBlock), 0, s, ctx->cell_of, n, ctx->cell_start,
+                     ctx->cell_cursor, ctx->order);
+  hipLaunchKernelGGL(k_cell_sort, dim3(nblocks(g.ncell)), dim3(kBlock), 0, s, ctx->cell_start, g.ncell, ctx->id,
+                     ctx->order);
+  hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, s, ctx->order, n, ctx->ncap, ctx->pos, ctx->vel,
+                     ctx->frc, ctx->id, ctx->pos2, ctx->vel2, ctx->frc2, ctx->id2);
+  HIPCHK(hipMemcpyAsync(ctx->pos, ctx->pos2, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->id, ctx->id2, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+  for (int d = 0; d < 3; ++d) {
+    HIPCHK(hipMemcpyAsync(ctx->vel + (size_t)d * ctx->ncap, ctx->vel2 + (size_t)d * ctx->ncap, sizeof(double) * n,
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->frc + (size_t)d * ctx->ncap, ctx->frc2 + (size_t)d * ctx->ncap, sizeof(double) * n,
+                          hipMemcpyDeviceToDevice, s));
+  }
+  if (!ctx->nnbr) HIPCHK(dalloc(&ctx->nnbr, ctx->ncap));
+  const double rcs2 = ctx->rcs * ctx->rcs;
+  hipLaunchKernelGGL(k_nbr<false>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g, ctx->cell_start, rcs2,
+                     ctx->ncap, 0, ctx->nnbr, (int*)nullptr, ctx->flags + 1, ctx->flags);
+  rc = read_flags(ctx);
+  if (rc) return rc;
+  if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
+  const int kmax = ctx->h_flags[1];
+  if (kmax > ctx->kcap || !ctx->nbr) {
+    hipFree(ctx->nbr);
+    ctx->nbr = nullptr;
+    int kc = std::max(kmax + kmax / 8 + 4, 8);
+    HIPCHK(dalloc(&ctx->nbr, (size_t)kc * ctx->ncap));
+    ctx->kcap = kc;
+    ctx->layout_version++;
+  }
+  hipLaunchKernelGGL(k_nbr<true>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g, ctx->cell_start, rcs2,
+                     ctx->ncap, ctx->kcap, ctx->nnbr, ctx->nbr, ctx->flags + 1, ctx->flags);
+  ctx->have_list = true;
+  return FIRE_OK;
+}
+
+// One force evaluation (with reductions) enqueued on stream s.  prec: 0 FP64, 1 FP32.
+void launch_forces(fire_ctx* ctx, hipStream_t s, int prec) {
+  const int n = ctx->n, nb = nblocks(n);
+  const PotDev& P = ctx->pot;
+  if (P.kind == FIRE_POT_LJ) {
+    if (prec)
+      hipLaunchKernelGGL(k_lj_force<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
+                         ctx->ncap, ctx->ncap, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl);
+    else
+      hipLaunchKernelGGL(k_lj_force<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
+                         ctx->ncap, ctx->ncap, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl);
+  } else if (P.kind == FIRE_POT_GUPTA) {
+    if (prec) {
+      hipLaunchKernelGGL(k_gupta_density<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
+                         ctx->ncap, ctx->box, P, ctx->part_emb, ctx->ctrl);
+      hipLaunchKernelGGL(k_gupta_force<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
+                         ctx->ncap, ctx->ncap, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl);
+    } else {
+      hipLaunchKernelGGL(k_gupta_density<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
+                         ctx->ncap, ctx->box, P, ctx->part_emb, ctx->ctrl);
+      hipLaunchKernelGGL(k_gupta_force<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
+                         ctx->ncap, ctx->ncap, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl);
+    }
+  } else {
+    hipLaunchKernelGGL(k_harmonic_force, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->ncap, P, ctx->frc,
+                       ctx->vel, ctx->part, ctx->ctrl);
+  }
+}
+
+void launch_control(fire_ctx* ctx, hipStream_t s, int eval_only) {
+  const int nb = nblocks(ctx->n);
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(1024), 0, s, ctx->ctrl, ctx->part,
+                     ctx->pot.kind == FIRE_POT_GUPTA ? ctx->part_emb : (const double*)nullptr, nb, eval_only,
+                     ctx->trace);
+}
+
+void launch_update(fire_ctx* ctx, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->vel, ctx->frc, ctx->n,
+                     ctx->ncap, ctx->ctrl);
+}
+
+void launch_iteration(fire_ctx* ctx, hipStream_t s, int prec) {
+  launch_update(ctx, s);
+  launch_forces(ctx, s, prec);
+  launch_control(ctx, s, 0);
+}
+
+int graph_for(fire_ctx* ctx, int prec, hipGraphExec_t* out) {
+  const long long key = ctx->layout_version * 1000003LL + (long long)ctx->n * 7 + ctx->graph_k;
+  if (ctx->gexec[prec] && ctx->graph_key[prec] == key && ctx->trace == nullptr) {
+    *out = ctx->gexec[prec];
+    return FIRE_OK;
+  }
+  if (ctx->gexec[prec]) hipGraphExecDestroy(ctx->gexec[prec]);
+  ctx->gexec[prec] = nullptr;
+  hipGraph_t g;
+  HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+  for (int k = 0; k < ctx->graph_k; ++k) launch_iteration(ctx, ctx->cap_stream, prec);
+  HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
+  hipError_t e = hipGraphInstantiate(&ctx->gexec[prec], g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return set_err(ctx, FIRE_E_DEVICE, std::string("hipGraphInstantiate: ") + hip_err_str(e));
+  ctx->graph_key[prec] = ctx->trace ? -1 : key;
+  *out = ctx->gexec[prec];
+  return FIRE_OK;
+}
+
+int stage_in(fire_ctx* ctx, long long n, const double* src, bool host, hipStream_t s) {
+  if (n <= 0 || n > (1LL << 30)) return set_err(ctx, FIRE_E_ARG, "n must be in 1 .. 2^30");
+  if (!src) return set_err(ctx, FIRE_E_ARG, "positions are NULL");
+  int rc = ensure_atoms(ctx, (int)n);
+  if (rc) return rc;
+  ctx->n = (int)n;
+  const double* d = src;
+  if (host) {
+    for (long long i = 0; i < 3 * n; ++i)
+      if (!std::isfinite(src[i])) return set_err(ctx, FIRE_E_NONFINITE, "non-finite input position");
+    HIPCHK(hipMemcpyAsync(ctx->stage, src, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    d = ctx->stage;
+  }
+  HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
+  hipLaunchKernelGGL(k_stage_in, dim3(nblocks(n)), dim3(kBlock), 0, s, d, (int)n, ctx->ncap, ctx->pos, ctx->vel,
+                     ctx->frc, ctx->id, ctx->flags);
+  if (!host) {
+    rc = read_flags(ctx);
+    if (rc) return rc;
+    if (ctx->h_flags[0] & ERR_NONFINITE) return set_err(ctx, FIRE_E_NONFINITE, "non-finite input position");
+  }
+  return FIRE_OK;
+}
+
+void ctrl_defaults(fire_ctx* ctx, Ctrl& c, double tol, long long max_steps) {
+  const fire_params& p = ctx->params;
+  memset(&c, 0, sizeof(c));
+  c.status = ST_RUNNING;
+  c.precision = p.precision == FIRE_FP64 ? 0 : 1;
+  c.dt_start = p.dt_start;
+  c.dtmax = p.tmax * p.dt_start;
+  c.dtmin = p.tmin * p.dt_start;
+  c.dtgrow = p.dtgrow;
+  c.dtshrink = p.dtshrink;
+  c.alpha0 = p.alpha0;
+  c.alphashrink = p.alphashrink;
+  c.f2a = p.f2a;
+  c.tol = tol;
+  c.switch_tol = p.mixed_switch > 0 ? p.mixed_switch : 100.0 * tol;
+  c.skin_half = ctx->pot.kind == FIRE_POT_HARMONIC ? 1e300 : 0.5 * ctx->skin;
+  c.max_steps = max_steps;
+  c.delaystep = p.delaystep;
+  c.vdfmax = p.vdfmax;
+  c.halfstepback = p.halfstepback;
+  c.initialdelay = p.initialdelay;
+  c.integrator = p.integrator;
+  c.criterion = p.criterion;
+  c.variant = p.variant;
+  c.mode = p.precision;
+  c.natoms = ctx->n;
+  c.dt = p.dt_start;
+  c.alpha = p.alpha0;
+  c.trace_cap = ctx->trace_cap;
+}
+
+int check_status_error(fire_ctx* ctx, int st) {
+  if (st == FIRE_E_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
+  if (st == FIRE_E_NONFINITE) return set_err(ctx, FIRE_E_NONFINITE, "non-finite energy or force");
+  if (st < 0) return set_err(ctx, st, "device error");
+  return FIRE_OK;
+}
+
+// Evaluate E and F at the staged positions (list rebuilt); precision per params.
+int evaluate(fire_ctx* ctx, hipStream_t s) {
+  int rc = rebuild(ctx);
+  if (rc) return rc;
+  ctrl_defaults(ctx, *ctx->h_ctrl, 0.0, 0);
+  HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  launch_forces(ctx, s, ctx->params.precision == FIRE_FP64 ? 0 : 1);
+  launch_control(ctx, s, 1);
+  return FIRE_OK;
+}
+
+int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps, fire_result* out) {
+  if (max_steps < 0) return set_err(ctx, FIRE_E_ARG, "max_steps must be >= 0");
+  int rc = rebuild(ctx);
+  if (rc) return rc;
+  long long rebuilds = 1;
+  ctrl_defaults(ctx, *ctx->h_ctrl, tol, max_steps);
+  int prec = ctx->h_ctrl->precision;
+  HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  launch_forces(ctx, s, prec);
+  launch_control(ctx, s, 0);
+  // graph size: short for small systems (launch-bound), longer for large ones
+  ctx->graph_k = ctx->n < 20000 ? 32 : 16;
+  int* st = ctx->h_status;
+  const int poll_bytes = 32;
+  for (;;) {
+    // pipeline: two replays in flight, poll the older one
+    hipGraphExec_t g;
+    rc = graph_for(ctx, prec, &g);
+    if (rc) return rc;
+    HIPCHK(hipGraphLaunch(g, s));
+    HIPCHK(hipMemcpyAsync(st, ctx->ctrl, poll_bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(ctx->ev[0], s));
+    int cur = 0;
+    for (;;) {
+      HIPCHK(hipGraphLaunch(g, s));
+      HIPCHK(hipMemcpyAsync(st + 8 * (cur ^ 1), ctx->ctrl, poll_bytes, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(ctx->ev[cur ^ 1], s));
+      HIPCHK(hipEventSynchronize(ctx->ev[cur]));
+      if (st[8 * cur] != ST_RUNNING) break;
+      cur ^= 1;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const int status = st[8 * (cur ^ 1)];
+    const int pause = st[8 * (cur ^ 1) + 1];
+    if (status != ST_PAUSED) break;
+    // ---- host work at a pause point (before the next update); small
+    // uploads go through pinned memory and are waited for
+    int* up = ctx->h_flags + 2;
+    up[0] = ST_RUNNING;
+    up[1] = 0;
+    if (pause & PAUSE_PRECISION) prec = 0;
+    if (pause & PAUSE_BIG_STEP) {
+      HIPCHK(hipMemcpyAsync(ctx->ctrl, up, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+      launch_update(ctx, s);
+      rc = rebuild(ctx);
+      if (rc) return rc;
+      ++rebuilds;
+      double* zero = ctx->h_zero;
+      *zero = 0.0;
+      HIPCHK(hipMemcpyAsync(&ctx->ctrl->disp, zero, sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+      launch_forces(ctx, s, prec);
+      launch_control(ctx, s, 0);
+    } else {
+      if (pause & PAUSE_REBUILD) {
+        rc = rebuild(ctx);
+        if (rc) return rc;
+        ++rebuilds;
+      }
+      HIPCHK(hipMemcpyAsync(ctx->ctrl, up, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  }
+  HIPCHK(hipMemcpyAsync(ctx->h_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const Ctrl& h = *ctx->h_ctrl;
+  rc = check_status_error(ctx, h.status);
+  if (rc) return rc;
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    out->stop_reason = h.status;
+    out->precision_switched = (ctx->params.precision == FIRE_MIXED && h.precision == 0) ? 1 : 0;
+    out->iterations = h.iter;
+    out->force_evals = h.evals;
+    out->iterations_low = h.iter_low;
+    out->rebuilds = rebuilds;
+    out->energy = h.energy;
+    out->energy_per_atom = h.energy / ctx->n;
+    out->fmax = h.fmax;
+    out->f2norm = h.f2norm;
+    out->dt = h.dt;
+    out->alpha = h.alpha;
+  }
+  return FIRE_OK;
+}
+
+int check_ctx(fire_ctx* ctx) {
+  if (!ctx) return FIRE_E_ARG;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return set_err(ctx, FIRE_E_DEVICE, std::string("hipSetDevice: ") + hip_err_str(e));
+  return FIRE_OK;
+}
+
+hipStream_t pick_stream(fire_ctx* ctx, void* stream) { return stream ? (hipStream_t)stream : ctx->stream; }
+
+int validate_params(const fire_params* p) {
+  if (!(p->dt_start > 0) || !(p->tmax > 0) || !(p->tmin >= 0) || !(p->dtgrow >= 1) || !(p->dtshrink > 0) ||
+      !(p->dtshrink <= 1) || !(p->alpha0 >= 0) || !(p->alpha0 <= 1) || !(p->alphashrink > 0) ||
+      !(p->alphashrink <= 1) || !(p->f2a > 0) || p->delaystep < 0 || p->vdfmax < 0)
+    return FIRE_E_ARG;
+  if (p->integrator < 0 || p->integrator > 2 || p->criterion < 0 || p->criterion > 1 || p->variant < 0 ||
+      p->variant > 1 || p->precision < 0 || p->precision > 2)
+    return FIRE_E_ARG;
+  return FIRE_OK;
+}
+
+// ---- Lanczos helpers (vectors are 3 planes of ncap doubles in sorted order)
+
+int dev_dot(fire_ctx* ctx, hipStream_t s, const double* a, const double* b, double* out_host) {
+  const int n = ctx->n, nb = nblocks(n);
+  hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kBlock), 0, s, a, b, n, ctx->ncap, ctx->part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kBlock), 0, s, ctx->part, nb, ctx->part_emb);
+  HIPCHK(hipMemcpyAsync(out_host, ctx->part_emb, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return FIRE_OK;
+}
+
+int dev_remove_mean(fire_ctx* ctx, hipStream_t s, double* a) {
+  const int n = ctx->n, nb = nblocks(n);
+  hipLaunchKernelGGL(k_plane_sums, dim3(nb), dim3(kBlock), 0, s, a, n, ctx->ncap, ctx->bbox_part);
+  std::vector<double> h(3 * (size_t)nb);
+  HIPCHK(hipMemcpyAsync(h.data(), ctx->bbox_part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double m[3] = {0, 0, 0};
+  for (int q = 0; q < nb; ++q)
+    for (int d = 0; d < 3; ++d) m[d] += h[3 * q + d];
+  hipLaunchKernelGGL(k_sub_plane, dim3(nb), dim3(kBlock), 0, s, a, n, ctx->ncap, m[0] / n, m[1] / n, m[2] / n);
+  return FIRE_OK;
+}
+
+// hu = H u for sorted-order planes u (list and positions current).
+void launch_hvp(fire_ctx* ctx, hipStream_t s, const double* u, double* hu, double* pre) {
+  const int n = ctx->n, nb = nblocks(n);
+  if (ctx->pot.kind == FIRE_POT_GUPTA)
+    hipLaunchKernelGGL(k_gupta_hvp_pre, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n, ctx->ncap,
+                       ctx->ncap, ctx->box, ctx->pot, u, pre);
+  hipLaunchKernelGGL(k_hvp, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n, ctx->ncap, ctx->ncap,
+                     ctx->box, ctx->pot, u, (const double*)pre, hu);
+}
+
+// Smallest eigenvalue of the symmetric tridiagonal matrix (a diagonal, b off-diagonal) by Sturm bisection.
+double tridiag_min_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int k = (int)a.size();
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < k; ++i) {
+    double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < k - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < k; ++i) {
+      double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+      q = a[i] - x - (i > 0 ? bb / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+void fire_params_default(fire_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->dt_start = 1.0;
+  p->tmax = 10.0;
+  p->tmin = 0.02;
+  p->dtgrow = 1.1;
+  p->dtshrink = 0.5;
+  p->alpha0 = 0.25;
+  p->alphashrink = 0.99;
+  p->f2a = 1.0;
+  p->delaystep = 20;
+  p->vdfmax = 2000;
+  p->halfstepback = 1;
+  p->initialdelay = 1;
+  p->integrator = FIRE_INT_EULER_IMPLICIT;
+  p->criterion = FIRE_CRIT_FMAX;
+  p->variant = FIRE_VARIANT_FIRE2;
+  p->precision = FIRE_FP64;
+  p->mixed_switch = 0.0;
+  p->skin = 0.0;
+}
+
+const char* fire_stop_name(int r) {
+  switch (r) {
+    case FIRE_STOP_CONVERGED: return "converged";
+    case FIRE_STOP_MAX_STEPS: return "max_steps";
+    case FIRE_STOP_MAXVDOTF: return "maxvdotf";
+    default: return "unknown";
+  }
+}
+
+const char* fire_last_error(const fire_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int fire_init(fire_ctx** out, int device, const fire_params* params) {
+  if (!out) return FIRE_E_ARG;
+  *out = nullptr;
+  if (params && validate_params(params)) return FIRE_E_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FIRE_E_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FIRE_E_DEVICE;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FIRE_E_DEVICE;
+  fire_ctx* ctx = new fire_ctx();
+  ctx->device = device;
+  if (params) ctx->params = *params;
+  else fire_params_default(&ctx->params);
+  int rc = FIRE_OK;
+  auto init = [&]() -> int {
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipMalloc((void**)&ctx->ctrl, sizeof(Ctrl)));
+    HIPCHK(hipMalloc((void**)&ctx->flags, 4 * sizeof(int)));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_flags, 4 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_status, 16 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_zero, sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming));
+    return FIRE_OK;
+  };
+  rc = init();
+  if (rc) {
+    fire_finalize(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return FIRE_OK;
+}
+
+void fire_finalize(fire_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  drop_graphs(ctx);
+  free_single(ctx);
+  hipFree(ctx->nbr);
+  hipFree(ctx->nnbr);
+  hipFree(ctx->cell_count);
+  hipFree(ctx->cell_start);
+  hipFree(ctx->cell_cursor);
+  hipFree(ctx->aux);
+  hipFree(ctx->ctrl);
+  hipFree(ctx->flags);
+  hipFree(ctx->trace);
+  if (ctx->h_flags) hipHostFree(ctx->h_flags);
+  if (ctx->h_ctrl) hipHostFree(ctx->h_ctrl);
+  if (ctx->h_status) hipHostFree(ctx->h_status);
+  if (ctx->h_zero) hipHostFree(ctx->h_zero);
+  for (int k = 0; k < 2; ++k)
+    if (ctx->ev[k]) hipEventDestroy(ctx->ev[k]);
+  fire_batched_release(ctx->batched);
+  if (ctx->stream) hipStreamDestroy(ctx->stream);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  delete ctx;
+}
+
+int fire_set_params(fire_ctx* ctx, const fire_params* p) {
+  if (!ctx || !p) return FIRE_E_ARG;
+  if (validate_params(p)) return set_err(ctx, FIRE_E_ARG, "invalid FIRE parameters");
+  ctx->params = *p;
+  return FIRE_OK;
+}
+
+int fire_get_params(const fire_ctx* ctx, fire_params* p) {
+  if (!ctx || !p) return FIRE_E_ARG;
+  *p = ctx->params;
+  return FIRE_OK;
+}
+
+static int energy_forces_common(fire_ctx* ctx, long long n, const double* pos, bool host, const fire_box* box,
+                                const fire_potential* pot, double* energy, double* forces, hipStream_t s) {
+  int rc = prepare_system(ctx, box, pot);
+  if (rc) return rc;
+  hipStream_t saved = ctx->stream;
+  ctx->stream = s;
+  rc = stage_in(ctx, n, pos, host, s);
+  if (!rc) rc = evaluate(ctx, s);
+  ctx->stream = saved;
+  if (rc) return rc;
+  if (host) {
+    HIPCHK(hipMemcpyAsync(ctx->h_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    if (forces) {
+      hipLaunchKernelGGL(k_scatter_vec, dim3(nblocks(n)), dim3(kBlock), 0, s, ctx->frc, (int)n, ctx->ncap, ctx->id,
+                         ctx->stage);
+      HIPCHK(hipMemcpyAsync(forces, ctx->stage, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    rc = check_status_error(ctx, ctx->h_ctrl->status);
+    if (rc) return rc;
+    if (energy) *energy = ctx->h_ctrl->energy;
+  } else {
+    if (forces)
+      hipLaunchKernelGGL(k_scatter_vec, dim3(nblocks(n)), dim3(kBlock), 0, s, ctx->frc, (int)n, ctx->ncap, ctx->id,
+                         forces);
+    if (energy) HIPCHK(hipMemcpyAsync(energy, &ctx->ctrl->energy, sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return FIRE_OK;
+}
+
+int fire_energy_forces(fire_ctx* ctx, long long n, const double* pos, const fire_box* box, const fire_potential* pot,
+                       double* energy, double* forces) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return energy_forces_common(ctx, n, pos, true, box, pot, energy, forces, ctx->stream);
+}
+
+int fire_energy_forces_dev(fire_ctx* ctx, long long n, const double* d_pos, const fire_box* box,
+                           const fire_potential* pot, double* d_energy, double* d_forces, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return energy_forces_common(ctx, n, d_pos, false, box, pot, d_energy, d_forces, pick_stream(ctx, stream));
+}
+
+static int minimize_common(fire_ctx* ctx, long long n, double* pos, bool host, const fire_box* box,
+                           const fire_potential* pot, double tol, long long max_steps, fire_result* out,
+                           double* trace_host, hipStream_t s) {
+  if (!(tol >= 0)) return set_err(ctx, FIRE_E_ARG, "tol must be >= 0");
+  int rc = prepare_system(ctx, box, pot);
+  if (rc) return rc;
+  hipStream_t saved = ctx->stream;
+  ctx->stream = s;
+  rc = stage_in(ctx, n, pos, host, s);
+  if (!rc && trace_host) {
+    hipFree(ctx->trace);
+    ctx->trace = nullptr;
+    ctx->trace_cap = max_steps + 1;
+    hipError_t e = dalloc(&ctx->trace, (size_t)FIRE_TRACE_COLS * (max_steps + 1));
+    if (e != hipSuccess) rc = set_err(ctx, FIRE_E_OOM, "trace allocation");
+  }
+  if (!rc) rc = minimize_impl(ctx, s, tol, max_steps, out);
+  if (!rc) {
+    double* dst = host ? ctx->stage : pos;
+    hipLaunchKernelGGL(k_stage_out_pos, dim3(nblocks(n)), dim3(kBlock), 0, s, ctx->pos, (int)n, ctx->id, ctx->box,
+                       dst);
+    if (host) {
+      hipError_t e = hipMemcpyAsync(pos, ctx->stage, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) rc = set_err(ctx, FIRE_E_DEVICE, hip_err_str(e));
+    }
+    if (!rc && trace_host && out) {
+      hipError_t e = hipMemcpyAsync(trace_host, ctx->trace,
+                                    sizeof(double) * FIRE_TRACE_COLS * (size_t)(out->iterations + 1),
+                                    hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) rc = set_err(ctx, FIRE_E_DEVICE, hip_err_str(e));
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (!rc && e != hipSuccess) rc = set_err(ctx, FIRE_E_DEVICE, hip_err_str(e));
+  }
+  if (trace_host) {
+    hipFree(ctx->trace);
+    ctx->trace = nullptr;
+    ctx->trace_cap = 0;
+    drop_graphs(ctx);
+  }
+  ctx->stream = saved;
+  return rc;
+}
+
+int fire_minimize(fire_ctx* ctx, long long n, double* pos, const fire_box* box, const fire_potential* pot, double tol,
+                  long long max_steps, fire_result* out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return minimize_common(ctx, n, pos, true, box, pot, tol, max_steps, out, nullptr, ctx->stream);
+}
+
+int fire_minimize_traced(fire_ctx* ctx, long long n, double* pos, const fire_box* box, const fire_potential* pot,
+                         double tol, long long max_steps, fire_result* out, double* trace) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!trace || !out) return set_err(ctx, FIRE_E_ARG, "trace and out are required");
+  return minimize_common(ctx, n, pos, true, box, pot, tol, max_steps, out, trace, ctx->stream);
+}
+
+int fire_minimize_dev(fire_ctx* ctx, long long n, double* d_pos, const fire_box* box, const fire_potential* pot,
+                      double tol, long long max_steps, fire_result* out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return minimize_common(ctx, n, d_pos, false, box, pot, tol, max_steps, out, nullptr, pick_stream(ctx, stream));
+}
+
+static int hvp_common(fire_ctx* ctx, long long n, const double* pos, const double* u, bool host, const fire_box* box,
+                      const fire_potential* pot, double* hu, hipStream_t s) {
+  if (!u || !hu) return set_err(ctx, FIRE_E_ARG, "u and hu are required");
+  int rc = prepare_system(ctx, box, pot);
+  if (rc) return rc;
+  hipStream_t saved = ctx->stream;
+  ctx->stream = s;
+  rc = stage_in(ctx, n, pos, host, s);
+  if (!rc) rc = rebuild(ctx);
+  if (!rc) rc = ensure_aux(ctx, 9);
+  if (!rc) {
+    const double* usrc = u;
+    if (host) {
+      hipError_t e = hipMemcpyAsync(ctx->stage, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) rc = set_err(ctx, FIRE_E_DEVICE, hip_err_str(e));
+      usrc = ctx->stage;
+    }
+    double* us = ctx->aux;
+    double* hs = ctx->aux + 3 * (size_t)ctx->ncap;
+    double* pre = ctx->aux + 6 * (size_t)ctx->ncap;
+    if (!rc) {
+      hipLaunchKernelGGL(k_gather_vec, dim3(nblocks(n)), dim3(kBlock), 0, s, usrc, (int)n, ctx->ncap, ctx->id, us);
+      launch_hvp(ctx, s, us, hs, pre);
+      double* dst = host ? ctx->stage : hu;
+      hipLaunchKernelGGL(k_scatter_vec, dim3(nblocks(n)), dim3(kBlock), 0, s, hs, (int)n, ctx->ncap, ctx->id, dst);
+      if (host) {
+        hipError_t e = hipMemcpyAsync(hu, ctx->stage, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) rc = set_err(ctx, FIRE_E_DEVICE, hip_err_str(e));
+        e = hipStreamSynchronize(s);
+        if (!rc && e != hipSuccess) rc = set_err(ctx, FIRE_E_DEVICE, hip_err_str(e));
+      }
+    }
+  }
+  ctx->stream = saved;
+  return rc;
+}
+
+int fire_hvp(fire_ctx* ctx, long long n, const double* pos, const double* u, const fire_box* box,
+             const fire_potential* pot, double* hu) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return hvp_common(ctx, n, pos, u, true, box, pot, hu, ctx->stream);
+}
+
+int fire_hvp_dev(fire_ctx* ctx, long long n, const double* d_pos, const double* d_u, const fire_box* box,
+                 const fire_potential* pot, double* d_hu, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return hvp_common(ctx, n, d_pos, d_u, false, box, pot, d_hu, pick_stream(ctx, stream));
+}
+
+int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const fire_box* box,
+                          const fire_potential* pot, const double* u0, int k, double* lambda_min) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!lambda_min || k < 1 || k > 500) return set_err(ctx, FIRE_E_ARG, "need lambda_min and 1 <= k <= 500");
+  rc = prepare_system(ctx, box, pot);
+  if (rc) return rc;
+  hipStream_t s = ctx->stream;
+  rc = stage_in(ctx, n, pos, true, s);
+  if (rc) return rc;
+  rc = rebuild(ctx);
+  if (rc) return rc;
+  // planes: k+1 Lanczos vectors (3 each) + w (3) + hvp prologue (3)
+  const int nv = k + 1;
+  rc = ensure_aux(ctx, 3 * nv + 6);
+  if (rc) return rc;
+  const size_t pl = 3 * (size_t)ctx->ncap;
+  double* V = ctx->aux;
+  double* w = ctx->aux + nv * pl;
+  double* pre = w + pl;
+  std::vector<double> start(3 * (size_t)n);
+  if (u0) {
+    memcpy(start.data(), u0, sizeof(double) * 3 * n);
+  } else {
+    unsigned long long x = 0x9E3779B97F4A7C15ULL;  // splitmix64 stream, deterministic start vector
+    for (size_t i = 0; i < start.size(); ++i) {
+      x += 0x9E3779B97F4A7C15ULL;
+      unsigned long long z = x;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+      z ^= z >> 31;
+      start[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(ctx->stage, start.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_gather_vec, dim3(nblocks(n)), dim3(kBlock), 0, s, ctx->stage, (int)n, ctx->ncap, ctx->id, V);
+  // rigid translations are zero modes of every pair potential: keep them out
+  const bool project = ctx->pot.kind != FIRE_POT_HARMONIC;
+  if (project) {
+    rc = dev_remove_mean(ctx, s, V);
+    if (rc) return rc;
+  }
+  double nrm2;
+  rc = dev_dot(ctx, s, V, V, &nrm2);
+  if (rc) return rc;
+  if (!(nrm2 > 0)) return set_err(ctx, FIRE_E_ARG, "start vector has no component off translations");
+  const int nb = nblocks(n);
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, s, V, V, (int)n, ctx->ncap, 1.0 / std::sqrt(nrm2), 0.0);
+  std::vector<double> a, b;
+  for (int j = 0; j < k; ++j) {
+    double* vj = V + j * pl;
+    launch_hvp(ctx, s, vj, w, pre);
+    rc = dev_remove_mean(ctx, s, w);
+    if (rc) return rc;
+    // full re-orthogonalisation against all previous vectors (twice)
+    double aj = 0.0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q <= j; ++q) {
+        double h;
+        rc = dev_dot(ctx, s, V + q * pl, w, &h);
+        if (rc) return rc;
+        if (q == j) aj += h;
+        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, s, w, V + q * pl, (int)n, ctx->ncap, 1.0, -h);
+      }
+    a.push_back(aj);
+    double bb;
+    rc = dev_dot(ctx, s, w, w, &bb);
+    if (rc) return rc;
+    double bj = std::sqrt(std::max(bb, 0.0));
+    if (j == k - 1 || bj < 1e-12 * std::fabs(aj)) break;
+    b.push_back(bj);
+    HIPCHK(hipMemcpyAsync(V + (j + 1) * pl, w, sizeof(double) * pl, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, s, V + (j + 1) * pl, V, (int)n, ctx->ncap, 1.0 / bj, 0.0);
+  }
+  b.resize(a.size() > 0 ? a.size() - 1 : 0);
+  *lambda_min = tridiag_min_eig(a, b);
+  return FIRE_OK;
+}
+
+int fire_minimize_batched(fire_ctx* ctx, int nsys, const long long* offsets, double* pos, const fire_box* boxes,
+                          const fire_potential* pot, const fire_params* per_sys, double tol, long long max_steps,
+                          fire_result* out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return fire_batched_run(ctx, nsys, offsets, pos, boxes, pot, per_sys, tol, max_steps, out);
+}
+
+}  // extern "C"
