@@ -1,0 +1,251 @@
+"""FIRE 2.0 hot-path benchmark on one MI355X.
+
+A step is one full FIRE 2.0 relaxation of the workload to fmax < 1e-6 (all
+hot-path stages: stage-in and cell sort, neighbour list, force passes with
+fused reductions, FIRE control and update), starting from the same
+HBM-resident positions each time.
+
+Default workload (the headline configuration): LJ, FCC 32x32x32 cells
+(131,072 sites, 655 vacancies -> 130,417 atoms), Gaussian noise 0.05 sigma,
+FP64 path; the mixed-precision path is run on the same input beside it.
+
+Prints ONE JSON line.  value = atom-force-evals/s = atoms * force evaluations
+/ wall time of the K timed relaxations.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom-force-evals/s + FIRE2 steps/s to fmax 1e-6; mixed/batched vs FP64 plain"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+# Algorithmic cost of one force evaluation per atom (each in-range pair counted
+# once, FCC neighbour shells): LJ rc = 2.5 sigma -> 54 neighbours = 27 pairs of
+# ~30 flop; Gupta r_out = 5 A -> 42 neighbours = 21 pairs of ~125 flop (FP64,
+# two exponentials and a square root).  Bytes: positions read once, velocities
+# read for P = F.v, forces written (3 x 8 B each); the EAM form adds F'(rho)
+# written and read (2 x 8 B).
+ALG = {
+    "lj": {"bytes": 72.0, "flops": 27.0 * 30.0, "kernel": "k_lj_force"},
+    "gupta": {"bytes": 88.0, "flops": 21.0 * 125.0, "kernel": "k_gupta_force"},
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha1()
+    for f in ("fire2.hip", "fire2_internal.h"):
+        with open(os.path.join(ROOT, "paper_1908_02038_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_system(name: str):
+    from paper_1908_02038_amd import inputs
+    return inputs.WORKLOADS[name]()
+
+
+def time_relaxations(ctx, pos0_dev, s, steps: int, warmup: int, max_steps: int):
+    import torch
+    work = torch.empty_like(pos0_dev)
+    res = None
+    for _ in range(warmup):
+        work.copy_(pos0_dev)
+        res = ctx.fire_minimize_dev(work, s.box, s.potential, s.tol, max_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        work.copy_(pos0_dev)
+        results.append(ctx.fire_minimize_dev(work, s.box, s.potential, s.tol, max_steps))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, results, work
+
+
+def kernel_time_ms(ctx, reps: int) -> float:
+    """Average duration of one force evaluation (the dominant kernel), HIP
+    events on the stream the kernels are launched on."""
+    import torch
+    stream = torch.cuda.current_stream()
+    ctx.fire_repeat_forces_dev(3)  # warm
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    ctx.fire_repeat_forces_dev(reps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def cpu_baseline(s, budget_s: float):
+    """The oracle as it stands (brute-force pair sums, OpenMP over atoms) on a
+    bounded sample: the first FIRE 2.0 iterations of the same workload."""
+    import oracle
+    n = len(s.pos)
+    t0 = time.perf_counter()
+    oracle.energy_forces(s.pos, s.box, s.potential)
+    t1 = time.perf_counter() - t0
+    steps = max(0, min(10, int(budget_s / max(t1, 1e-9)) - 2))
+    t0 = time.perf_counter()
+    r = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, s.tol, steps)
+    dt = time.perf_counter() - t0
+    evals = r["force_evals"]
+    return {
+        "value": n * evals / dt,
+        "unit": "atom-force-evals/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": f"{steps} FIRE 2.0 iterations ({evals} brute-force force evaluations) of the full {n}-atom "
+                  f"workload, {dt:.1f} s",
+        "steps_per_s": r["iterations"] / dt if dt > 0 else None,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lj_bulk", choices=["lj_small", "lj_bulk", "gupta_bulk", "gupta_slab"])
+    ap.add_argument("--max-steps", type=int, default=100000)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(the multi-GPU decomposition is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1908_02038_amd import api
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    s = make_system(args.workload)
+    n = len(s.pos)
+    kind = s.potential["kind"]
+    log(f"[bench] workload {args.workload}: {n} atoms, potential {kind}, tol {s.tol}")
+    pos0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+
+    # ---- FP64 plain path (headline)
+    ctx = api.Context(0, s.fire, precision="fp64")
+    dt, res, final = time_relaxations(ctx, pos0, s, args.steps, args.warmup, args.max_steps)
+    r = res[-1]
+    evals = sum(x["force_evals"] for x in res)
+    iters = sum(x["iterations"] for x in res)
+    value = n * evals / dt
+    log(f"[bench] fp64: {args.steps} relaxations in {dt:.3f} s, {r['iterations']} iterations each, "
+        f"stop {r['stop']}, E/N {r['energy_per_atom']:.12f}, fmax {r['fmax']:.3e}, rebuilds {r['rebuilds']}")
+    kt = kernel_time_ms(ctx, args.kernel_reps)
+    alg = ALG[kind]
+    bytes_launch = alg["bytes"] * n
+    flops_launch = alg["flops"] * n
+    hbm_ach = bytes_launch / (kt * 1e-3) / 1e9
+    alu_ach = flops_launch / (kt * 1e-3) / 1e12
+    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    ai = alg["flops"] / alg["bytes"]
+    kname = alg["kernel"]
+    traffic = load_traffic(kname, args.workload)
+    if ai > ridge:
+        roof = {"bound": "alu", "achieved": alu_ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": alu_ach / PEAK_FP64_TFLOPS}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": hbm_ach / PEAK_HBM_GBS}
+    roof.update({"traffic": traffic, "kernel": kname + "<double>", "ms_per_launch": kt,
+                 "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops_launch,
+                 "hbm_achieved_GBs": hbm_ach, "hbm_frac": hbm_ach / PEAK_HBM_GBS,
+                 "arithmetic_intensity": ai, "ridge": ridge})
+    log(f"[bench] force pass {kt * 1e3:.1f} us/launch: {hbm_ach:.0f} GB/s alg ({hbm_ach / PEAK_HBM_GBS:.3f} of HBM), "
+        f"{alu_ach:.2f} TFLOP/s alg ({alu_ach / PEAK_FP64_TFLOPS:.3f} of FP64)")
+    ctx.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "atom-force-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "atoms": n, "potential": kind, "fmax_tol": s.tol,
+                   "fire": {k: s.fire[k] for k in ("dt_start", "tmax", "alpha0", "delaystep", "dtgrow",
+                                                   "dtshrink", "integrator")}},
+        "steps_per_s": iters / dt,
+        "iterations_per_relaxation": r["iterations"],
+        "stop": r["stop"],
+        "energy_per_atom": r["energy_per_atom"],
+        "fmax": r["fmax"],
+        "roofline": roof,
+    }
+
+    # ---- mixed precision on the same input
+    if not args.no_mixed:
+        ctxm = api.Context(0, s.fire, precision="mixed")
+        dtm, resm, _ = time_relaxations(ctxm, pos0, s, args.steps, args.warmup, args.max_steps)
+        rm = resm[-1]
+        evm = sum(x["force_evals"] for x in resm)
+        itm = sum(x["iterations"] for x in resm)
+        ktm = kernel_time_ms(ctxm, args.kernel_reps)  # params say mixed -> FP32 pair kernel
+        ctxm.close()
+        out["mixed"] = {
+            "value": n * evm / dtm,
+            "ms_per_step": dtm / args.steps * 1e3,
+            "steps_per_s": itm / dtm,
+            "iterations_per_relaxation": rm["iterations"],
+            "iterations_fp32": rm["iterations_low"],
+            "stop": rm["stop"],
+            "energy_per_atom": rm["energy_per_atom"],
+            "energy_per_atom_rel_diff_vs_fp64": abs(rm["energy_per_atom"] - r["energy_per_atom"])
+            / abs(r["energy_per_atom"]),
+            "fmax": rm["fmax"],
+            "fp32_force_pass_ms": ktm,
+            "speedup_vs_fp64_wall": dt / args.steps / (dtm / args.steps),
+        }
+        log(f"[bench] mixed: {rm['iterations']} iterations ({rm['iterations_low']} FP32), "
+            f"{dtm / args.steps * 1e3:.1f} ms/relaxation, FP32 force pass {ktm * 1e3:.1f} us")
+
+    if not args.no_cpu:
+        log("[bench] cpu oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_budget)
+        log(f"[bench] cpu: {out['cpu_baseline']['sample']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

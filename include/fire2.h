@@ -14,8 +14,9 @@
  *   - Positions, forces and direction fields are row-major double[n][3] in the
  *     caller's atom order.  Energies are in the potential's units.
  *   - Host-pointer calls copy in and out and return when the result is on the
- *     host.  *_dev calls take device pointers and a hipStream_t (passed as
- *     void*, NULL = the context's stream); they enqueue on that stream.
+ *     host.  *_dev calls take device pointers and a hipStream_t passed as
+ *     void* (NULL is the legacy default stream, as in HIP); they enqueue on
+ *     that stream, after the work already queued there.
  *     fire_energy_forces_dev and fire_hvp_dev do not synchronise;
  *     fire_minimize_dev polls a small status word and returns when done.
  *   - The caller owns every array it passes; the context owns its device
@@ -205,6 +206,14 @@ int fire_hvp_dev(fire_ctx* ctx, long long n, const double* d_pos, const double* 
 int fire_minimize_dev(fire_ctx* ctx, long long n, double* d_pos, const fire_box* box,
                       const fire_potential* pot, double tol, long long max_steps, fire_result* out,
                       void* stream);
+
+/* Measurement hook: re-run the force evaluation (density and force passes for
+ * the EAM form) of the system left by the last call on ctx, at its current
+ * positions and neighbour list, reps times on stream, with the same kernels
+ * and launch shapes as inside fire_minimize and the precision of the
+ * context's params.  Forces and reductions are recomputed to the same values;
+ * nothing else changes.  FIRE_E_ARG if no system has been evaluated yet. */
+int fire_repeat_forces_dev(fire_ctx* ctx, int reps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -253,6 +253,13 @@ class Context:
         return _result(r)
 
 
+    def fire_repeat_forces_dev(self, reps: int, stream=None):
+        """Re-run the force pass of the last system reps times on torch's
+        current stream (measurement hook)."""
+        st = self._stream() if stream is None else stream
+        self._check(self.lib.fire_repeat_forces_dev(self.handle, int(reps), st))
+
+
 def fire_init(device: int = 0, fire: dict | None = None, **over) -> Context:
     return Context(device, fire, **over)
 

@@ -8,8 +8,9 @@
 //              pair terms over a cell-sorted full neighbour list; the force
 //              epilogue reduces E, P = F.v, |F|^2, |v|^2, max |F_i|^2,
 //              max |v_i|^2 per block (wave64 shuffles -> LDS)
-//   k_control  fixed-order second reduction stage + the scalar FIRE 2.0
-//              logic (counters, dt/alpha, stop tests, mixing coefficients)
+//   (last block of the force pass) fixed-order second reduction stage and
+//              the scalar FIRE 2.0 logic (counters, dt/alpha, stop tests,
+//              mixing coefficients)
 // K iterations are captured in a hipGraph and replayed; every kernel exits at
 // once when the control record says the run is stopped or paused, and the
 // host only polls a 32-byte status word between replays.
@@ -111,11 +112,18 @@ __device__ __forceinline__ bool ctrl_running(const Ctrl* c) {
 
 // ----------------------------------------------------------- stage in/out
 
+// Caller AoS positions -> slot order (identity), zero v and F; slots n..ncap
+// get NaN positions (the neighbour-list padding target).
 __global__ void k_stage_in(const double* __restrict__ src, int n, int ncap, double4* __restrict__ pos,
                            double* __restrict__ vel, double* __restrict__ frc, int* __restrict__ id,
                            int* __restrict__ flags) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i > ncap) return;
+  if (i >= n) {
+    const double qn = __builtin_nan("");
+    pos[i] = make_double4(qn, qn, qn, 0.0);
+    return;
+  }
   double x = src[3 * i], y = src[3 * i + 1], z = src[3 * i + 2];
   if (!isfinite(x) || !isfinite(y) || !isfinite(z)) atomicOr(flags, ERR_NONFINITE);
   pos[i] = make_double4(x, y, z, 0.0);
@@ -262,20 +270,18 @@ __global__ void k_cell_fill(const int* __restrict__ cell_of, int n, const int* _
   order[start[c] + atomicAdd(&cursor[c], 1)] = i;
 }
 
-// Deterministic order inside each cell: by caller atom index.
-__global__ void k_cell_sort(const int* __restrict__ start, int ncell, const int* __restrict__ id,
+// Deterministic order inside each cell: by caller atom index.  One thread per
+// slot ranks its atom among the cell's members.
+__global__ void k_cell_rank(const int* __restrict__ cell_of, const int* __restrict__ start,
+                            const int* __restrict__ bucket, int n, const int* __restrict__ id,
                             int* __restrict__ order) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  int b = start[c], e = start[c + 1];
-  for (int a = b + 1; a < e; ++a) {
-    int v = order[a], key = id[v], k = a - 1;
-    while (k >= b && id[order[k]] > key) {
-      order[k + 1] = order[k];
-      --k;
-    }
-    order[k + 1] = v;
-  }
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int a = bucket[s], c = cell_of[a], key = id[a];
+  const int b = start[c], e = start[c + 1];
+  int rank = 0;
+  for (int t = b; t < e; ++t) rank += id[bucket[t]] < key;
+  order[b + rank] = a;
 }
 
 __global__ void k_permute(const int* __restrict__ order, int n, int ncap, const double4* __restrict__ pos,
@@ -294,67 +300,87 @@ __global__ void k_permute(const int* __restrict__ order, int n, int ncap, const 
   }
 }
 
-// Neighbour search over the cell stencil: count (FILL = false) or write the
-// full list (FILL = true) of atoms within rcs of each atom, cells in fixed
-// order, atoms of a cell in slot order.
-template <bool FILL>
-__global__ void k_nbr(const double4* __restrict__ pos, int n, BoxDev box, Grid g, const int* __restrict__ start,
-                      double rcs2, int stride, int kcap, int* __restrict__ nnbr, int* __restrict__ nbr,
-                      int* __restrict__ maxcount, int* __restrict__ flags) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double4 pi = pos[i];
-  int c[3] = {cell_coord(pi.x, g, 0), cell_coord(pi.y, g, 1), cell_coord(pi.z, g, 2)};
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Full neighbour list of every atom (all atoms within rcs, cells in fixed
+// order, atoms of a cell in slot order), stored per wave of 64 atoms as
+// nbr[(w * kcap + k) * 64 + lane].  Each wave's lists are padded to a common
+// length (a multiple of 4, kept in wcnt[w]) with the index of a dummy slot
+// whose position is NaN, so the force loops run a wave-uniform trip count and
+// the padding fails every cutoff test.  The grid covers every wave of the
+// allocation.  flags[0] |= overlap, flags[1] = max count.
+__global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict__ pos, int n, BoxDev box, Grid g,
+                                                      const int* __restrict__ start, double rcs2, int kcap,
+                                                      int dummy, int* __restrict__ nbr, int* __restrict__ wcnt,
+                                                      int* __restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = i >> 6, lane = threadIdx.x & 63;
+  int* lst = nbr + (size_t)w * kcap * 64 + lane;
   int cnt = 0;
   bool overlap = false;
-  for (int oz = g.lo_off[2]; oz <= g.hi_off[2]; ++oz) {
-    int cz = c[2] + oz;
-    if (box.per[2]) cz = (cz + g.n[2]) % g.n[2];
-    else if (cz < 0 || cz >= g.n[2]) continue;
-    for (int oy = g.lo_off[1]; oy <= g.hi_off[1]; ++oy) {
-      int cy = c[1] + oy;
-      if (box.per[1]) cy = (cy + g.n[1]) % g.n[1];
-      else if (cy < 0 || cy >= g.n[1]) continue;
-      for (int ox = g.lo_off[0]; ox <= g.hi_off[0]; ++ox) {
-        int cx = c[0] + ox;
-        if (box.per[0]) cx = (cx + g.n[0]) % g.n[0];
-        else if (cx < 0 || cx >= g.n[0]) continue;
-        int cell = cx + g.n[0] * (cy + g.n[1] * cz);
-        for (int j = start[cell], e = start[cell + 1]; j < e; ++j) {
-          if (j == i) continue;
-          double4 pj = pos[j];
-          double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-          min_image(dx, dy, dz, box);
-          double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == 0.0) overlap = true;
-          if (r2 < rcs2) {
-            if (FILL && cnt < kcap) nbr[(size_t)cnt * stride + i] = j;
-            ++cnt;
+  if (i < n) {
+    const double4 pi = pos[i];
+    const int c[3] = {cell_coord(pi.x, g, 0), cell_coord(pi.y, g, 1), cell_coord(pi.z, g, 2)};
+    for (int oz = g.lo_off[2]; oz <= g.hi_off[2]; ++oz) {
+      int cz = c[2] + oz;
+      if (box.per[2]) cz = (cz + g.n[2]) % g.n[2];
+      else if (cz < 0 || cz >= g.n[2]) continue;
+      for (int oy = g.lo_off[1]; oy <= g.hi_off[1]; ++oy) {
+        int cy = c[1] + oy;
+        if (box.per[1]) cy = (cy + g.n[1]) % g.n[1];
+        else if (cy < 0 || cy >= g.n[1]) continue;
+        for (int ox = g.lo_off[0]; ox <= g.hi_off[0]; ++ox) {
+          int cx = c[0] + ox;
+          if (box.per[0]) cx = (cx + g.n[0]) % g.n[0];
+          else if (cx < 0 || cx >= g.n[0]) continue;
+          const int cell = cx + g.n[0] * (cy + g.n[1] * cz);
+          for (int j = start[cell], e = start[cell + 1]; j < e; ++j) {
+            if (j == i) continue;
+            const double4 pj = pos[j];
+            double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            min_image(dx, dy, dz, box);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) overlap = true;
+            if (r2 < rcs2) {
+              if (cnt < kcap) lst[(size_t)cnt * 64] = j;
+              ++cnt;
+            }
           }
         }
       }
     }
   }
-  if (overlap) atomicOr(flags, ERR_OVERLAP);
-  if (!FILL) {
-    nnbr[i] = cnt;
-    atomicMax(maxcount, cnt);
+  const int m = wave_max_i(cnt);
+  const int kw = min((m + 3) & ~3, kcap);
+  for (int k = cnt; k < kw; ++k) lst[(size_t)k * 64] = dummy;
+  if (lane == 0) {
+    wcnt[w] = kw;
+    atomicMax(&flags[1], m);
   }
+  if (overlap) atomicOr(&flags[0], ERR_OVERLAP);
 }
 
 // ----------------------------------------------------------- FIRE update
 
 // One integration step of every atom with the coefficients the control
-// kernel prepared:
+// prepared:
 //   P <= 0 (neg):  x -= hsb v;  v = 0                      (Algorithm 2)
 //   mix_first:     v = cv v + cf F                         (Algorithm 1)
 //   v += kick1 F;  [v = cv v + cf F];  x += dtx v;  v += kick2 F
 // semi-implicit Euler: kick1 = dt/m, kick2 = 0 (Algorithm 4); explicit Euler:
 // kick1 = 0, kick2 = dt/m (Algorithm 3); velocity Verlet: kick1 = dt/2m and
 // the second half kick in the force epilogue (Algorithm 6).
+// An atom farther than skin/2 from its position at the last list build sets
+// ctrl->viol; the next force pass then hands control to the host for a
+// rebuild.
 __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, double* __restrict__ vel,
-                                                   const double* __restrict__ frc, int n, int ncap,
-                                                   const Ctrl* __restrict__ ctrl) {
+                                                   const double* __restrict__ frc,
+                                                   const double4* __restrict__ xref, int n, int ncap,
+                                                   Ctrl* __restrict__ ctrl) {
   if (!ctrl_running(ctrl)) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -384,232 +410,36 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
   vel[i] = v[0];
   vel[ncap + i] = v[1];
   vel[2 * ncap + i] = v[2];
+  const double4 r = xref[i];
+  const double ex = x[0] - r.x, ey = x[1] - r.y, ez = x[2] - r.z;
+  if (ex * ex + ey * ey + ez * ez > ctrl->skin_half2) atomicOr(&ctrl->viol, 1);
 }
 
-// Force-pass epilogue of one atom: store F, apply the velocity-Verlet second
-// half kick, and fold E, P, |F|^2, |v|^2, max |F_i|^2, max |v_i|^2 into the
-// block's reduction record.
-__device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, double fy, double fz, double e,
-                                               double* __restrict__ frc, double* __restrict__ vel, int ncap,
-                                               double kick3, double* __restrict__ part, int rec) {
-  double r[6] = {0, 0, 0, 0, 0, 0};
-  if (valid) {
-    frc[i] = fx;
-    frc[ncap + i] = fy;
-    frc[2 * ncap + i] = fz;
-    double vx = vel[i], vy = vel[ncap + i], vz = vel[2 * ncap + i];
-    if (kick3 != 0.0) {
-      vx += kick3 * fx;
-      vy += kick3 * fy;
-      vz += kick3 * fz;
-      vel[i] = vx;
-      vel[ncap + i] = vy;
-      vel[2 * ncap + i] = vz;
+// Entry gate of the force-evaluation kernels: run only while the FIRE loop is
+// running and the list is valid; the first block that sees a skin violation
+// hands control to the host.
+__device__ __forceinline__ bool pass_gate(Ctrl* c) {
+  const int st = __hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (st != ST_RUNNING) return false;
+  if (__hip_atomic_load(&c->viol, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c->pause |= PAUSE_REBUILD;
+      __hip_atomic_store(&c->status, ST_PAUSED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    double f2 = fx * fx + fy * fy + fz * fz, v2 = vx * vx + vy * vy + vz * vz;
-    r[0] = e;
-    r[1] = fx * vx + fy * vy + fz * vz;
-    r[2] = f2;
-    r[3] = v2;
-    r[4] = f2;
-    r[5] = v2;
+    return false;
   }
-  block_reduce<4, 2>(r);
-  if (threadIdx.x == 0) {
-    double* o = part + (size_t)kRed * rec;
-    o[R_E] = r[0];
-    o[R_P] = r[1];
-    o[R_F2] = r[2];
-    o[R_V2] = r[3];
-    o[R_FMAX2] = r[4];
-    o[R_VMAX2] = r[5];
-  }
+  return true;
 }
 
-// ------------------------------------------------------------ pair kernels
-
-// Energy-shifted LJ.  Separations and the r^2 < rc^2 test in FP64; the pair
-// terms and per-atom accumulation in T (double, or float for the mixed path).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                     const int* __restrict__ nnbr, int n, int stride, int ncap,
-                                                     BoxDev box, PotDev pot, double* __restrict__ frc,
-                                                     double* __restrict__ vel, double* __restrict__ part,
-                                                     Ctrl* __restrict__ ctrl) {
-  if (!ctrl_running(ctrl)) return;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
-  T ax = 0, ay = 0, az = 0, ae = 0;
-  if (valid) {
-    const double4 pi = pos[i];
-    const int cnt = nnbr[i];
-    const T eps24 = (T)(24.0 * pot.eps), eps4 = (T)(4.0 * pot.eps), sig2 = (T)pot.sig2, sh = (T)pot.shift;
-    for (int k = 0; k < cnt; ++k) {
-      const int j = nbr[(size_t)k * stride + i];
-      const double4 pj = pos[j];
-      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-      min_image(dx, dy, dz, box);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < pot.rc2) {
-        T ir2;
-        if constexpr (sizeof(T) == 8) ir2 = rcp_d(r2);
-        else ir2 = rcp_f((float)r2);
-        const T s2 = sig2 * ir2, s6 = s2 * s2 * s2;
-        const T fr = eps24 * s6 * ((T)2 * s6 - (T)1) * ir2;
-        ax += fr * (T)dx;
-        ay += fr * (T)dy;
-        az += fr * (T)dz;
-        ae += (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh);
-      }
-    }
-  }
-  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, ctrl->kick3, part, b);
+__device__ __forceinline__ double ld_cohere(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
-// F'(rho_i) = -xi / (2 sqrt(rho_i)) in pos[i].w and sums F(rho_i) per block.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                          const int* __restrict__ nnbr, int n, int stride,
-                                                          BoxDev box, PotDev pot, double* __restrict__ part_emb,
-                                                          const Ctrl* __restrict__ ctrl) {
-  if (!ctrl_running(ctrl)) return;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * blockDim.x + threadIdx.x;
-  double emb = 0.0;
-  if (i < n) {
-    const double4 pi = pos[i];
-    const int cnt = nnbr[i];
-    const T qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in, inv_w = (T)pot.inv_w;
-    T rho = 0;
-    for (int k = 0; k < cnt; ++k) {
-      const int j = nbr[(size_t)k * stride + i];
-      const double4 pj = pos[j];
-      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-      min_image(dx, dy, dz, box);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < pot.rc2) {
-        T r;
-        if constexpr (sizeof(T) == 8) r = sqrt(r2);
-        else r = sqrtf((float)r2);
-        const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
-        const T S = (1 - s) * (1 - s) * (1 + 2 * s);
-        rho += exp(-qr0 * (r - r0)) * S;
-      }
-    }
-    double fp = 0.0;
-    if (rho > 0) {
-      const double sq = sqrt((double)rho);
-      fp = -0.5 * pot.xi / sq;
-      emb = -pot.xi * sq;
-    }
-    pos[i].w = fp;
-  }
-  double r[1] = {emb};
-  block_reduce<1, 0>(r);
-  if (threadIdx.x == 0) part_emb[b] = r[0];
-}
-
-// Gupta force pass: F_i = -sum_j [c phi_t'(r) + (F'_i + F'_j) rho_t'(r)] d/r,
-// e_i = w_e sum_j phi_t(r).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                        const int* __restrict__ nnbr, int n, int stride, int ncap,
-                                                        BoxDev box, PotDev pot, double* __restrict__ frc,
-                                                        double* __restrict__ vel, double* __restrict__ part,
-                                                        Ctrl* __restrict__ ctrl) {
-  if (!ctrl_running(ctrl)) return;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
-  T ax = 0, ay = 0, az = 0, ae = 0;
-  if (valid) {
-    const double4 pi = pos[i];
-    const int cnt = nnbr[i];
-    const T A = (T)pot.A, pr0 = (T)pot.pr0, qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in,
-            inv_w = (T)pot.inv_w, cpair = (T)pot.cpair, epair = (T)pot.epair, fpi = (T)pi.w;
-    for (int k = 0; k < cnt; ++k) {
-      const int j = nbr[(size_t)k * stride + i];
-      const double4 pj = pos[j];
-      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-      min_image(dx, dy, dz, box);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < pot.rc2) {
-        T ir;
-        if constexpr (sizeof(T) == 8) ir = rsqrt_d(r2);
-        else ir = rsqrt_f((float)r2);
-        const T r = (T)r2 * ir;
-        const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
-        const T S = (1 - s) * (1 - s) * (1 + 2 * s);
-        const T dS = (T)(-6) * s * (1 - s) * inv_w;
-        const T ph = A * exp(-pr0 * (r - r0));
-        const T rh = exp(-qr0 * (r - r0));
-        const T dph = ph * (dS - pr0 * S);
-        const T drh = rh * (dS - qr0 * S);
-        const T dEdr = cpair * dph + (fpi + (T)pj.w) * drh;
-        const T fr = -dEdr * ir;
-        ax += fr * (T)dx;
-        ay += fr * (T)dy;
-        az += fr * (T)dz;
-        ae += epair * ph * S;
-      }
-    }
-  }
-  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, ctrl->kick3, part, b);
-}
-
-// Quadratic test well E = 1/2 sum k_d x_d^2 (no pairs).
-__global__ __launch_bounds__(kBlock) void k_harmonic_force(const double4* __restrict__ pos, int n, int ncap,
-                                                           PotDev pot, double* __restrict__ frc,
-                                                           double* __restrict__ vel, double* __restrict__ part,
-                                                           Ctrl* __restrict__ ctrl) {
-  if (!ctrl_running(ctrl)) return;
-  const int b = blockIdx.x;
-  const int i = b * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
-  double fx = 0, fy = 0, fz = 0, e = 0;
-  if (valid) {
-    double4 p = pos[i];
-    fx = -pot.k[0] * p.x;
-    fy = -pot.k[1] * p.y;
-    fz = -pot.k[2] * p.z;
-    e = 0.5 * (pot.k[0] * p.x * p.x + pot.k[1] * p.y * p.y + pot.k[2] * p.z * p.z);
-  }
-  force_epilogue(i, valid, fx, fy, fz, e, frc, vel, ncap, ctrl->kick3, part, b);
-}
-
-// --------------------------------------------------------- FIRE control
-
-// Second reduction stage (fixed order) and the scalar FIRE logic, one block.
-// eval_only: record E and the force norms of a single evaluation, no FIRE step.
-__global__ __launch_bounds__(1024) void k_control(Ctrl* __restrict__ c, const double* __restrict__ part,
-                                                  const double* __restrict__ part_emb, int nrec, int eval_only,
-                                                  double* __restrict__ trace) {
-  if (c->status != ST_RUNNING) return;
-  double r[6] = {0, 0, 0, 0, 0, 0};
-  for (int q = threadIdx.x; q < nrec; q += blockDim.x) {
-    const double* o = part + (size_t)kRed * q;
-    r[0] += o[R_E] + (part_emb ? part_emb[q] : 0.0);
-    r[1] += o[R_P];
-    r[2] += o[R_F2];
-    r[3] += o[R_V2];
-    r[4] = fmax(r[4], o[R_FMAX2]);
-    r[5] = fmax(r[5], o[R_VMAX2]);
-  }
-  // block_reduce assumes kBlock threads; do the 1024-thread tree here
-  __shared__ double sm[16][6];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int k = 0; k < 4; ++k) r[k] = wave_sum(r[k]);
-  for (int k = 4; k < 6; ++k) r[k] = wave_max(r[k]);
-  if (lane == 0)
-    for (int k = 0; k < 6; ++k) sm[w][k] = r[k];
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
-    for (int k = 0; k < 4; ++k) r[k] += sm[q][k];
-    for (int k = 4; k < 6; ++k) r[k] = fmax(r[k], sm[q][k]);
-  }
+// The scalar FIRE logic (one thread) on the reduced E, P, |F|^2, |v|^2,
+// max|F_i|^2, max|v_i|^2 of the force evaluation just finished: stop tests,
+// then the branch of Algorithm 2 (or 1) for the next iteration and the
+// coefficients of the next update.
+__device__ void fire_control(Ctrl* __restrict__ c, const double (&r)[6], double* __restrict__ trace) {
   const double E = r[0], P = r[1], F2 = r[2], V2 = r[3], fm = sqrt(r[4]), vm = sqrt(r[5]);
   c->energy = E;
   c->P = P;
@@ -629,7 +459,7 @@ __global__ __launch_bounds__(1024) void k_control(Ctrl* __restrict__ c, const do
     c->status = FIRE_E_NONFINITE;
     return;
   }
-  if (eval_only) return;
+  if (c->eval_only) return;
   if (trace && it < c->trace_cap) {
     double* t = trace + (size_t)FIRE_TRACE_COLS * it;
     t[0] = (double)it;
@@ -689,7 +519,7 @@ __global__ __launch_bounds__(1024) void k_control(Ctrl* __restrict__ c, const do
   }
   const double dtf = dt * c->f2a;
   const double fn = sqrt(F2);
-  const double Pe = neg ? 0.0 : P, V2e = neg ? 0.0 : V2, vme = neg ? 0.0 : vm;
+  const double Pe = neg ? 0.0 : P, V2e = neg ? 0.0 : V2;
   double k1, k2, k3, cv, cf;
   int mix_first = 0;
   if (c->integrator == FIRE_INT_EULER_EXPLICIT) {
@@ -715,29 +545,13 @@ __global__ __launch_bounds__(1024) void k_control(Ctrl* __restrict__ c, const do
     cv = neg ? 1.0 : 1.0 - alpha_mix;
     cf = (neg || !(fn > 0.0)) ? 0.0 : alpha_mix * sqrt(V2) / fn;
   }
-  const double hsb = (neg && c->variant == FIRE_VARIANT_FIRE2 && c->halfstepback) ? 0.5 * dt : 0.0;
-  // bound on any atom's displacement in this update, for the list skin
-  const double fme = fm;
-  double vb = vme;
-  if (mix_first) vb = cv * vb + cf * fme;
-  vb += k1 * fme;
-  if (!mix_first) vb = cv * vb + cf * fme;
-  const double step = hsb * vm + dt * vb;
-  if (step > c->skin_half) {
-    pause |= PAUSE_BIG_STEP;
-  } else if (c->disp + step > c->skin_half) {
-    pause |= PAUSE_REBUILD;
-    c->disp = step;
-  } else {
-    c->disp += step;
-  }
   c->dt = dt;
   c->alpha = alpha;
   c->branch = neg ? -1 : 1;
   c->P_used = P;
   c->neg = neg;
   c->mix_first = mix_first;
-  c->hsb = hsb;
+  c->hsb = (neg && c->variant == FIRE_VARIANT_FIRE2 && c->halfstepback) ? 0.5 * dt : 0.0;
   c->kick1 = k1;
   c->kick2 = k2;
   c->kick3 = k3;
@@ -751,20 +565,257 @@ __global__ __launch_bounds__(1024) void k_control(Ctrl* __restrict__ c, const do
   }
 }
 
+// Force-pass epilogue of one atom: store F, apply the velocity-Verlet second
+// half kick, fold E, P, |F|^2, |v|^2, max |F_i|^2, max |v_i|^2 into the
+// block's reduction record; the last block to finish reduces all records in
+// fixed order (second stage) and runs the FIRE control.
+__device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, double fy, double fz, double e,
+                                               double* __restrict__ frc, double* __restrict__ vel, int ncap,
+                                               double* __restrict__ part, const double* __restrict__ part_emb,
+                                               int rec, Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
+  double r[6] = {0, 0, 0, 0, 0, 0};
+  if (valid) {
+    frc[i] = fx;
+    frc[ncap + i] = fy;
+    frc[2 * ncap + i] = fz;
+    double vx = vel[i], vy = vel[ncap + i], vz = vel[2 * ncap + i];
+    const double kick3 = ctrl->kick3;
+    if (kick3 != 0.0) {
+      vx += kick3 * fx;
+      vy += kick3 * fy;
+      vz += kick3 * fz;
+      vel[i] = vx;
+      vel[ncap + i] = vy;
+      vel[2 * ncap + i] = vz;
+    }
+    const double f2 = fx * fx + fy * fy + fz * fz, v2 = vx * vx + vy * vy + vz * vz;
+    r[0] = e;
+    r[1] = fx * vx + fy * vy + fz * vz;
+    r[2] = f2;
+    r[3] = v2;
+    r[4] = f2;
+    r[5] = v2;
+  }
+  block_reduce<4, 2>(r);
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    double* o = part + (size_t)kRed * rec;
+    o[R_E] = r[0] + (part_emb ? part_emb[rec] : 0.0);
+    o[R_P] = r[1];
+    o[R_F2] = r[2];
+    o[R_V2] = r[3];
+    o[R_FMAX2] = r[4];
+    o[R_VMAX2] = r[5];
+    __threadfence();
+    const unsigned int t = atomicAdd(&ctrl->ticket, 1u);
+    is_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double q[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+    const double* o = part + (size_t)kRed * b;
+    q[0] += ld_cohere(o + R_E);
+    q[1] += ld_cohere(o + R_P);
+    q[2] += ld_cohere(o + R_F2);
+    q[3] += ld_cohere(o + R_V2);
+    q[4] = fmax(q[4], ld_cohere(o + R_FMAX2));
+    q[5] = fmax(q[5], ld_cohere(o + R_VMAX2));
+  }
+  block_reduce<4, 2>(q);
+  if (threadIdx.x == 0) {
+    ctrl->ticket = 0;
+    fire_control(ctrl, q, trace);
+  }
+}
+
+// ------------------------------------------------------------ pair kernels
+
+// Neighbour loop shared by the pair kernels: wave-uniform trip count, four
+// neighbours per step (index loads, then position gathers, then pair terms).
+template <typename F>
+__device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, const int* __restrict__ nbr,
+                                               const int* __restrict__ wcnt, int kcap, int i, F&& pair) {
+  const int w = i >> 6, lane = threadIdx.x & 63;
+  const int kw = __builtin_amdgcn_readfirstlane(wcnt[w]);
+  const int* lst = nbr + (size_t)w * kcap * 64 + lane;
+  for (int k = 0; k < kw; k += 4) {
+    const int j0 = lst[(size_t)(k + 0) * 64], j1 = lst[(size_t)(k + 1) * 64];
+    const int j2 = lst[(size_t)(k + 2) * 64], j3 = lst[(size_t)(k + 3) * 64];
+    const double4 p0 = pos[j0], p1 = pos[j1], p2 = pos[j2], p3 = pos[j3];
+    pair(p0);
+    pair(p1);
+    pair(p2);
+    pair(p3);
+  }
+}
+
+// Energy-shifted LJ.  Separations and the r^2 < rc^2 test in FP64; the pair
+// terms and per-atom accumulation in T (double, or float for the mixed path).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                     const int* __restrict__ wcnt, int n, int kcap, int ncap,
+                                                     BoxDev box, PotDev pot, double* __restrict__ frc,
+                                                     double* __restrict__ vel, double* __restrict__ part,
+                                                     Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
+  if (!pass_gate(ctrl)) return;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  T ax = 0, ay = 0, az = 0, ae = 0;
+  const double4 pi = pos[i];  // slots n..ncap hold NaN
+  const T eps24 = (T)(24.0 * pot.eps), eps4 = (T)(4.0 * pot.eps), sig2 = (T)pot.sig2, sh = (T)pot.shift;
+  for_neighbours(pos, nbr, wcnt, kcap, i, [&](const double4& pj) {
+    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    min_image(dx, dy, dz, box);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < pot.rc2) {
+      T ir2;
+      if constexpr (sizeof(T) == 8) ir2 = rcp_d(r2);
+      else ir2 = rcp_f((float)r2);
+      const T s2 = sig2 * ir2, s6 = s2 * s2 * s2;
+      const T fr = eps24 * s6 * ((T)2 * s6 - (T)1) * ir2;
+      ax += fr * (T)dx;
+      ay += fr * (T)dy;
+      az += fr * (T)dz;
+      ae += (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh);
+    }
+  });
+  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, nullptr, b, ctrl,
+                 trace);
+}
+
+// Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
+// F'(rho_i) = -xi / (2 sqrt(rho_i)) in pos[i].w and sums F(rho_i) per block.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                          const int* __restrict__ wcnt, int n, int kcap,
+                                                          BoxDev box, PotDev pot, double* __restrict__ part_emb,
+                                                          Ctrl* __restrict__ ctrl) {
+  if (!pass_gate(ctrl)) return;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * blockDim.x + threadIdx.x;
+  double emb = 0.0;
+  const double4 pi = pos[i];
+  const T qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in, inv_w = (T)pot.inv_w;
+  T rho = 0;
+  for_neighbours(pos, nbr, wcnt, kcap, i, [&](const double4& pj) {
+    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    min_image(dx, dy, dz, box);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < pot.rc2) {
+      T r;
+      if constexpr (sizeof(T) == 8) r = sqrt(r2);
+      else r = sqrtf((float)r2);
+      const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
+      const T S = (1 - s) * (1 - s) * (1 + 2 * s);
+      rho += exp(-qr0 * (r - r0)) * S;
+    }
+  });
+  if (i < n) {
+    double fp = 0.0;
+    if (rho > 0) {
+      const double sq = sqrt((double)rho);
+      fp = -0.5 * pot.xi / sq;
+      emb = -pot.xi * sq;
+    }
+    pos[i].w = fp;
+  }
+  double r[1] = {emb};
+  block_reduce<1, 0>(r);
+  if (threadIdx.x == 0) part_emb[b] = r[0];
+}
+
+// Gupta force pass: F_i = -sum_j [c phi_t'(r) + (F'_i + F'_j) rho_t'(r)] d/r,
+// e_i = w_e sum_j phi_t(r).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                        const int* __restrict__ wcnt, int n, int kcap, int ncap,
+                                                        BoxDev box, PotDev pot, double* __restrict__ frc,
+                                                        double* __restrict__ vel, double* __restrict__ part,
+                                                        const double* __restrict__ part_emb,
+                                                        Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
+  if (!pass_gate(ctrl)) return;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  T ax = 0, ay = 0, az = 0, ae = 0;
+  const double4 pi = pos[i];
+  const T A = (T)pot.A, pr0 = (T)pot.pr0, qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in,
+          inv_w = (T)pot.inv_w, cpair = (T)pot.cpair, epair = (T)pot.epair, fpi = (T)pi.w;
+  for_neighbours(pos, nbr, wcnt, kcap, i, [&](const double4& pj) {
+    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    min_image(dx, dy, dz, box);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < pot.rc2) {
+      T ir;
+      if constexpr (sizeof(T) == 8) ir = rsqrt_d(r2);
+      else ir = rsqrt_f((float)r2);
+      const T r = (T)r2 * ir;
+      const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
+      const T S = (1 - s) * (1 - s) * (1 + 2 * s);
+      const T dS = (T)(-6) * s * (1 - s) * inv_w;
+      const T ph = A * exp(-pr0 * (r - r0));
+      const T rh = exp(-qr0 * (r - r0));
+      const T dph = ph * (dS - pr0 * S);
+      const T drh = rh * (dS - qr0 * S);
+      const T dEdr = cpair * dph + (fpi + (T)pj.w) * drh;
+      const T fr = -dEdr * ir;
+      ax += fr * (T)dx;
+      ay += fr * (T)dy;
+      az += fr * (T)dz;
+      ae += epair * ph * S;
+    }
+  });
+  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, part_emb, b, ctrl,
+                 trace);
+}
+
+// Quadratic test well E = 1/2 sum k_d x_d^2 (no pairs).
+__global__ __launch_bounds__(kBlock) void k_harmonic_force(const double4* __restrict__ pos, int n, int ncap,
+                                                           PotDev pot, double* __restrict__ frc,
+                                                           double* __restrict__ vel, double* __restrict__ part,
+                                                           Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
+  if (!pass_gate(ctrl)) return;
+  const int b = blockIdx.x;
+  const int i = b * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  double fx = 0, fy = 0, fz = 0, e = 0;
+  if (valid) {
+    double4 p = pos[i];
+    fx = -pot.k[0] * p.x;
+    fy = -pot.k[1] * p.y;
+    fz = -pot.k[2] * p.z;
+    e = 0.5 * (pot.k[0] * p.x * p.x + pot.k[1] * p.y * p.y + pot.k[2] * p.z * p.z);
+  }
+  force_epilogue(i, valid, fx, fy, fz, e, frc, vel, ncap, part, nullptr, b, ctrl, trace);
+}
+
 // ------------------------------------------------------- Hessian * u (FP64)
+
+// Neighbour indices of atom i one at a time (dummy padding included; callers
+// reject it by the cutoff test before touching per-atom arrays).
+template <typename F>
+__device__ __forceinline__ void for_neighbour_index(const int* __restrict__ nbr, const int* __restrict__ wcnt,
+                                                    int kcap, int i, F&& fn) {
+  const int w = i >> 6, lane = threadIdx.x & 63;
+  const int kw = wcnt[w];
+  const int* lst = nbr + (size_t)w * kcap * 64 + lane;
+  for (int k = 0; k < kw; ++k) fn(lst[(size_t)k * 64]);
+}
 
 // Gupta HVP prologue: rho_i, F'_i, F''_i and s_i = sum_j rho'(r) dh.(u_i - u_j).
 __global__ __launch_bounds__(kBlock) void k_gupta_hvp_pre(const double4* __restrict__ pos,
-                                                          const int* __restrict__ nbr, const int* __restrict__ nnbr,
-                                                          int n, int stride, int ncap, BoxDev box, PotDev pot,
+                                                          const int* __restrict__ nbr, const int* __restrict__ wcnt,
+                                                          int n, int kcap, int ncap, BoxDev box, PotDev pot,
                                                           const double* __restrict__ u, double* __restrict__ aux) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 pi = pos[i];
   const double ui[3] = {u[i], u[ncap + i], u[2 * ncap + i]};
   double rho = 0.0, s = 0.0;
-  for (int k = 0, cnt = nnbr[i]; k < cnt; ++k) {
-    const int j = nbr[(size_t)k * stride + i];
+  for_neighbour_index(nbr, wcnt, kcap, i, [&](int j) {
     const double4 pj = pos[j];
     double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     min_image(dx, dy, dz, box);
@@ -779,7 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_gupta_hvp_pre(const double4* __restr
       const double w = (dx * (ui[0] - u[j]) + dy * (ui[1] - u[ncap + j]) + dz * (ui[2] - u[2 * ncap + j])) * ir;
       s += drh * w;
     }
-  }
+  });
   double f1 = 0.0, f2 = 0.0;
   if (rho > 0.0) {
     const double sq = sqrt(rho);
@@ -794,7 +845,7 @@ __global__ __launch_bounds__(kBlock) void k_gupta_hvp_pre(const double4* __restr
 // Hu_i = sum_j [B(g1, g2) w + (F''_i s_i + F''_j s_j) rho' dh], w = u_i - u_j,
 // with B(g1, g2) w = g2 (dh.w) dh + (g1 / r)(w - (dh.w) dh).
 __global__ __launch_bounds__(kBlock) void k_hvp(const double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                const int* __restrict__ nnbr, int n, int stride, int ncap,
+                                                const int* __restrict__ wcnt, int n, int kcap, int ncap,
                                                 BoxDev box, PotDev pot, const double* __restrict__ u,
                                                 const double* __restrict__ aux, double* __restrict__ hu) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -808,13 +859,12 @@ __global__ __launch_bounds__(kBlock) void k_hvp(const double4* __restrict__ pos,
   double acc[3] = {0, 0, 0};
   const bool gupta = pot.kind == FIRE_POT_GUPTA;
   const double f1i = gupta ? aux[i] : 0.0, f2i = gupta ? aux[ncap + i] : 0.0, si = gupta ? aux[2 * ncap + i] : 0.0;
-  for (int k = 0, cnt = nnbr[i]; k < cnt; ++k) {
-    const int j = nbr[(size_t)k * stride + i];
+  for_neighbour_index(nbr, wcnt, kcap, i, [&](int j) {
     const double4 pj = pos[j];
     double d[3] = {pi.x - pj.x, pi.y - pj.y, pi.z - pj.z};
     min_image(d[0], d[1], d[2], box);
     const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (!(r2 < pot.rc2)) continue;
+    if (!(r2 < pot.rc2)) return;
     const double r = sqrt(r2), ir = 1.0 / r;
     const double w[3] = {ui[0] - u[j], ui[1] - u[ncap + j], ui[2] - u[2 * ncap + j]};
     const double dw = (d[0] * w[0] + d[1] * w[1] + d[2] * w[2]) * ir;  // dh.w
@@ -840,7 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp(const double4* __restrict__ pos,
       const double dh = d[q] * ir;
       acc[q] += g2 * dw * dh + g1 * ir * (w[q] - dw * dh) + extra * dh;
     }
-  }
+  });
   hu[i] = acc[0];
   hu[ncap + i] = acc[1];
   hu[2 * ncap + i] = acc[2];
@@ -936,7 +986,9 @@ struct fire_ctx {
   int ccap = 0;
   int *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr;
   int kcap = 0;
-  int *nbr = nullptr, *nnbr = nullptr;
+  int *nbr = nullptr, *wcnt = nullptr;  // list [wave][k][lane], padded length per wave
+  double4* xref = nullptr;                // positions at the last list build
+  int* bucket = nullptr;                  // cell-bucketed slots before ranking
   double *part = nullptr, *part_emb = nullptr, *bbox_part = nullptr;
   double* aux = nullptr;  // HVP / Lanczos planes
   int aux_planes = 0;
@@ -991,6 +1043,9 @@ void free_single(fire_ctx* c) {
   hipFree(c->pos); hipFree(c->pos2); hipFree(c->vel); hipFree(c->vel2); hipFree(c->frc); hipFree(c->frc2);
   hipFree(c->id); hipFree(c->id2); hipFree(c->cell_of); hipFree(c->order); hipFree(c->stage);
   hipFree(c->part); hipFree(c->part_emb); hipFree(c->bbox_part);
+  hipFree(c->xref); hipFree(c->bucket); hipFree(c->wcnt);
+  c->xref = nullptr;
+  c->bucket = c->wcnt = nullptr;
   c->pos = c->pos2 = nullptr;
   c->vel = c->vel2 = c->frc = c->frc2 = nullptr;
   c->id = c->id2 = c->cell_of = c->order = nullptr;
@@ -1006,14 +1061,18 @@ void drop_graphs(fire_ctx* c) {
   }
 }
 
+// Capacity is a multiple of the block size, so every launch over ceil(n/256)
+// blocks stays inside the arrays; pos has one extra slot (NaN) that pads the
+// neighbour lists.
 int ensure_atoms(fire_ctx* ctx, int n) {
   if (n <= ctx->ncap) return FIRE_OK;
   drop_graphs(ctx);
   free_single(ctx);
-  int cap = std::max(n, 64);
-  int nb = nblocks(cap);
-  HIPCHK(dalloc(&ctx->pos, cap));
-  HIPCHK(dalloc(&ctx->pos2, cap));
+  const int cap = ((std::max(n, 64) + kBlock - 1) / kBlock) * kBlock;
+  const int nb = cap / kBlock;
+  HIPCHK(dalloc(&ctx->pos, cap + 1));
+  HIPCHK(dalloc(&ctx->pos2, cap + 1));
+  HIPCHK(dalloc(&ctx->xref, cap));
   HIPCHK(dalloc(&ctx->vel, 3 * (size_t)cap));
   HIPCHK(dalloc(&ctx->vel2, 3 * (size_t)cap));
   HIPCHK(dalloc(&ctx->frc, 3 * (size_t)cap));
@@ -1022,17 +1081,18 @@ int ensure_atoms(fire_ctx* ctx, int n) {
   HIPCHK(dalloc(&ctx->id2, cap));
   HIPCHK(dalloc(&ctx->cell_of, cap));
   HIPCHK(dalloc(&ctx->order, cap));
+  HIPCHK(dalloc(&ctx->bucket, cap));
+  HIPCHK(dalloc(&ctx->wcnt, cap / 64));
   HIPCHK(dalloc(&ctx->stage, 3 * (size_t)cap));
   HIPCHK(dalloc(&ctx->part, (size_t)kRed * nb));
   HIPCHK(dalloc(&ctx->part_emb, nb));
   HIPCHK(dalloc(&ctx->bbox_part, 6 * (size_t)nb));
+  HIPCHK(hipMemset(ctx->wcnt, 0, sizeof(int) * (cap / 64)));
   ctx->ncap = cap;
   ctx->layout_version++;
-  if (ctx->kcap) {  // neighbour list is sized by ncap
+  if (ctx->kcap) {  // the neighbour list is sized by ncap
     hipFree(ctx->nbr);
-    hipFree(ctx->nnbr);
     ctx->nbr = nullptr;
-    ctx->nnbr = nullptr;
     ctx->kcap = 0;
   }
   if (ctx->aux_planes) {
@@ -1175,31 +1235,34 @@ int read_flags(fire_ctx* ctx) {
   return FIRE_OK;
 }
 
-// Sort atoms by cell and build the neighbour list of the current positions.
+// Sort atoms by cell (stable: by caller index inside a cell) and build the
+// neighbour list of the current positions; positions on periodic axes are
+// wrapped into the box.  Records the build positions for the skin test.
 int rebuild(fire_ctx* ctx) {
   const int n = ctx->n;
+  hipStream_t s = ctx->stream;
   if (ctx->pot.kind == FIRE_POT_HARMONIC) {  // no pairs, no list
+    HIPCHK(hipMemcpyAsync(ctx->xref, ctx->pos, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
     ctx->have_list = true;
     return FIRE_OK;
   }
   int rc = make_grid(ctx, n);
   if (rc) return rc;
   const Grid& g = ctx->grid;
-  hipStream_t s = ctx->stream;
   HIPCHK(hipMemsetAsync(ctx->cell_count, 0, sizeof(int) * (g.ncell + 1), s));
   HIPCHK(hipMemsetAsync(ctx->cell_cursor, 0, sizeof(int) * (g.ncell + 1), s));
-  HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
   const int nb = nblocks(n);
   hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g, ctx->cell_of,
                      ctx->cell_count);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctx->cell_count, g.ncell, ctx->cell_start);
   hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(kBlock), 0, s, ctx->cell_of, n, ctx->cell_start,
-                     ctx->cell_cursor, ctx->order);
-  hipLaunchKernelGGL(k_cell_sort, dim3(nblocks(g.ncell)), dim3(kBlock), 0, s, ctx->cell_start, g.ncell, ctx->id,
-                     ctx->order);
+                     ctx->cell_cursor, ctx->bucket);
+  hipLaunchKernelGGL(k_cell_rank, dim3(nb), dim3(kBlock), 0, s, ctx->cell_of, ctx->cell_start, ctx->bucket, n,
+                     ctx->id, ctx->order);
   hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, s, ctx->order, n, ctx->ncap, ctx->pos, ctx->vel,
                      ctx->frc, ctx->id, ctx->pos2, ctx->vel2, ctx->frc2, ctx->id2);
   HIPCHK(hipMemcpyAsync(ctx->pos, ctx->pos2, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->xref, ctx->pos2, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->id, ctx->id2, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
   for (int d = 0; d < 3; ++d) {
     HIPCHK(hipMemcpyAsync(ctx->vel + (size_t)d * ctx->ncap, ctx->vel2 + (size_t)d * ctx->ncap, sizeof(double) * n,
@@ -1207,73 +1270,74 @@ int rebuild(fire_ctx* ctx) {
     HIPCHK(hipMemcpyAsync(ctx->frc + (size_t)d * ctx->ncap, ctx->frc2 + (size_t)d * ctx->ncap, sizeof(double) * n,
                           hipMemcpyDeviceToDevice, s));
   }
-  if (!ctx->nnbr) HIPCHK(dalloc(&ctx->nnbr, ctx->ncap));
   const double rcs2 = ctx->rcs * ctx->rcs;
-  hipLaunchKernelGGL(k_nbr<false>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g, ctx->cell_start, rcs2,
-                     ctx->ncap, 0, ctx->nnbr, (int*)nullptr, ctx->flags + 1, ctx->flags);
-  rc = read_flags(ctx);
-  if (rc) return rc;
-  if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
-  const int kmax = ctx->h_flags[1];
-  if (kmax > ctx->kcap || !ctx->nbr) {
-    hipFree(ctx->nbr);
-    ctx->nbr = nullptr;
-    int kc = std::max(kmax + kmax / 8 + 4, 8);
-    HIPCHK(dalloc(&ctx->nbr, (size_t)kc * ctx->ncap));
-    ctx->kcap = kc;
+  if (ctx->kcap == 0) {
+    // first guess from the mean density; a larger count triggers one more pass
+    double vol = 1.0;
+    for (int k = 0; k < 3; ++k) vol *= g.n[k] / std::max(g.inv[k], 1e-300);
+    double dens = n / std::max(vol, 1e-300);
+    int guess = (int)(1.4 * dens * 4.18879 * rcs2 * ctx->rcs) + 16;
+    ctx->kcap = std::min((guess + 3) & ~3, std::max(4, ((n + 3) & ~3)));
+    HIPCHK(dalloc(&ctx->nbr, (size_t)ctx->kcap * ctx->ncap));
     ctx->layout_version++;
   }
-  hipLaunchKernelGGL(k_nbr<true>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g, ctx->cell_start, rcs2,
-                     ctx->ncap, ctx->kcap, ctx->nnbr, ctx->nbr, ctx->flags + 1, ctx->flags);
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
+    hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g,
+                       ctx->cell_start, rcs2, ctx->kcap, ctx->ncap, ctx->nbr, ctx->wcnt, ctx->flags);
+    rc = read_flags(ctx);
+    if (rc) return rc;
+    if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
+    const int kmax = ctx->h_flags[1];
+    if (kmax <= ctx->kcap) break;
+    hipFree(ctx->nbr);
+    ctx->nbr = nullptr;
+    ctx->kcap = ((kmax + kmax / 8 + 8) + 3) & ~3;
+    HIPCHK(dalloc(&ctx->nbr, (size_t)ctx->kcap * ctx->ncap));
+    ctx->layout_version++;
+  }
   ctx->have_list = true;
   return FIRE_OK;
 }
 
-// One force evaluation (with reductions) enqueued on stream s.  prec: 0 FP64, 1 FP32.
+// One force evaluation (passes + fused reductions and control) enqueued on
+// stream s.  prec: 0 FP64 pair terms, 1 FP32.
 void launch_forces(fire_ctx* ctx, hipStream_t s, int prec) {
-  const int n = ctx->n, nb = nblocks(n);
+  const int n = ctx->n, nb = nblocks(n), kc = ctx->kcap, nc = ctx->ncap;
   const PotDev& P = ctx->pot;
   if (P.kind == FIRE_POT_LJ) {
     if (prec)
-      hipLaunchKernelGGL(k_lj_force<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
-                         ctx->ncap, ctx->ncap, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl);
+      hipLaunchKernelGGL(k_lj_force<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, kc, nc,
+                         ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
     else
-      hipLaunchKernelGGL(k_lj_force<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
-                         ctx->ncap, ctx->ncap, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl);
+      hipLaunchKernelGGL(k_lj_force<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, kc,
+                         nc, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
   } else if (P.kind == FIRE_POT_GUPTA) {
     if (prec) {
-      hipLaunchKernelGGL(k_gupta_density<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
-                         ctx->ncap, ctx->box, P, ctx->part_emb, ctx->ctrl);
-      hipLaunchKernelGGL(k_gupta_force<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
-                         ctx->ncap, ctx->ncap, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl);
+      hipLaunchKernelGGL(k_gupta_density<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n,
+                         kc, ctx->box, P, ctx->part_emb, ctx->ctrl);
+      hipLaunchKernelGGL(k_gupta_force<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, kc,
+                         nc, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace);
     } else {
-      hipLaunchKernelGGL(k_gupta_density<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
-                         ctx->ncap, ctx->box, P, ctx->part_emb, ctx->ctrl);
-      hipLaunchKernelGGL(k_gupta_force<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n,
-                         ctx->ncap, ctx->ncap, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl);
+      hipLaunchKernelGGL(k_gupta_density<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n,
+                         kc, ctx->box, P, ctx->part_emb, ctx->ctrl);
+      hipLaunchKernelGGL(k_gupta_force<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, kc,
+                         nc, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace);
     }
   } else {
-    hipLaunchKernelGGL(k_harmonic_force, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->ncap, P, ctx->frc,
-                       ctx->vel, ctx->part, ctx->ctrl);
+    hipLaunchKernelGGL(k_harmonic_force, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, nc, P, ctx->frc, ctx->vel,
+                       ctx->part, ctx->ctrl, ctx->trace);
   }
 }
 
-void launch_control(fire_ctx* ctx, hipStream_t s, int eval_only) {
-  const int nb = nblocks(ctx->n);
-  hipLaunchKernelGGL(k_control, dim3(1), dim3(1024), 0, s, ctx->ctrl, ctx->part,
-                     ctx->pot.kind == FIRE_POT_GUPTA ? ctx->part_emb : (const double*)nullptr, nb, eval_only,
-                     ctx->trace);
-}
-
 void launch_update(fire_ctx* ctx, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->vel, ctx->frc, ctx->n,
-                     ctx->ncap, ctx->ctrl);
+  hipLaunchKernelGGL(k_update, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->vel, ctx->frc, ctx->xref,
+                     ctx->n, ctx->ncap, ctx->ctrl);
 }
 
 void launch_iteration(fire_ctx* ctx, hipStream_t s, int prec) {
   launch_update(ctx, s);
   launch_forces(ctx, s, prec);
-  launch_control(ctx, s, 0);
 }
 
 int graph_for(fire_ctx* ctx, int prec, hipGraphExec_t* out) {
@@ -1310,7 +1374,8 @@ int stage_in(fire_ctx* ctx, long long n, const double* src, bool host, hipStream
     d = ctx->stage;
   }
   HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
-  hipLaunchKernelGGL(k_stage_in, dim3(nblocks(n)), dim3(kBlock), 0, s, d, (int)n, ctx->ncap, ctx->pos, ctx->vel,
+  hipLaunchKernelGGL(k_stage_in, dim3(nblocks(ctx->ncap + 1)), dim3(kBlock), 0, s, d, (int)n, ctx->ncap, ctx->pos,
+                     ctx->vel,
                      ctx->frc, ctx->id, ctx->flags);
   if (!host) {
     rc = read_flags(ctx);
@@ -1320,7 +1385,7 @@ int stage_in(fire_ctx* ctx, long long n, const double* src, bool host, hipStream
   return FIRE_OK;
 }
 
-void ctrl_defaults(fire_ctx* ctx, Ctrl& c, double tol, long long max_steps) {
+void ctrl_defaults(fire_ctx* ctx, Ctrl& c, double tol, long long max_steps, int eval_only) {
   const fire_params& p = ctx->params;
   memset(&c, 0, sizeof(c));
   c.status = ST_RUNNING;
@@ -1335,7 +1400,8 @@ void ctrl_defaults(fire_ctx* ctx, Ctrl& c, double tol, long long max_steps) {
   c.f2a = p.f2a;
   c.tol = tol;
   c.switch_tol = p.mixed_switch > 0 ? p.mixed_switch : 100.0 * tol;
-  c.skin_half = ctx->pot.kind == FIRE_POT_HARMONIC ? 1e300 : 0.5 * ctx->skin;
+  c.skin_half2 = ctx->pot.kind == FIRE_POT_HARMONIC ? 1e300 : 0.25 * ctx->skin * ctx->skin;
+  c.eval_only = eval_only;
   c.max_steps = max_steps;
   c.delaystep = p.delaystep;
   c.vdfmax = p.vdfmax;
@@ -1362,11 +1428,22 @@ int check_status_error(fire_ctx* ctx, int st) {
 int evaluate(fire_ctx* ctx, hipStream_t s) {
   int rc = rebuild(ctx);
   if (rc) return rc;
-  ctrl_defaults(ctx, *ctx->h_ctrl, 0.0, 0);
+  ctrl_defaults(ctx, *ctx->h_ctrl, 0.0, 0, 1);
   HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   launch_forces(ctx, s, ctx->params.precision == FIRE_FP64 ? 0 : 1);
-  launch_control(ctx, s, 1);
+  return FIRE_OK;
+}
+
+// Resume the device FIRE loop: status running, no pause, no skin violation.
+int resume(fire_ctx* ctx, hipStream_t s) {
+  int* up = ctx->h_flags + 2;
+  up[0] = ST_RUNNING;
+  up[1] = 0;
+  *ctx->h_zero = 0.0;
+  HIPCHK(hipMemcpyAsync(ctx->ctrl, up, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(&ctx->ctrl->viol, ctx->h_zero, sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
   return FIRE_OK;
 }
 
@@ -1375,18 +1452,17 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
   int rc = rebuild(ctx);
   if (rc) return rc;
   long long rebuilds = 1;
-  ctrl_defaults(ctx, *ctx->h_ctrl, tol, max_steps);
+  ctrl_defaults(ctx, *ctx->h_ctrl, tol, max_steps, 0);
   int prec = ctx->h_ctrl->precision;
   HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
-  launch_forces(ctx, s, prec);
-  launch_control(ctx, s, 0);
-  // graph size: short for small systems (launch-bound), longer for large ones
+  launch_forces(ctx, s, prec);  // evaluation 0 and the set-up of iteration 1
+  // graph length: short for small systems (launch-bound), longer for large ones
   ctx->graph_k = ctx->n < 20000 ? 32 : 16;
   int* st = ctx->h_status;
   const int poll_bytes = 32;
   for (;;) {
-    // pipeline: two replays in flight, poll the older one
+    // two replays in flight; poll the older one
     hipGraphExec_t g;
     rc = graph_for(ctx, prec, &g);
     if (rc) return rc;
@@ -1406,32 +1482,18 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
     const int status = st[8 * (cur ^ 1)];
     const int pause = st[8 * (cur ^ 1) + 1];
     if (status != ST_PAUSED) break;
-    // ---- host work at a pause point (before the next update); small
-    // uploads go through pinned memory and are waited for
-    int* up = ctx->h_flags + 2;
-    up[0] = ST_RUNNING;
-    up[1] = 0;
-    if (pause & PAUSE_PRECISION) prec = 0;
-    if (pause & PAUSE_BIG_STEP) {
-      HIPCHK(hipMemcpyAsync(ctx->ctrl, up, 2 * sizeof(int), hipMemcpyHostToDevice, s));
-      launch_update(ctx, s);
+    if (pause & PAUSE_PRECISION) {  // before the next update: switch pair precision
+      prec = 0;
+      rc = resume(ctx, s);
+      if (rc) return rc;
+    }
+    if (pause & PAUSE_REBUILD) {  // after an update: new list, then this iteration's forces
       rc = rebuild(ctx);
       if (rc) return rc;
       ++rebuilds;
-      double* zero = ctx->h_zero;
-      *zero = 0.0;
-      HIPCHK(hipMemcpyAsync(&ctx->ctrl->disp, zero, sizeof(double), hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
+      rc = resume(ctx, s);
+      if (rc) return rc;
       launch_forces(ctx, s, prec);
-      launch_control(ctx, s, 0);
-    } else {
-      if (pause & PAUSE_REBUILD) {
-        rc = rebuild(ctx);
-        if (rc) return rc;
-        ++rebuilds;
-      }
-      HIPCHK(hipMemcpyAsync(ctx->ctrl, up, 2 * sizeof(int), hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
     }
   }
   HIPCHK(hipMemcpyAsync(ctx->h_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -1464,7 +1526,12 @@ int check_ctx(fire_ctx* ctx) {
   return FIRE_OK;
 }
 
-hipStream_t pick_stream(fire_ctx* ctx, void* stream) { return stream ? (hipStream_t)stream : ctx->stream; }
+// Device-pointer calls enqueue on the caller's stream as given (NULL is the
+// legacy default stream, as everywhere in HIP).
+hipStream_t pick_stream(fire_ctx* ctx, void* stream) {
+  (void)ctx;
+  return (hipStream_t)stream;
+}
 
 int validate_params(const fire_params* p) {
   if (!(p->dt_start > 0) || !(p->tmax > 0) || !(p->tmin >= 0) || !(p->dtgrow >= 1) || !(p->dtshrink > 0) ||
@@ -1505,9 +1572,9 @@ int dev_remove_mean(fire_ctx* ctx, hipStream_t s, double* a) {
 void launch_hvp(fire_ctx* ctx, hipStream_t s, const double* u, double* hu, double* pre) {
   const int n = ctx->n, nb = nblocks(n);
   if (ctx->pot.kind == FIRE_POT_GUPTA)
-    hipLaunchKernelGGL(k_gupta_hvp_pre, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n, ctx->ncap,
+    hipLaunchKernelGGL(k_gupta_hvp_pre, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, ctx->kcap,
                        ctx->ncap, ctx->box, ctx->pot, u, pre);
-  hipLaunchKernelGGL(k_hvp, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->nnbr, n, ctx->ncap, ctx->ncap,
+  hipLaunchKernelGGL(k_hvp, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, ctx->kcap, ctx->ncap,
                      ctx->box, ctx->pot, u, (const double*)pre, hu);
 }
 
@@ -1623,7 +1690,7 @@ void fire_finalize(fire_ctx* ctx) {
   drop_graphs(ctx);
   free_single(ctx);
   hipFree(ctx->nbr);
-  hipFree(ctx->nnbr);
+  hipFree(ctx->wcnt);
   hipFree(ctx->cell_count);
   hipFree(ctx->cell_start);
   hipFree(ctx->cell_cursor);
@@ -1893,6 +1960,21 @@ int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const f
   }
   b.resize(a.size() > 0 ? a.size() - 1 : 0);
   *lambda_min = tridiag_min_eig(a, b);
+  return FIRE_OK;
+}
+
+int fire_repeat_forces_dev(fire_ctx* ctx, int reps, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!ctx->have_list || ctx->n <= 0 || reps < 0) return set_err(ctx, FIRE_E_ARG, "no evaluated system");
+  hipStream_t s = pick_stream(ctx, stream);
+  // a running control record with no Verlet half kick, so the passes recompute
+  // forces and reductions only
+  ctrl_defaults(ctx, *ctx->h_ctrl, 0.0, 0, 1);
+  HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int prec = ctx->params.precision == FIRE_FP64 ? 0 : 1;
+  for (int r = 0; r < reps; ++r) launch_forces(ctx, s, prec);
   return FIRE_OK;
 }
 

@@ -17,8 +17,8 @@ enum RedField { R_E = 0, R_P = 1, R_F2 = 2, R_V2 = 3, R_FMAX2 = 4, R_VMAX2 = 5, 
 constexpr int ST_RUNNING = 0;
 constexpr int ST_PAUSED = 10;
 // ctrl->pause bits
-constexpr int PAUSE_REBUILD = 1;    // rebuild the list before the next update
-constexpr int PAUSE_BIG_STEP = 2;   // next update may exceed skin/2: update, rebuild, then evaluate
+constexpr int PAUSE_REBUILD = 1;    // an atom moved more than skin/2 in the last update:
+                                    // rebuild the list, then evaluate forces
 constexpr int PAUSE_PRECISION = 4;  // mixed mode: continue with FP64 pair terms
 // ctrl->error bits (set by kernels)
 constexpr int ERR_OVERLAP = 1;
@@ -45,17 +45,21 @@ struct PotDev {
 struct Ctrl {
   int status, pause, precision, error;  // precision: 0 FP64 pair terms, 1 FP32
   long long iter, evals;
+  int viol;            // set by the update when an atom left its skin
+  int eval_only;       // 1: the force pass only records E and the norms
+  unsigned int ticket; // blocks of the current force pass that are done
+  int pad0;
   // parameters
   double dt_start, dtmax, dtmin, dtgrow, dtshrink, alpha0, alphashrink, f2a;
-  double tol, switch_tol, skin_half;
+  double tol, switch_tol, skin_half2;
   long long max_steps, trace_cap, iter_low;
   int delaystep, vdfmax, halfstepback, initialdelay;
   int integrator, criterion, variant, mode;
   double natoms;
   // FIRE state
-  double dt, alpha, disp;
+  double dt, alpha;
   long long npos, nneg;
-  int branch, neg, mix_first, pad0;
+  int branch, neg, mix_first, pad1;
   double P_used;
   // coefficients of the next update
   double hsb, kick1, kick2, kick3, cv, cf, dtx;
