@@ -32,12 +32,13 @@ PEAK_FP64_TFLOPS = 78.6
 
 # Algorithmic cost of one force evaluation per atom (each in-range pair counted
 # once, FCC neighbour shells): LJ rc = 2.5 sigma -> 54 neighbours = 27 pairs of
-# ~30 flop; Gupta r_out = 5 A -> 42 neighbours = 21 pairs of ~125 flop (FP64,
-# two exponentials and a square root).  Bytes: positions read once, velocities
+# ~25 flop (separation 3, r^2 5, 1/r^2 1, r^-6 3, force factor 4, F_i and F_j
+# updates 6, plus the cutoff test); Gupta r_out = 5 A -> 42 neighbours = 21
+# pairs of ~125 flop (FP64, two exponentials and a square root).  Bytes: positions read once, velocities
 # read for P = F.v, forces written (3 x 8 B each); the EAM form adds F'(rho)
 # written and read (2 x 8 B).
 ALG = {
-    "lj": {"bytes": 72.0, "flops": 27.0 * 30.0, "kernel": "k_lj_force"},
+    "lj": {"bytes": 72.0, "flops": 27.0 * 25.0, "kernel": "k_lj_force"},
     "gupta": {"bytes": 88.0, "flops": 21.0 * 125.0, "kernel": "k_gupta_force"},
 }
 
@@ -182,7 +183,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": hbm_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": hbm_ach / PEAK_HBM_GBS}
-    roof.update({"traffic": traffic, "kernel": kname + "<double>", "ms_per_launch": kt,
+    roof.update({"traffic": traffic, "kernel": kname + "<double, false, false>", "ms_per_launch": kt,
                  "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops_launch,
                  "hbm_achieved_GBs": hbm_ach, "hbm_frac": hbm_ach / PEAK_HBM_GBS,
                  "arithmetic_intensity": ai, "ridge": ridge})

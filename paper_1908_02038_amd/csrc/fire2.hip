@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -80,19 +81,12 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * per + min(x, rem) + idx;
 }
 
-__device__ __forceinline__ void min_image(double& dx, double& dy, double& dz, const BoxDev& b) {
-  if (b.per[0]) dx -= b.L[0] * rint(dx * b.invL[0]);
-  if (b.per[1]) dy -= b.L[1] * rint(dy * b.invL[1]);
-  if (b.per[2]) dz -= b.L[2] * rint(dz * b.invL[2]);
-}
-
-// 1/x and 1/sqrt(x) from the hardware estimates plus two Newton steps.
+// 1/x and 1/sqrt(x) from the hardware estimates plus Newton steps (one step
+// for the reciprocal squares the estimate's relative error, which is far
+// below 1e-8, to round-off level).
 __device__ __forceinline__ double rcp_d(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
 }
 __device__ __forceinline__ double rsqrt_d(double x) {
   double y = __builtin_amdgcn_rsq(x);
@@ -112,24 +106,22 @@ __device__ __forceinline__ bool ctrl_running(const Ctrl* c) {
 
 // ----------------------------------------------------------- stage in/out
 
-// Caller AoS positions -> slot order (identity), zero v and F; slots n..ncap
-// get NaN positions (the neighbour-list padding target).
+// Caller AoS positions -> slot order (identity), zero v and F.
 __global__ void k_stage_in(const double* __restrict__ src, int n, int ncap, double4* __restrict__ pos,
                            double* __restrict__ vel, double* __restrict__ frc, int* __restrict__ id,
                            int* __restrict__ flags) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > ncap) return;
-  if (i >= n) {
-    const double qn = __builtin_nan("");
-    pos[i] = make_double4(qn, qn, qn, 0.0);
-    return;
-  }
+  if (i >= n) return;
   double x = src[3 * i], y = src[3 * i + 1], z = src[3 * i + 2];
   if (!isfinite(x) || !isfinite(y) || !isfinite(z)) atomicOr(flags, ERR_NONFINITE);
   pos[i] = make_double4(x, y, z, 0.0);
   vel[i] = vel[ncap + i] = vel[2 * ncap + i] = 0.0;
   frc[i] = frc[ncap + i] = frc[2 * ncap + i] = 0.0;
   id[i] = i;
+}
+
+__global__ void k_set_pos(double4* __restrict__ pos, int slot, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) pos[slot] = make_double4(v, v, v, 0.0);
 }
 
 // Sorted-order vector (3 planes) from a caller-order AoS vector.
@@ -175,13 +167,26 @@ __global__ void k_stage_out_pos(const double4* __restrict__ pos, int n, const in
 }
 
 // ------------------------------------------------------- cell-list build
+//
+// Periodic images are explicit: at every list build each atom within rcs of a
+// periodic face gets ghost copies (shifted by the box length) in an extra
+// layer of cells outside the box, so pair loops never take a minimum image.
+// All atoms (real and ghost) are counting-sorted by cell; cells inside the box
+// are numbered first (in Morton order), so real atoms occupy slots [0, n) and
+// ghosts follow.  The update and density kernels refresh each atom's ghosts.
 
 struct Grid {
-  int n[3];
+  int n[3];              // cells per axis, including one ghost layer on each side of periodic axes
   int ncell;
-  double lo[3], inv[3];
-  int lo_off[3], hi_off[3];  // stencil offsets per axis
+  double lo[3], inv[3];  // origin of the (extended) grid and 1 / cell edge
+  int in_lo[3], in_hi[3];  // cell coordinates inside the box (real atoms)
 };
+
+// Shift of a ghost: two bits per axis (1: +L, 2: -L).
+__device__ __forceinline__ double ghost_shift(int code, int d, const BoxDev& b) {
+  const int c = (code >> (2 * d)) & 3;
+  return c == 1 ? b.L[d] : (c == 2 ? -b.L[d] : 0.0);
+}
 
 // Bounding box partials (min x,y,z then max x,y,z) per block.
 __global__ void k_bbox(const double4* __restrict__ pos, int n, double* __restrict__ part) {
@@ -215,13 +220,31 @@ __device__ __forceinline__ int cell_coord(double x, const Grid& g, int d) {
   return min(max(c, 0), g.n[d] - 1);
 }
 
-// Wrap periodic coordinates into the box and count atoms per cell.
-__global__ void k_cell_count(double4* __restrict__ pos, int n, BoxDev box, Grid g, int* __restrict__ cell_of,
-                             int* __restrict__ count) {
+// Cell of a real atom: always inside the box (rounding at a face cannot push
+// it into a ghost layer).
+__device__ __forceinline__ int real_cell_coord(double x, const Grid& g, int d) {
+  int c = (int)floor((x - g.lo[d]) * g.inv[d]);
+  return min(max(c, g.in_lo[d]), g.in_hi[d]);
+}
+
+// Cell of a ghost: in the ghost layer on every shifted axis, inside the box
+// on the others.
+__device__ __forceinline__ int ghost_cell_coord(double x, int code, const Grid& g, int d) {
+  const int c = (code >> (2 * d)) & 3;
+  if (c == 1) return g.n[d] - 1;
+  if (c == 2) return 0;
+  return real_cell_coord(x, g, d);
+}
+
+// Wrap the real atoms into the box on periodic axes and count their ghosts:
+// an atom within rcs of the low face has an image at +L, within rcs of the
+// high face one at -L; every non-empty combination over axes is one ghost.
+__global__ void k_ghost_count(double4* __restrict__ pos, int n, BoxDev box, double rcs, int* __restrict__ gcount) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double4 p = pos[i];
   double r[3] = {p.x, p.y, p.z};
+  int choices = 1;
 #pragma unroll
   for (int d = 0; d < 3; ++d)
     if (box.per[d]) {
@@ -230,10 +253,62 @@ __global__ void k_cell_count(double4* __restrict__ pos, int n, BoxDev box, Grid 
       if (t >= box.L[d]) t -= box.L[d];
       if (t < 0.0) t = 0.0;
       r[d] = box.lo[d] + t;
+      if (t < rcs || t >= box.L[d] - rcs) choices *= 2;
     }
   pos[i] = make_double4(r[0], r[1], r[2], p.w);
-  int c = cell_coord(r[0], g, 0) + g.n[0] * (cell_coord(r[1], g, 1) + g.n[1] * cell_coord(r[2], g, 2));
+  gcount[i] = choices - 1;
+}
+
+// Ghost positions (slots n + goff[i] ...) with their source slot and shift code.
+__global__ void k_ghost_fill(double4* __restrict__ pos, int n, BoxDev box, double rcs, const int* __restrict__ goff,
+                             int* __restrict__ gsrc, int* __restrict__ gcode) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = pos[i];
+  const double r[3] = {p.x, p.y, p.z};
+  int opt[3] = {0, 0, 0};  // shift code per axis, 0 if none
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (box.per[d]) {
+      const double t = r[d] - box.lo[d];
+      if (t < rcs) opt[d] = 1;
+      else if (t >= box.L[d] - rcs) opt[d] = 2;
+    }
+  int k = 0;
+  for (int m = 1; m < 8; ++m) {
+    if (((m & 1) && !opt[0]) || ((m & 2) && !opt[1]) || ((m & 4) && !opt[2])) continue;
+    const int code = ((m & 1) ? opt[0] : 0) | (((m & 2) ? opt[1] : 0) << 2) | (((m & 4) ? opt[2] : 0) << 4);
+    const int g = goff[i] + k++;
+    pos[n + g] = make_double4(r[0] + ghost_shift(code, 0, box), r[1] + ghost_shift(code, 1, box),
+                              r[2] + ghost_shift(code, 2, box), p.w);
+    gsrc[g] = i;
+    gcode[g] = code;
+  }
+}
+
+// Cell of every slot (real and ghost) and per-cell counts.  Ordering key
+// inside a cell: caller index (times 8, plus the ghost's combination).
+__global__ void k_cell_count(const double4* __restrict__ pos, int n, int nt, Grid g,
+                             const int* __restrict__ cell_rank, const int* __restrict__ id,
+                             const int* __restrict__ gsrc, const int* __restrict__ gcode,
+                             int* __restrict__ cell_of, long long* __restrict__ key, int* __restrict__ count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const double4 p = pos[i];
+  int cc[3];
+  if (i < n) {
+    cc[0] = real_cell_coord(p.x, g, 0);
+    cc[1] = real_cell_coord(p.y, g, 1);
+    cc[2] = real_cell_coord(p.z, g, 2);
+  } else {
+    const int code = gcode[i - n];
+    cc[0] = ghost_cell_coord(p.x, code, g, 0);
+    cc[1] = ghost_cell_coord(p.y, code, g, 1);
+    cc[2] = ghost_cell_coord(p.z, code, g, 2);
+  }
+  const int c = cell_rank[cc[0] + g.n[0] * (cc[1] + g.n[1] * cc[2])];
   cell_of[i] = c;
+  key[i] = i < n ? 8LL * id[i] : 8LL * id[gsrc[i - n]] + 1 + gcode[i - n];
   atomicAdd(&count[c], 1);
 }
 
@@ -270,34 +345,61 @@ __global__ void k_cell_fill(const int* __restrict__ cell_of, int n, const int* _
   order[start[c] + atomicAdd(&cursor[c], 1)] = i;
 }
 
-// Deterministic order inside each cell: by caller atom index.  One thread per
-// slot ranks its atom among the cell's members.
+// Deterministic order inside each cell: by key.  One thread per slot ranks
+// its atom among the cell's members.
 __global__ void k_cell_rank(const int* __restrict__ cell_of, const int* __restrict__ start,
-                            const int* __restrict__ bucket, int n, const int* __restrict__ id,
+                            const int* __restrict__ bucket, int nt, const long long* __restrict__ key,
                             int* __restrict__ order) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const int a = bucket[s], c = cell_of[a], key = id[a];
+  if (s >= nt) return;
+  const int a = bucket[s], c = cell_of[a];
+  const long long k = key[a];
   const int b = start[c], e = start[c + 1];
   int rank = 0;
-  for (int t = b; t < e; ++t) rank += id[bucket[t]] < key;
+  for (int t = b; t < e; ++t) rank += key[bucket[t]] < k;
   order[b + rank] = a;
 }
 
-__global__ void k_permute(const int* __restrict__ order, int n, int ncap, const double4* __restrict__ pos,
+// Gather every slot into its sorted place.  Real atoms (old slots < n) land
+// in new slots < n and carry v, F, id; ghosts carry their source and shift.
+__global__ void k_permute(const int* __restrict__ order, int n, int nt, int ncap, const double4* __restrict__ pos,
                           const double* __restrict__ vel, const double* __restrict__ frc,
-                          const int* __restrict__ id, double4* __restrict__ pos2, double* __restrict__ vel2,
-                          double* __restrict__ frc2, int* __restrict__ id2) {
+                          const int* __restrict__ id, const int* __restrict__ cell_of,
+                          const int* __restrict__ gsrc, const int* __restrict__ gcode,
+                          double4* __restrict__ pos2, double* __restrict__ vel2, double* __restrict__ frc2,
+                          int* __restrict__ id2, int* __restrict__ srank, int* __restrict__ new_of_old,
+                          int* __restrict__ gsrc2, int* __restrict__ gcode2) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  int o = order[s];
+  if (s >= nt) return;
+  const int o = order[s];
   pos2[s] = pos[o];
-  id2[s] = id[o];
+  srank[s] = cell_of[o];
+  if (s < n) {
+    id2[s] = id[o];
+    new_of_old[o] = s;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    vel2[d * ncap + s] = vel[d * ncap + o];
-    frc2[d * ncap + s] = frc[d * ncap + o];
+    for (int d = 0; d < 3; ++d) {
+      vel2[d * ncap + s] = vel[d * ncap + o];
+      frc2[d * ncap + s] = frc[d * ncap + o];
+    }
+  } else {
+    gsrc2[s - n] = gsrc[o - n];  // still an old real slot; mapped by k_ghost_link
+    gcode2[s - n] = gcode[o - n];
   }
+}
+
+// Link ghosts to the new slots of their sources: real_of[] (slot -> real
+// slot, identity for real atoms) and the per-atom ghost lists (at most 7).
+__global__ void k_ghost_link(int n, int ng, const int* __restrict__ new_of_old, int* __restrict__ gsrc,
+                             int* __restrict__ real_of, int* __restrict__ gcnt, int* __restrict__ glist) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) real_of[s] = s;
+  if (s >= ng) return;
+  const int src = new_of_old[gsrc[s]];
+  gsrc[s] = src;
+  real_of[n + s] = src;
+  const int k = atomicAdd(&gcnt[src], 1);
+  glist[8 * src + k] = n + s;
 }
 
 __device__ __forceinline__ int wave_max_i(int v) {
@@ -306,62 +408,217 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-// Full neighbour list of every atom (all atoms within rcs, cells in fixed
-// order, atoms of a cell in slot order), stored per wave of 64 atoms as
-// nbr[(w * kcap + k) * 64 + lane].  Each wave's lists are padded to a common
-// length (a multiple of 4, kept in wcnt[w]) with the index of a dummy slot
-// whose position is NaN, so the force loops run a wave-uniform trip count and
-// the padding fails every cutoff test.  The grid covers every wave of the
-// allocation.  flags[0] |= overlap, flags[1] = max count.
-__global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict__ pos, int n, BoxDev box, Grid g,
+// Neighbour k of lane `lane` of wave w: groups of four consecutive neighbours
+// of one atom are adjacent, so a lane fetches a group with one vector load and
+// a wave's group loads are contiguous.
+__device__ __forceinline__ size_t lidx(int w, int k, int lane, int kcap) {
+  return (((size_t)w * (kcap >> 2) + (k >> 2)) * 64 + lane) * 4 + (k & 3);
+}
+
+// Full neighbour list of every real atom: all slots (real or ghost) within
+// rcs, in ascending slot order, stored per wave of 64 atoms at
+// lidx(w, k, lane).  Each wave's lists are padded to a common length (a
+// multiple of 4, kept in wcnt[w]) with a dummy slot far outside the system,
+// so the force loops run a wave-uniform trip count and the padding fails
+// every cutoff test.  The grid covers every wave of the allocation.
+// flags[0] |= overlap, flags[1] = max count.
+__global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict__ pos, int n, Grid g,
+                                                      const int* __restrict__ cell_rank,
                                                       const int* __restrict__ start, double rcs2, int kcap,
                                                       int dummy, int* __restrict__ nbr, int* __restrict__ wcnt,
                                                       int* __restrict__ flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = i >> 6, lane = threadIdx.x & 63;
-  int* lst = nbr + (size_t)w * kcap * 64 + lane;
   int cnt = 0;
   bool overlap = false;
   if (i < n) {
     const double4 pi = pos[i];
-    const int c[3] = {cell_coord(pi.x, g, 0), cell_coord(pi.y, g, 1), cell_coord(pi.z, g, 2)};
-    for (int oz = g.lo_off[2]; oz <= g.hi_off[2]; ++oz) {
-      int cz = c[2] + oz;
-      if (box.per[2]) cz = (cz + g.n[2]) % g.n[2];
-      else if (cz < 0 || cz >= g.n[2]) continue;
-      for (int oy = g.lo_off[1]; oy <= g.hi_off[1]; ++oy) {
-        int cy = c[1] + oy;
-        if (box.per[1]) cy = (cy + g.n[1]) % g.n[1];
-        else if (cy < 0 || cy >= g.n[1]) continue;
-        for (int ox = g.lo_off[0]; ox <= g.hi_off[0]; ++ox) {
-          int cx = c[0] + ox;
-          if (box.per[0]) cx = (cx + g.n[0]) % g.n[0];
-          else if (cx < 0 || cx >= g.n[0]) continue;
-          const int cell = cx + g.n[0] * (cy + g.n[1] * cz);
-          for (int j = start[cell], e = start[cell + 1]; j < e; ++j) {
-            if (j == i) continue;
-            const double4 pj = pos[j];
-            double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-            min_image(dx, dy, dz, box);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 == 0.0) overlap = true;
-            if (r2 < rcs2) {
-              if (cnt < kcap) lst[(size_t)cnt * 64] = j;
-              ++cnt;
-            }
+    const int c[3] = {real_cell_coord(pi.x, g, 0), real_cell_coord(pi.y, g, 1), real_cell_coord(pi.z, g, 2)};
+    // stencil cells in ascending rank, so each list comes out sorted by slot:
+    // lanes of a wave then read nearby (or identical) neighbours at each step
+    int cells[27];
+    int nc = 0;
+    for (int oz = -1; oz <= 1; ++oz) {
+      const int cz = c[2] + oz;
+      if (cz < 0 || cz >= g.n[2]) continue;
+      for (int oy = -1; oy <= 1; ++oy) {
+        const int cy = c[1] + oy;
+        if (cy < 0 || cy >= g.n[1]) continue;
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int cx = c[0] + ox;
+          if (cx < 0 || cx >= g.n[0]) continue;
+          const int r = cell_rank[cx + g.n[0] * (cy + g.n[1] * cz)];
+          int k = nc++;
+          while (k > 0 && cells[k - 1] > r) {
+            cells[k] = cells[k - 1];
+            --k;
           }
+          cells[k] = r;
+        }
+      }
+    }
+    for (int q = 0; q < nc; ++q) {
+      const int cell = cells[q];
+      for (int j = start[cell], e = start[cell + 1]; j < e; ++j) {
+        if (j == i) continue;
+        const double4 pj = pos[j];
+        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 == 0.0) overlap = true;
+        if (r2 < rcs2) {
+          if (cnt < kcap) nbr[lidx(w, cnt, lane, kcap)] = j;
+          ++cnt;
         }
       }
     }
   }
   const int m = wave_max_i(cnt);
   const int kw = min((m + 3) & ~3, kcap);
-  for (int k = cnt; k < kw; ++k) lst[(size_t)k * 64] = dummy;
+  for (int k = cnt; k < kw; ++k) nbr[lidx(w, k, lane, kcap)] = dummy;
   if (lane == 0) {
     wcnt[w] = kw;
     atomicMax(&flags[1], m);
   }
   if (overlap) atomicOr(&flags[0], ERR_OVERLAP);
+}
+
+// Per-tile halo for the LDS-staged passes.  Tile b is the 256 slots of block
+// b; its halo is every atom of every cell in the stencil of a cell the tile
+// occupies (a superset of the tile's neighbours), as the sorted list of those
+// cells' slot runs.  The kernel writes the halo's slot list (hslot, at most
+// hcap entries), its size (tile_h), and rewrites the tile's neighbour lists
+// as 16-bit halo indices (nbr16; padding -> index H, an LDS slot set to a far
+// position).  A halo that does not fit sets flags[3]; flags[2] = max H.
+constexpr int kCandMax = 4096;
+__global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ srank, const int* __restrict__ start,
+                                                      const int* __restrict__ rank_cell,
+                                                      const int* __restrict__ cell_rank, int n, Grid g,
+                                                      const int* __restrict__ nbr, const int* __restrict__ wcnt,
+                                                      int kcap, int hcap, int dummy, int* __restrict__ tile_h,
+                                                      int* __restrict__ hslot, unsigned short* __restrict__ nbr16,
+                                                      int* __restrict__ flags) {
+  __shared__ int cand[kCandMax];
+  __shared__ int hoff[kCandMax + 1];
+  __shared__ int dcell[kBlock];
+  __shared__ int s_ndc, s_nu, s_H, s_bad;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int s0 = b * kBlock;
+  if (s0 >= n) {
+    if (t == 0) tile_h[b] = 0;
+    return;
+  }
+  const int s1 = min(s0 + kBlock, n);
+  if (t == 0) {  // distinct occupied cells (slots are sorted by cell rank)
+    int nd = 0;
+    for (int s = s0; s < s1; ++s)
+      if (s == s0 || srank[s] != srank[s - 1]) dcell[nd++] = srank[s];
+    s_ndc = nd;
+    s_bad = nd * 27 > kCandMax;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (t == 0) {
+      tile_h[b] = -1;
+      atomicOr(&flags[3], 1);
+    }
+    return;
+  }
+  const int ncand = s_ndc * 27;
+  int P = 1;
+  while (P < ncand) P <<= 1;
+  for (int q = t; q < P; q += blockDim.x) {
+    int v = INT_MAX;
+    if (q < ncand) {
+      const int lin = rank_cell[dcell[q / 27]], o = q % 27;
+      const int c3[3] = {lin % g.n[0] + o % 3 - 1, (lin / g.n[0]) % g.n[1] + (o / 3) % 3 - 1,
+                         lin / (g.n[0] * g.n[1]) + o / 9 - 1};
+      bool ok = true;
+      for (int d = 0; d < 3; ++d)
+        if (c3[d] < 0 || c3[d] >= g.n[d]) ok = false;
+      if (ok) v = cell_rank[c3[0] + g.n[0] * (c3[1] + g.n[1] * c3[2])];
+    }
+    cand[q] = v;
+  }
+  __syncthreads();
+  // bitonic sort of cand[0..P)
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = t; q < P; q += blockDim.x) {
+        const int p = q ^ j;
+        if (p > q) {
+          const int a = cand[q], c = cand[p];
+          const bool up = (q & k) == 0;
+          if ((a > c) == up) {
+            cand[q] = c;
+            cand[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  if (t == 0) {  // unique cells and their offsets in the halo
+    int nu = 0, H = 0, prev = -1;
+    for (int q = 0; q < P; ++q) {
+      const int r = cand[q];
+      if (r == INT_MAX) break;
+      if (r == prev) continue;
+      prev = r;
+      cand[nu] = r;
+      hoff[nu] = H;
+      H += start[r + 1] - start[r];
+      ++nu;
+    }
+    hoff[nu] = H;
+    s_nu = nu;
+    s_H = H;
+  }
+  __syncthreads();
+  const int nu = s_nu, H = s_H;
+  if (H + 1 > hcap) {
+    if (t == 0) {
+      tile_h[b] = -1;
+      atomicOr(&flags[3], 1);
+      atomicMax(&flags[2], H);
+    }
+    return;
+  }
+  auto find = [&](int r) {  // index of cell rank r in cand[0..nu)
+    int lo = 0, hi = nu - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cand[mid] < r) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  int* hs = hslot + (size_t)b * hcap;
+  for (int q = t; q < H; q += blockDim.x) {
+    int lo = 0, hi = nu - 1;  // last h with hoff[h] <= q
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (hoff[mid] <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    hs[q] = start[cand[lo]] + (q - hoff[lo]);
+  }
+  const int i = s0 + t;
+  const int w = i >> 6, lane = t & 63;
+  const int kw = wcnt[w];
+  for (int k = 0; k < kw; ++k) {
+    const int j = nbr[lidx(w, k, lane, kcap)];
+    int l = H;
+    if (j != dummy) {
+      const int r = srank[j];
+      const int h = find(r);
+      if (cand[h] != r) atomicOr(&flags[3], 2);  // not in the halo: fall back to global gathers
+      l = hoff[h] + (j - start[r]);
+    }
+    nbr16[lidx(w, k, lane, kcap)] = (unsigned short)l;
+  }
+  if (t == 0) {
+    tile_h[b] = H;
+    atomicMax(&flags[2], H);
+  }
 }
 
 // ----------------------------------------------------------- FIRE update
@@ -379,8 +636,9 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
 // rebuild.
 __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, double* __restrict__ vel,
                                                    const double* __restrict__ frc,
-                                                   const double4* __restrict__ xref, int n, int ncap,
-                                                   Ctrl* __restrict__ ctrl) {
+                                                   const double4* __restrict__ xref, const int* __restrict__ gcnt,
+                                                   const int* __restrict__ glist, const int* __restrict__ gcode,
+                                                   BoxDev box, int n, int ncap, Ctrl* __restrict__ ctrl) {
   if (!ctrl_running(ctrl)) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -410,6 +668,11 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
   vel[i] = v[0];
   vel[ncap + i] = v[1];
   vel[2 * ncap + i] = v[2];
+  for (int k = 0, gc = gcnt[i]; k < gc; ++k) {  // periodic images move along
+    const int g = glist[8 * i + k], code = gcode[g - n];
+    pos[g] = make_double4(x[0] + ghost_shift(code, 0, box), x[1] + ghost_shift(code, 1, box),
+                          x[2] + ghost_shift(code, 2, box), p.w);
+  }
   const double4 r = xref[i];
   const double ex = x[0] - r.x, ey = x[1] - r.y, ez = x[2] - r.z;
   if (ex * ex + ey * ey + ez * ez > ctrl->skin_half2) atomicOr(&ctrl->viol, 1);
@@ -632,55 +895,133 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
 
 // ------------------------------------------------------------ pair kernels
 
+// Tile data of the LDS-staged passes.
+struct Tiles {
+  const int* tile_h;           // halo size per tile
+  const int* hslot;            // halo slot lists, hcap per tile
+  const unsigned short* nbr16; // neighbour lists as halo indices
+  int hcap;
+};
+
+extern __shared__ __align__(16) unsigned char dyn_lds[];
+
+// Position of the list padding slot: far outside any system, finite in FP32.
+constexpr double kFar = 1.0e20;
+
+// Copy tile b's halo positions into LDS (plus the far entry for the padding);
+// four entries per thread and round, so their loads are in flight together.
+__device__ __forceinline__ const double4* stage_halo(const double4* __restrict__ pos, const Tiles& tl, int b) {
+  double4* h = reinterpret_cast<double4*>(dyn_lds);
+  const int H = tl.tile_h[b];
+  const int* hs = tl.hslot + (size_t)b * tl.hcap;
+  const int step = blockDim.x;
+  for (int q0 = threadIdx.x; q0 < H; q0 += 4 * step) {
+    int idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) idx[u] = (q0 + u * step < H) ? hs[q0 + u * step] : -1;
+    double4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (idx[u] >= 0) v[u] = pos[idx[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (idx[u] >= 0) h[q0 + u * step] = v[u];
+  }
+  if (threadIdx.x == 0) h[H] = make_double4(kFar, kFar, kFar, 0.0);
+  __syncthreads();
+  return h;
+}
+
 // Neighbour loop shared by the pair kernels: wave-uniform trip count, four
-// neighbours per step (index loads, then position gathers, then pair terms).
-template <typename F>
-__device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, const int* __restrict__ nbr,
+// neighbours per step, software-pipelined: index groups are fetched two steps
+// ahead (one 8- or 16-byte load per lane), and for global gathers the
+// positions one step ahead.  LDS: positions from the tile's halo in LDS by
+// 16-bit index; otherwise gathered from global memory by slot index.
+template <bool LDS, typename F>
+__device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, const double4* __restrict__ halo,
+                                               const int* __restrict__ nbr, const Tiles& tl,
                                                const int* __restrict__ wcnt, int kcap, int i, F&& pair) {
   const int w = i >> 6, lane = threadIdx.x & 63;
-  const int kw = __builtin_amdgcn_readfirstlane(wcnt[w]);
-  const int* lst = nbr + (size_t)w * kcap * 64 + lane;
-  for (int k = 0; k < kw; k += 4) {
-    const int j0 = lst[(size_t)(k + 0) * 64], j1 = lst[(size_t)(k + 1) * 64];
-    const int j2 = lst[(size_t)(k + 2) * 64], j3 = lst[(size_t)(k + 3) * 64];
-    const double4 p0 = pos[j0], p1 = pos[j1], p2 = pos[j2], p3 = pos[j3];
-    pair(p0);
-    pair(p1);
-    pair(p2);
-    pair(p3);
+  const int ng = __builtin_amdgcn_readfirstlane(wcnt[w]) >> 2;
+  const size_t base = (size_t)w * (kcap >> 2) * 64 + lane;
+  if constexpr (LDS) {
+    const ushort4* l4 = reinterpret_cast<const ushort4*>(tl.nbr16) + base;
+    ushort4 a = make_ushort4(0, 0, 0, 0), b = a;
+    if (ng > 0) a = l4[0];
+    if (ng > 1) b = l4[64];
+    for (int g = 0; g < ng; ++g) {
+      const ushort4 c = a;
+      a = b;
+      if (g + 2 < ng) b = l4[(size_t)(g + 2) * 64];
+      const double4 p0 = halo[c.x], p1 = halo[c.y], p2 = halo[c.z], p3 = halo[c.w];
+      pair(p0);
+      pair(p1);
+      pair(p2);
+      pair(p3);
+    }
+  } else {
+    const int4* l4 = reinterpret_cast<const int4*>(nbr) + base;
+    int4 a = make_int4(0, 0, 0, 0), b = a;
+    double4 q0{}, q1{}, q2{}, q3{};
+    if (ng > 0) {
+      a = l4[0];
+      q0 = pos[a.x];
+      q1 = pos[a.y];
+      q2 = pos[a.z];
+      q3 = pos[a.w];
+    }
+    if (ng > 1) a = l4[64];
+    if (ng > 2) b = l4[128];
+    for (int g = 0; g < ng; ++g) {
+      const double4 p0 = q0, p1 = q1, p2 = q2, p3 = q3;
+      if (g + 1 < ng) {
+        q0 = pos[a.x];
+        q1 = pos[a.y];
+        q2 = pos[a.z];
+        q3 = pos[a.w];
+      }
+      a = b;
+      if (g + 3 < ng) b = l4[(size_t)(g + 3) * 64];
+      pair(p0);
+      pair(p1);
+      pair(p2);
+      pair(p3);
+    }
   }
 }
 
 // Energy-shifted LJ.  Separations and the r^2 < rc^2 test in FP64; the pair
 // terms and per-atom accumulation in T (double, or float for the mixed path).
-template <typename T>
+// WE: accumulate the energy (the FIRE logic itself needs only forces).
+template <typename T, bool LDS, bool WE>
 __global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                     const int* __restrict__ wcnt, int n, int kcap, int ncap,
-                                                     BoxDev box, PotDev pot, double* __restrict__ frc,
+                                                     Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
+                                                     int ncap, PotDev pot, double* __restrict__ frc,
                                                      double* __restrict__ vel, double* __restrict__ part,
                                                      Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
   if (!pass_gate(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
+  const double4* halo = LDS ? stage_halo(pos, tl, b) : nullptr;
   const int i = b * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   T ax = 0, ay = 0, az = 0, ae = 0;
-  const double4 pi = pos[i];  // slots n..ncap hold NaN
+  const double4 pi = pos[i];
   const T eps24 = (T)(24.0 * pot.eps), eps4 = (T)(4.0 * pot.eps), sig2 = (T)pot.sig2, sh = (T)pot.shift;
-  for_neighbours(pos, nbr, wcnt, kcap, i, [&](const double4& pj) {
-    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-    min_image(dx, dy, dz, box);
+  for_neighbours<LDS>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
+    const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < pot.rc2) {
-      T ir2;
-      if constexpr (sizeof(T) == 8) ir2 = rcp_d(r2);
-      else ir2 = rcp_f((float)r2);
-      const T s2 = sig2 * ir2, s6 = s2 * s2 * s2;
-      const T fr = eps24 * s6 * ((T)2 * s6 - (T)1) * ir2;
-      ax += fr * (T)dx;
-      ay += fr * (T)dy;
-      az += fr * (T)dz;
-      ae += (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh);
-    }
+    // branch-free: out-of-range lanes (including the far padding) evaluate at
+    // r = 1 and get a zero weight, so the pairs of a step interleave
+    const bool in = r2 < pot.rc2;
+    T ir2;
+    if constexpr (sizeof(T) == 8) ir2 = rcp_d(in ? r2 : 1.0);
+    else ir2 = rcp_f(in ? (float)r2 : 1.0f);
+    const T s2 = sig2 * ir2, s6 = s2 * s2 * s2;
+    const T fr = in ? eps24 * s6 * ((T)2 * s6 - (T)1) * ir2 : (T)0;
+    ax += fr * (T)dx;
+    ay += fr * (T)dy;
+    az += fr * (T)dz;
+    if constexpr (WE) ae += in ? (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh) : (T)0;
   });
   force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, nullptr, b, ctrl,
                  trace);
@@ -688,30 +1029,31 @@ __global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__
 
 // Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
 // F'(rho_i) = -xi / (2 sqrt(rho_i)) in pos[i].w and sums F(rho_i) per block.
-template <typename T>
+template <typename T, bool LDS>
 __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                          const int* __restrict__ wcnt, int n, int kcap,
-                                                          BoxDev box, PotDev pot, double* __restrict__ part_emb,
-                                                          Ctrl* __restrict__ ctrl) {
+                                                          Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
+                                                          PotDev pot, const int* __restrict__ gcnt,
+                                                          const int* __restrict__ glist,
+                                                          double* __restrict__ part_emb, Ctrl* __restrict__ ctrl) {
   if (!pass_gate(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
+  const double4* halo = LDS ? stage_halo(pos, tl, b) : nullptr;
   const int i = b * blockDim.x + threadIdx.x;
   double emb = 0.0;
   const double4 pi = pos[i];
   const T qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in, inv_w = (T)pot.inv_w;
   T rho = 0;
-  for_neighbours(pos, nbr, wcnt, kcap, i, [&](const double4& pj) {
-    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-    min_image(dx, dy, dz, box);
+  for_neighbours<LDS>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
+    const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < pot.rc2) {
-      T r;
-      if constexpr (sizeof(T) == 8) r = sqrt(r2);
-      else r = sqrtf((float)r2);
-      const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
-      const T S = (1 - s) * (1 - s) * (1 + 2 * s);
-      rho += exp(-qr0 * (r - r0)) * S;
-    }
+    const bool in = r2 < pot.rc2;
+    T r;
+    if constexpr (sizeof(T) == 8) r = sqrt(in ? r2 : 1.0);
+    else r = sqrtf(in ? (float)r2 : 1.0f);
+    const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
+    const T S = (1 - s) * (1 - s) * (1 + 2 * s);
+    const T v = exp(-qr0 * (r - r0)) * S;
+    rho += in ? v : (T)0;
   });
   if (i < n) {
     double fp = 0.0;
@@ -721,6 +1063,7 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
       emb = -pot.xi * sq;
     }
     pos[i].w = fp;
+    for (int k = 0, gc = gcnt[i]; k < gc; ++k) pos[glist[8 * i + k]].w = fp;
   }
   double r[1] = {emb};
   block_reduce<1, 0>(r);
@@ -729,44 +1072,45 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
 
 // Gupta force pass: F_i = -sum_j [c phi_t'(r) + (F'_i + F'_j) rho_t'(r)] d/r,
 // e_i = w_e sum_j phi_t(r).
-template <typename T>
+template <typename T, bool LDS, bool WE>
 __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                        const int* __restrict__ wcnt, int n, int kcap, int ncap,
-                                                        BoxDev box, PotDev pot, double* __restrict__ frc,
+                                                        Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
+                                                        int ncap, PotDev pot, double* __restrict__ frc,
                                                         double* __restrict__ vel, double* __restrict__ part,
                                                         const double* __restrict__ part_emb,
                                                         Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
   if (!pass_gate(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
+  const double4* halo = LDS ? stage_halo(pos, tl, b) : nullptr;
   const int i = b * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   T ax = 0, ay = 0, az = 0, ae = 0;
   const double4 pi = pos[i];
   const T A = (T)pot.A, pr0 = (T)pot.pr0, qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in,
           inv_w = (T)pot.inv_w, cpair = (T)pot.cpair, epair = (T)pot.epair, fpi = (T)pi.w;
-  for_neighbours(pos, nbr, wcnt, kcap, i, [&](const double4& pj) {
-    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-    min_image(dx, dy, dz, box);
+  for_neighbours<LDS>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
+    const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < pot.rc2) {
-      T ir;
-      if constexpr (sizeof(T) == 8) ir = rsqrt_d(r2);
-      else ir = rsqrt_f((float)r2);
-      const T r = (T)r2 * ir;
-      const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
-      const T S = (1 - s) * (1 - s) * (1 + 2 * s);
-      const T dS = (T)(-6) * s * (1 - s) * inv_w;
-      const T ph = A * exp(-pr0 * (r - r0));
-      const T rh = exp(-qr0 * (r - r0));
-      const T dph = ph * (dS - pr0 * S);
-      const T drh = rh * (dS - qr0 * S);
-      const T dEdr = cpair * dph + (fpi + (T)pj.w) * drh;
-      const T fr = -dEdr * ir;
-      ax += fr * (T)dx;
-      ay += fr * (T)dy;
-      az += fr * (T)dz;
-      ae += epair * ph * S;
-    }
+    const bool in = r2 < pot.rc2;
+    const double r2c = in ? r2 : 1.0;
+    T ir;
+    if constexpr (sizeof(T) == 8) ir = rsqrt_d(r2c);
+    else ir = rsqrt_f((float)r2c);
+    const T r = (T)r2c * ir;
+    const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
+    const T S = (1 - s) * (1 - s) * (1 + 2 * s);
+    const T dS = (T)(-6) * s * (1 - s) * inv_w;
+    const T ph = A * exp(-pr0 * (r - r0));
+    const T rh = exp(-qr0 * (r - r0));
+    const T dph = ph * (dS - pr0 * S);
+    const T drh = rh * (dS - qr0 * S);
+    const T fpj = in ? (T)pj.w : (T)0;
+    const T dEdr = cpair * dph + (fpi + fpj) * drh;
+    const T fr = in ? -dEdr * ir : (T)0;
+    ax += fr * (T)dx;
+    ay += fr * (T)dy;
+    az += fr * (T)dz;
+    if constexpr (WE) ae += in ? epair * ph * S : (T)0;
   });
   force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, part_emb, b, ctrl,
                  trace);
@@ -801,15 +1145,16 @@ __device__ __forceinline__ void for_neighbour_index(const int* __restrict__ nbr,
                                                     int kcap, int i, F&& fn) {
   const int w = i >> 6, lane = threadIdx.x & 63;
   const int kw = wcnt[w];
-  const int* lst = nbr + (size_t)w * kcap * 64 + lane;
-  for (int k = 0; k < kw; ++k) fn(lst[(size_t)k * 64]);
+  for (int k = 0; k < kw; ++k) fn(nbr[lidx(w, k, lane, kcap)]);
 }
 
 // Gupta HVP prologue: rho_i, F'_i, F''_i and s_i = sum_j rho'(r) dh.(u_i - u_j).
+// Per-atom vectors are indexed by real slot (real_of maps ghosts to sources).
 __global__ __launch_bounds__(kBlock) void k_gupta_hvp_pre(const double4* __restrict__ pos,
                                                           const int* __restrict__ nbr, const int* __restrict__ wcnt,
-                                                          int n, int kcap, int ncap, BoxDev box, PotDev pot,
-                                                          const double* __restrict__ u, double* __restrict__ aux) {
+                                                          const int* __restrict__ real_of, int n, int kcap, int ncap,
+                                                          PotDev pot, const double* __restrict__ u,
+                                                          double* __restrict__ aux) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 pi = pos[i];
@@ -817,10 +1162,10 @@ __global__ __launch_bounds__(kBlock) void k_gupta_hvp_pre(const double4* __restr
   double rho = 0.0, s = 0.0;
   for_neighbour_index(nbr, wcnt, kcap, i, [&](int j) {
     const double4 pj = pos[j];
-    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-    min_image(dx, dy, dz, box);
+    const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < pot.rc2) {
+      j = real_of[j];
       const double r = sqrt(r2), ir = 1.0 / r;
       const double t = fmin(fmax((r - pot.r_in) * pot.inv_w, 0.0), 1.0);
       const double S = (1 - t) * (1 - t) * (1 + 2 * t), dS = -6.0 * t * (1 - t) * pot.inv_w;
@@ -845,8 +1190,8 @@ __global__ __launch_bounds__(kBlock) void k_gupta_hvp_pre(const double4* __restr
 // Hu_i = sum_j [B(g1, g2) w + (F''_i s_i + F''_j s_j) rho' dh], w = u_i - u_j,
 // with B(g1, g2) w = g2 (dh.w) dh + (g1 / r)(w - (dh.w) dh).
 __global__ __launch_bounds__(kBlock) void k_hvp(const double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                const int* __restrict__ wcnt, int n, int kcap, int ncap,
-                                                BoxDev box, PotDev pot, const double* __restrict__ u,
+                                                const int* __restrict__ wcnt, const int* __restrict__ real_of, int n,
+                                                int kcap, int ncap, PotDev pot, const double* __restrict__ u,
                                                 const double* __restrict__ aux, double* __restrict__ hu) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -861,10 +1206,10 @@ __global__ __launch_bounds__(kBlock) void k_hvp(const double4* __restrict__ pos,
   const double f1i = gupta ? aux[i] : 0.0, f2i = gupta ? aux[ncap + i] : 0.0, si = gupta ? aux[2 * ncap + i] : 0.0;
   for_neighbour_index(nbr, wcnt, kcap, i, [&](int j) {
     const double4 pj = pos[j];
-    double d[3] = {pi.x - pj.x, pi.y - pj.y, pi.z - pj.z};
-    min_image(d[0], d[1], d[2], box);
+    const double d[3] = {pi.x - pj.x, pi.y - pj.y, pi.z - pj.z};
     const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (!(r2 < pot.rc2)) return;
+    j = real_of[j];
     const double r = sqrt(r2), ir = 1.0 / r;
     const double w[3] = {ui[0] - u[j], ui[1] - u[ncap + j], ui[2] - u[2 * ncap + j]};
     const double dw = (d[0] * w[0] + d[1] * w[1] + d[2] * w[2]) * ir;  // dh.w
@@ -978,10 +1323,16 @@ struct fire_ctx {
   std::string err;
 
   // ---- single-system workspace
-  int n = 0, ncap = 0;
-  double4 *pos = nullptr, *pos2 = nullptr;
+  int n = 0, ncap = 0;        // real atoms and capacity (multiple of the block size)
+  int ng = 0, tcap = 0;       // ghosts; slot capacity (real + ghost + padding slot tcap - 1)
+  double4 *pos = nullptr, *pos2 = nullptr;   // slots
   double *vel = nullptr, *vel2 = nullptr, *frc = nullptr, *frc2 = nullptr;
   int *id = nullptr, *id2 = nullptr, *cell_of = nullptr, *order = nullptr;
+  long long* key = nullptr;                  // in-cell ordering key per slot
+  int *gcount = nullptr, *goff = nullptr;    // ghosts per real atom (pre-sort) and offsets
+  int *gsrc = nullptr, *gcode = nullptr, *gsrc2 = nullptr, *gcode2 = nullptr;  // per ghost
+  int *gcnt = nullptr, *glist = nullptr;     // ghosts of each real slot (at most 7)
+  int *new_of_old = nullptr, *real_of = nullptr;
   double* stage = nullptr;  // AoS staging [ncap][3]
   int ccap = 0;
   int *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr;
@@ -989,6 +1340,16 @@ struct fire_ctx {
   int *nbr = nullptr, *wcnt = nullptr;  // list [wave][k][lane], padded length per wave
   double4* xref = nullptr;                // positions at the last list build
   int* bucket = nullptr;                  // cell-bucketed slots before ranking
+  int* srank = nullptr;                   // cell rank of each slot
+  int *cell_rank = nullptr, *rank_cell = nullptr;  // linear cell <-> Morton rank
+  int rank_dims[3] = {0, 0, 0}, rank_per = -1;
+  // LDS-staged tiles
+  int* tile_h = nullptr;
+  int* hslot = nullptr;
+  unsigned short* nbr16 = nullptr;
+  int hcap = 0;
+  bool use_lds = false;
+  size_t lds_bytes = 0, lds_limit = 0;
   double *part = nullptr, *part_emb = nullptr, *bbox_part = nullptr;
   double* aux = nullptr;  // HVP / Lanczos planes
   int aux_planes = 0;
@@ -1039,17 +1400,32 @@ int set_err(fire_ctx* c, int code, const std::string& msg) {
                      std::string(#call) + ": " + hip_err_str(e_));                                 \
   } while (0)
 
-void free_single(fire_ctx* c) {
-  hipFree(c->pos); hipFree(c->pos2); hipFree(c->vel); hipFree(c->vel2); hipFree(c->frc); hipFree(c->frc2);
-  hipFree(c->id); hipFree(c->id2); hipFree(c->cell_of); hipFree(c->order); hipFree(c->stage);
-  hipFree(c->part); hipFree(c->part_emb); hipFree(c->bbox_part);
-  hipFree(c->xref); hipFree(c->bucket); hipFree(c->wcnt);
-  c->xref = nullptr;
-  c->bucket = c->wcnt = nullptr;
+void free_slots(fire_ctx* c) {
+  hipFree(c->pos); hipFree(c->pos2); hipFree(c->cell_of); hipFree(c->order); hipFree(c->bucket);
+  hipFree(c->srank); hipFree(c->key); hipFree(c->real_of); hipFree(c->gsrc); hipFree(c->gcode);
+  hipFree(c->gsrc2); hipFree(c->gcode2);
   c->pos = c->pos2 = nullptr;
+  c->cell_of = c->order = c->bucket = c->srank = c->real_of = nullptr;
+  c->gsrc = c->gcode = c->gsrc2 = c->gcode2 = nullptr;
+  c->key = nullptr;
+  c->tcap = 0;
+}
+
+void free_single(fire_ctx* c) {
+  free_slots(c);
+  hipFree(c->vel); hipFree(c->vel2); hipFree(c->frc); hipFree(c->frc2);
+  hipFree(c->id); hipFree(c->id2); hipFree(c->stage);
+  hipFree(c->part); hipFree(c->part_emb); hipFree(c->bbox_part);
+  hipFree(c->xref); hipFree(c->wcnt); hipFree(c->tile_h); hipFree(c->hslot); hipFree(c->nbr16);
+  hipFree(c->gcount); hipFree(c->goff); hipFree(c->gcnt); hipFree(c->glist); hipFree(c->new_of_old);
   c->vel = c->vel2 = c->frc = c->frc2 = nullptr;
-  c->id = c->id2 = c->cell_of = c->order = nullptr;
+  c->id = c->id2 = nullptr;
   c->stage = c->part = c->part_emb = c->bbox_part = nullptr;
+  c->xref = nullptr;
+  c->wcnt = c->tile_h = c->hslot = nullptr;
+  c->nbr16 = nullptr;
+  c->gcount = c->goff = c->gcnt = c->glist = c->new_of_old = nullptr;
+  c->use_lds = false;
   c->ncap = 0;
 }
 
@@ -1061,17 +1437,44 @@ void drop_graphs(fire_ctx* c) {
   }
 }
 
-// Capacity is a multiple of the block size, so every launch over ceil(n/256)
-// blocks stays inside the arrays; pos has one extra slot (NaN) that pads the
-// neighbour lists.
+// Slot arrays (real atoms, their ghosts, and the padding slot tcap - 1).
+// The positions of the first `keep` slots survive a reallocation.
+int ensure_slots(fire_ctx* ctx, int nt, int keep = 0) {
+  if (nt + 1 <= ctx->tcap) return FIRE_OK;
+  drop_graphs(ctx);
+  const int cap = std::max(nt + 1 + nt / 8, ctx->ncap + 1);
+  double4* np = nullptr;
+  HIPCHK(dalloc(&np, cap));
+  if (keep > 0 && ctx->pos) {
+    HIPCHK(hipMemcpyAsync(np, ctx->pos, sizeof(double4) * keep, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  free_slots(ctx);
+  ctx->pos = np;
+  HIPCHK(dalloc(&ctx->pos2, cap));
+  HIPCHK(dalloc(&ctx->cell_of, cap));
+  HIPCHK(dalloc(&ctx->order, cap));
+  HIPCHK(dalloc(&ctx->bucket, cap));
+  HIPCHK(dalloc(&ctx->srank, cap));
+  HIPCHK(dalloc(&ctx->key, cap));
+  HIPCHK(dalloc(&ctx->real_of, cap));
+  HIPCHK(dalloc(&ctx->gsrc, cap));
+  HIPCHK(dalloc(&ctx->gcode, cap));
+  HIPCHK(dalloc(&ctx->gsrc2, cap));
+  HIPCHK(dalloc(&ctx->gcode2, cap));
+  ctx->tcap = cap;
+  ctx->layout_version++;
+  return FIRE_OK;
+}
+
+// Real-atom arrays.  Capacity is a multiple of the block size, so every
+// launch over ceil(n/256) blocks stays inside them.
 int ensure_atoms(fire_ctx* ctx, int n) {
   if (n <= ctx->ncap) return FIRE_OK;
   drop_graphs(ctx);
   free_single(ctx);
   const int cap = ((std::max(n, 64) + kBlock - 1) / kBlock) * kBlock;
   const int nb = cap / kBlock;
-  HIPCHK(dalloc(&ctx->pos, cap + 1));
-  HIPCHK(dalloc(&ctx->pos2, cap + 1));
   HIPCHK(dalloc(&ctx->xref, cap));
   HIPCHK(dalloc(&ctx->vel, 3 * (size_t)cap));
   HIPCHK(dalloc(&ctx->vel2, 3 * (size_t)cap));
@@ -1079,18 +1482,22 @@ int ensure_atoms(fire_ctx* ctx, int n) {
   HIPCHK(dalloc(&ctx->frc2, 3 * (size_t)cap));
   HIPCHK(dalloc(&ctx->id, cap));
   HIPCHK(dalloc(&ctx->id2, cap));
-  HIPCHK(dalloc(&ctx->cell_of, cap));
-  HIPCHK(dalloc(&ctx->order, cap));
-  HIPCHK(dalloc(&ctx->bucket, cap));
+  HIPCHK(dalloc(&ctx->gcount, cap));
+  HIPCHK(dalloc(&ctx->goff, cap + 1));
+  HIPCHK(dalloc(&ctx->gcnt, cap));
+  HIPCHK(dalloc(&ctx->glist, 8 * (size_t)cap));
+  HIPCHK(dalloc(&ctx->new_of_old, cap));
   HIPCHK(dalloc(&ctx->wcnt, cap / 64));
+  HIPCHK(dalloc(&ctx->tile_h, nb));
   HIPCHK(dalloc(&ctx->stage, 3 * (size_t)cap));
   HIPCHK(dalloc(&ctx->part, (size_t)kRed * nb));
   HIPCHK(dalloc(&ctx->part_emb, nb));
   HIPCHK(dalloc(&ctx->bbox_part, 6 * (size_t)nb));
   HIPCHK(hipMemset(ctx->wcnt, 0, sizeof(int) * (cap / 64)));
+  HIPCHK(hipMemset(ctx->gcnt, 0, sizeof(int) * cap));
   ctx->ncap = cap;
   ctx->layout_version++;
-  if (ctx->kcap) {  // the neighbour list is sized by ncap
+  if (ctx->kcap) {  // the neighbour lists are sized by ncap
     hipFree(ctx->nbr);
     ctx->nbr = nullptr;
     ctx->kcap = 0;
@@ -1100,7 +1507,7 @@ int ensure_atoms(fire_ctx* ctx, int n) {
     ctx->aux = nullptr;
     ctx->aux_planes = 0;
   }
-  return FIRE_OK;
+  return ensure_slots(ctx, n + n / 2 + 64);
 }
 
 int ensure_aux(fire_ctx* ctx, int planes) {
@@ -1168,7 +1575,10 @@ int prepare_system(fire_ctx* ctx, const fire_box* b, const fire_potential* p) {
   return FIRE_OK;
 }
 
-// Cell grid from the box (periodic axes) or the current bounding box (free axes).
+// Cell grid: edge >= rcs; on periodic axes the box plus one ghost layer on
+// each side, on free axes the bounding box of the atoms.  Cells inside the
+// box get the first ranks (Morton order), the ghost layers the rest, so a
+// sort by rank puts real atoms before ghosts.
 int make_grid(fire_ctx* ctx, int n) {
   Grid& g = ctx->grid;
   double bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
@@ -1191,6 +1601,7 @@ int make_grid(fire_ctx* ctx, int n) {
   }
   const double rcs = ctx->rcs;
   long long ncell = 1;
+  int in_lo[3], in_hi[3];
   for (int k = 0; k < 3; ++k) {
     double lo, ext;
     if (ctx->box.per[k]) {
@@ -1200,19 +1611,26 @@ int make_grid(fire_ctx* ctx, int n) {
       lo = bmin[k];
       ext = bmax[k] - bmin[k];
     }
-    int nc = rcs > 0 ? (int)std::floor(ext / rcs) : 1;
-    nc = std::max(1, std::min(nc, 1024));
-    g.n[k] = nc;
-    g.lo[k] = lo;
-    g.inv[k] = ext > 0 ? nc / ext : 0.0;
+    // cell edge strictly above rcs, so rounding at a cell face never
+    // separates a pair inside the cutoff by more than one cell
+    int nc = rcs > 0 ? (int)std::floor(ext / (rcs * (1.0 + 1e-9))) : 1;
+    nc = std::max(1, std::min(nc, 1000));
+    const double inv = ext > 0 ? nc / ext : 0.0;
     if (ctx->box.per[k]) {
-      g.lo_off[k] = nc >= 3 ? -1 : 0;
-      g.hi_off[k] = nc >= 2 ? 1 : 0;
+      g.n[k] = nc + 2;
+      g.lo[k] = lo - ext / nc;
+      in_lo[k] = 1;
+      in_hi[k] = nc;
     } else {
-      g.lo_off[k] = -1;
-      g.hi_off[k] = 1;
+      g.n[k] = nc;
+      g.lo[k] = lo;
+      in_lo[k] = 0;
+      in_hi[k] = nc - 1;
     }
-    ncell *= nc;
+    g.inv[k] = inv;
+    g.in_lo[k] = in_lo[k];
+    g.in_hi[k] = in_hi[k];
+    ncell *= g.n[k];
   }
   if (ncell > (1LL << 26)) return set_err(ctx, FIRE_E_ARG, "cell grid too large");
   g.ncell = (int)ncell;
@@ -1220,49 +1638,147 @@ int make_grid(fire_ctx* ctx, int n) {
     hipFree(ctx->cell_count);
     hipFree(ctx->cell_start);
     hipFree(ctx->cell_cursor);
+    hipFree(ctx->cell_rank);
+    hipFree(ctx->rank_cell);
     int cap = g.ncell + 1;
     HIPCHK(dalloc(&ctx->cell_count, cap));
     HIPCHK(dalloc(&ctx->cell_start, cap));
     HIPCHK(dalloc(&ctx->cell_cursor, cap));
+    HIPCHK(dalloc(&ctx->cell_rank, cap));
+    HIPCHK(dalloc(&ctx->rank_cell, cap));
     ctx->ccap = cap;
+    ctx->rank_dims[0] = 0;
+  }
+  const int per_code = ctx->box.per[0] | (ctx->box.per[1] << 1) | (ctx->box.per[2] << 2);
+  if (ctx->rank_dims[0] != g.n[0] || ctx->rank_dims[1] != g.n[1] || ctx->rank_dims[2] != g.n[2] ||
+      ctx->rank_per != per_code) {
+    auto spread = [](unsigned v) {
+      unsigned long long x = v & 0x3ff;
+      x = (x | (x << 16)) & 0x30000ffULL;
+      x = (x | (x << 8)) & 0x300f00fULL;
+      x = (x | (x << 4)) & 0x30c30c3ULL;
+      x = (x | (x << 2)) & 0x9249249ULL;
+      return x;
+    };
+    std::vector<std::pair<unsigned long long, int>> key(g.ncell);
+    for (int c = 0; c < g.ncell; ++c) {
+      const int cc[3] = {c % g.n[0], (c / g.n[0]) % g.n[1], c / (g.n[0] * g.n[1])};
+      bool inside = true;
+      for (int k = 0; k < 3; ++k) inside = inside && cc[k] >= in_lo[k] && cc[k] <= in_hi[k];
+      const unsigned long long m = spread(cc[0]) | (spread(cc[1]) << 1) | (spread(cc[2]) << 2);
+      key[c] = {(inside ? 0ULL : (1ULL << 40)) | m, c};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int> rank(g.ncell), cell(g.ncell);
+    for (int r = 0; r < g.ncell; ++r) {
+      cell[r] = key[r].second;
+      rank[key[r].second] = r;
+    }
+    HIPCHK(hipMemcpy(ctx->cell_rank, rank.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->rank_cell, cell.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
+    for (int k = 0; k < 3; ++k) ctx->rank_dims[k] = g.n[k];
+    ctx->rank_per = per_code;
   }
   return FIRE_OK;
 }
 
 int read_flags(fire_ctx* ctx) {
-  HIPCHK(hipMemcpyAsync(ctx->h_flags, ctx->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->h_flags, ctx->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return FIRE_OK;
 }
 
-// Sort atoms by cell (stable: by caller index inside a cell) and build the
-// neighbour list of the current positions; positions on periodic axes are
-// wrapped into the box.  Records the build positions for the skin test.
+// Tile halos and 16-bit neighbour lists for the LDS-staged passes; falls back
+// to the global-gather passes when a halo does not fit the LDS of a block.
+int build_tiles(fire_ctx* ctx) {
+  hipStream_t s = ctx->stream;
+  const int n = ctx->n, nb = nblocks(n);
+  const size_t max_atoms = ctx->lds_limit / sizeof(double4);
+  const int hcap = (int)std::min<size_t>(max_atoms, 65535);
+  ctx->use_lds = false;
+  if (hcap < 64) return FIRE_OK;
+  if (!ctx->nbr16) HIPCHK(dalloc(&ctx->nbr16, (size_t)ctx->kcap * ctx->ncap));
+  if (!ctx->hslot || ctx->hcap != hcap) {
+    hipFree(ctx->hslot);
+    ctx->hslot = nullptr;
+    HIPCHK(dalloc(&ctx->hslot, (size_t)hcap * (ctx->ncap / kBlock)));
+    ctx->hcap = hcap;
+    ctx->layout_version++;
+  }
+  const Grid& g = ctx->grid;
+  HIPCHK(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), s));
+  hipLaunchKernelGGL(k_tile_halo, dim3(nb), dim3(kBlock), 0, s, ctx->srank, ctx->cell_start, ctx->rank_cell,
+                     ctx->cell_rank, n, g, ctx->nbr, ctx->wcnt, ctx->kcap, ctx->hcap, ctx->tcap - 1, ctx->tile_h,
+                     ctx->hslot, ctx->nbr16, ctx->flags);
+  int rc = read_flags(ctx);
+  if (rc) return rc;
+  if (ctx->h_flags[3]) return FIRE_OK;  // some halo too large: global gathers
+  const size_t bytes = sizeof(double4) * (size_t)(ctx->h_flags[2] + 1);
+  if (bytes > ctx->lds_limit) return FIRE_OK;
+  // round up so small changes of the largest halo do not force a new graph
+  const size_t rounded = std::min(ctx->lds_limit, (bytes + 4095) & ~(size_t)4095);
+  if (getenv("FIRE_DEBUG"))
+    fprintf(stderr, "[fire] rebuild: n %d, kcap %d, max halo %d atoms, %zu B LDS per tile block\n", n, ctx->kcap,
+            ctx->h_flags[2], rounded);
+  if (rounded != ctx->lds_bytes) {
+    ctx->lds_bytes = rounded;
+    ctx->layout_version++;
+  }
+  if (!ctx->use_lds) ctx->layout_version++;
+  ctx->use_lds = true;
+  return FIRE_OK;
+}
+
+// Sort atoms by cell (stable: by caller index inside a cell), regenerate the
+// periodic images and build the neighbour list of the current positions;
+// positions on periodic axes are wrapped into the box.  Records the build
+// positions for the skin test.
 int rebuild(fire_ctx* ctx) {
   const int n = ctx->n;
   hipStream_t s = ctx->stream;
   if (ctx->pot.kind == FIRE_POT_HARMONIC) {  // no pairs, no list
     HIPCHK(hipMemcpyAsync(ctx->xref, ctx->pos, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
+    ctx->ng = 0;
     ctx->have_list = true;
     return FIRE_OK;
   }
-  int rc = make_grid(ctx, n);
+  const int nb = nblocks(n);
+  // ---- periodic images
+  hipLaunchKernelGGL(k_ghost_count, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, ctx->rcs, ctx->gcount);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctx->gcount, n, ctx->goff);
+  HIPCHK(hipMemcpyAsync(ctx->h_flags, ctx->goff + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int ng = ctx->h_flags[0];
+  int rc = ensure_slots(ctx, n + ng, n);
+  if (rc) return rc;
+  ctx->ng = ng;
+  const int nt = n + ng;
+  hipLaunchKernelGGL(k_ghost_fill, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, ctx->rcs, ctx->goff,
+                     ctx->gsrc, ctx->gcode);
+  // ---- cell sort of all slots
+  rc = make_grid(ctx, n);
   if (rc) return rc;
   const Grid& g = ctx->grid;
   HIPCHK(hipMemsetAsync(ctx->cell_count, 0, sizeof(int) * (g.ncell + 1), s));
   HIPCHK(hipMemsetAsync(ctx->cell_cursor, 0, sizeof(int) * (g.ncell + 1), s));
-  const int nb = nblocks(n);
-  hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g, ctx->cell_of,
-                     ctx->cell_count);
+  HIPCHK(hipMemsetAsync(ctx->gcnt, 0, sizeof(int) * ctx->ncap, s));
+  const int nbt = nblocks(nt);
+  hipLaunchKernelGGL(k_cell_count, dim3(nbt), dim3(kBlock), 0, s, ctx->pos, n, nt, g, ctx->cell_rank, ctx->id,
+                     ctx->gsrc, ctx->gcode, ctx->cell_of, ctx->key, ctx->cell_count);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctx->cell_count, g.ncell, ctx->cell_start);
-  hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(kBlock), 0, s, ctx->cell_of, n, ctx->cell_start,
+  hipLaunchKernelGGL(k_cell_fill, dim3(nbt), dim3(kBlock), 0, s, ctx->cell_of, nt, ctx->cell_start,
                      ctx->cell_cursor, ctx->bucket);
-  hipLaunchKernelGGL(k_cell_rank, dim3(nb), dim3(kBlock), 0, s, ctx->cell_of, ctx->cell_start, ctx->bucket, n,
-                     ctx->id, ctx->order);
-  hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, s, ctx->order, n, ctx->ncap, ctx->pos, ctx->vel,
-                     ctx->frc, ctx->id, ctx->pos2, ctx->vel2, ctx->frc2, ctx->id2);
-  HIPCHK(hipMemcpyAsync(ctx->pos, ctx->pos2, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(ctx->xref, ctx->pos2, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_cell_rank, dim3(nbt), dim3(kBlock), 0, s, ctx->cell_of, ctx->cell_start, ctx->bucket, nt,
+                     ctx->key, ctx->order);
+  hipLaunchKernelGGL(k_permute, dim3(nbt), dim3(kBlock), 0, s, ctx->order, n, nt, ctx->ncap, ctx->pos, ctx->vel,
+                     ctx->frc, ctx->id, ctx->cell_of, ctx->gsrc, ctx->gcode, ctx->pos2, ctx->vel2, ctx->frc2,
+                     ctx->id2, ctx->srank, ctx->new_of_old, ctx->gsrc2, ctx->gcode2);
+  hipLaunchKernelGGL(k_ghost_link, dim3(nblocks(std::max(n, ng))), dim3(kBlock), 0, s, n, ng, ctx->new_of_old,
+                     ctx->gsrc2, ctx->real_of, ctx->gcnt, ctx->glist);
+  std::swap(ctx->pos, ctx->pos2);
+  std::swap(ctx->gsrc, ctx->gsrc2);
+  std::swap(ctx->gcode, ctx->gcode2);
+  HIPCHK(hipMemcpyAsync(ctx->xref, ctx->pos, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->id, ctx->id2, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
   for (int d = 0; d < 3; ++d) {
     HIPCHK(hipMemcpyAsync(ctx->vel + (size_t)d * ctx->ncap, ctx->vel2 + (size_t)d * ctx->ncap, sizeof(double) * n,
@@ -1270,21 +1786,24 @@ int rebuild(fire_ctx* ctx) {
     HIPCHK(hipMemcpyAsync(ctx->frc + (size_t)d * ctx->ncap, ctx->frc2 + (size_t)d * ctx->ncap, sizeof(double) * n,
                           hipMemcpyDeviceToDevice, s));
   }
+  const int dummy = ctx->tcap - 1;
+  hipLaunchKernelGGL(k_set_pos, dim3(1), dim3(64), 0, s, ctx->pos, dummy, kFar);
+  // ---- neighbour lists
   const double rcs2 = ctx->rcs * ctx->rcs;
   if (ctx->kcap == 0) {
     // first guess from the mean density; a larger count triggers one more pass
     double vol = 1.0;
-    for (int k = 0; k < 3; ++k) vol *= g.n[k] / std::max(g.inv[k], 1e-300);
-    double dens = n / std::max(vol, 1e-300);
-    int guess = (int)(1.4 * dens * 4.18879 * rcs2 * ctx->rcs) + 16;
-    ctx->kcap = std::min((guess + 3) & ~3, std::max(4, ((n + 3) & ~3)));
+    for (int k = 0; k < 3; ++k) vol *= (ctx->box.per[k] ? g.n[k] - 2 : g.n[k]) / std::max(g.inv[k], 1e-300);
+    const double dens = n / std::max(vol, 1e-300);
+    const int guess = (int)(1.4 * dens * 4.18879 * rcs2 * ctx->rcs) + 16;
+    ctx->kcap = std::min((guess + 3) & ~3, std::max(4, ((nt + 3) & ~3)));
     HIPCHK(dalloc(&ctx->nbr, (size_t)ctx->kcap * ctx->ncap));
     ctx->layout_version++;
   }
   for (int attempt = 0; attempt < 3; ++attempt) {
-    HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
-    hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, g,
-                       ctx->cell_start, rcs2, ctx->kcap, ctx->ncap, ctx->nbr, ctx->wcnt, ctx->flags);
+    HIPCHK(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), s));
+    hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, n, g, ctx->cell_rank,
+                       ctx->cell_start, rcs2, ctx->kcap, dummy, ctx->nbr, ctx->wcnt, ctx->flags);
     rc = read_flags(ctx);
     if (rc) return rc;
     if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
@@ -1294,50 +1813,65 @@ int rebuild(fire_ctx* ctx) {
     ctx->nbr = nullptr;
     ctx->kcap = ((kmax + kmax / 8 + 8) + 3) & ~3;
     HIPCHK(dalloc(&ctx->nbr, (size_t)ctx->kcap * ctx->ncap));
+    hipFree(ctx->nbr16);
+    ctx->nbr16 = nullptr;
     ctx->layout_version++;
   }
   ctx->have_list = true;
-  return FIRE_OK;
+  return build_tiles(ctx);
+}
+
+template <typename T, bool LDS, bool WE>
+void launch_pair_passes(fire_ctx* ctx, hipStream_t s) {
+  const int n = ctx->n, nb = nblocks(n), kc = ctx->kcap, nc = ctx->ncap;
+  const PotDev& P = ctx->pot;
+  const Tiles tl{ctx->tile_h, ctx->hslot, ctx->nbr16, ctx->hcap};
+  const size_t sm = LDS ? ctx->lds_bytes : 0;
+  if (P.kind == FIRE_POT_LJ) {
+    hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt,
+                       n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
+  } else {
+    hipLaunchKernelGGL((k_gupta_density<T, LDS>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl,
+                       ctx->wcnt, n, kc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl);
+    hipLaunchKernelGGL((k_gupta_force<T, LDS, WE>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl,
+                       ctx->wcnt, n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl,
+                       ctx->trace);
+  }
+}
+
+template <bool WE>
+void launch_pairs(fire_ctx* ctx, hipStream_t s, int prec) {
+  if (ctx->use_lds) {
+    if (prec) launch_pair_passes<float, true, WE>(ctx, s);
+    else launch_pair_passes<double, true, WE>(ctx, s);
+  } else {
+    if (prec) launch_pair_passes<float, false, WE>(ctx, s);
+    else launch_pair_passes<double, false, WE>(ctx, s);
+  }
 }
 
 // One force evaluation (passes + fused reductions and control) enqueued on
-// stream s.  prec: 0 FP64 pair terms, 1 FP32.
-void launch_forces(fire_ctx* ctx, hipStream_t s, int prec) {
-  const int n = ctx->n, nb = nblocks(n), kc = ctx->kcap, nc = ctx->ncap;
-  const PotDev& P = ctx->pot;
-  if (P.kind == FIRE_POT_LJ) {
-    if (prec)
-      hipLaunchKernelGGL(k_lj_force<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, kc, nc,
-                         ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
-    else
-      hipLaunchKernelGGL(k_lj_force<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, kc,
-                         nc, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
-  } else if (P.kind == FIRE_POT_GUPTA) {
-    if (prec) {
-      hipLaunchKernelGGL(k_gupta_density<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n,
-                         kc, ctx->box, P, ctx->part_emb, ctx->ctrl);
-      hipLaunchKernelGGL(k_gupta_force<float>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, kc,
-                         nc, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace);
-    } else {
-      hipLaunchKernelGGL(k_gupta_density<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n,
-                         kc, ctx->box, P, ctx->part_emb, ctx->ctrl);
-      hipLaunchKernelGGL(k_gupta_force<double>, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, kc,
-                         nc, ctx->box, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace);
-    }
-  } else {
-    hipLaunchKernelGGL(k_harmonic_force, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, nc, P, ctx->frc, ctx->vel,
-                       ctx->part, ctx->ctrl, ctx->trace);
+// stream s.  prec: 0 FP64 pair terms, 1 FP32.  with_e: also accumulate the
+// energy (the FIRE steps themselves only need forces and P).
+void launch_forces(fire_ctx* ctx, hipStream_t s, int prec, bool with_e = true) {
+  if (ctx->pot.kind == FIRE_POT_HARMONIC) {
+    hipLaunchKernelGGL(k_harmonic_force, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->n, ctx->ncap,
+                       ctx->pot, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
+    return;
   }
+  if (with_e) launch_pairs<true>(ctx, s, prec);
+  else launch_pairs<false>(ctx, s, prec);
 }
 
 void launch_update(fire_ctx* ctx, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->vel, ctx->frc, ctx->xref,
-                     ctx->n, ctx->ncap, ctx->ctrl);
+                     ctx->gcnt, ctx->glist, ctx->gcode, ctx->box, ctx->n, ctx->ncap, ctx->ctrl);
 }
 
+// One FIRE iteration; energies only when a trace is recorded.
 void launch_iteration(fire_ctx* ctx, hipStream_t s, int prec) {
   launch_update(ctx, s);
-  launch_forces(ctx, s, prec);
+  launch_forces(ctx, s, prec, ctx->trace != nullptr);
 }
 
 int graph_for(fire_ctx* ctx, int prec, hipGraphExec_t* out) {
@@ -1374,8 +1908,7 @@ int stage_in(fire_ctx* ctx, long long n, const double* src, bool host, hipStream
     d = ctx->stage;
   }
   HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
-  hipLaunchKernelGGL(k_stage_in, dim3(nblocks(ctx->ncap + 1)), dim3(kBlock), 0, s, d, (int)n, ctx->ncap, ctx->pos,
-                     ctx->vel,
+  hipLaunchKernelGGL(k_stage_in, dim3(nblocks(n)), dim3(kBlock), 0, s, d, (int)n, ctx->ncap, ctx->pos, ctx->vel,
                      ctx->frc, ctx->id, ctx->flags);
   if (!host) {
     rc = read_flags(ctx);
@@ -1437,7 +1970,7 @@ int evaluate(fire_ctx* ctx, hipStream_t s) {
 
 // Resume the device FIRE loop: status running, no pause, no skin violation.
 int resume(fire_ctx* ctx, hipStream_t s) {
-  int* up = ctx->h_flags + 2;
+  int* up = ctx->h_flags + 4;
   up[0] = ST_RUNNING;
   up[1] = 0;
   *ctx->h_zero = 0.0;
@@ -1498,9 +2031,27 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
   }
   HIPCHK(hipMemcpyAsync(ctx->h_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const Ctrl& h = *ctx->h_ctrl;
+  Ctrl h = *ctx->h_ctrl;
   rc = check_status_error(ctx, h.status);
   if (rc) return rc;
+  if (!ctx->trace) {
+    // the loop skips the energy; evaluate it once at the final positions with
+    // the run's last pair precision (forces and norms come out identical)
+    Ctrl& e = *ctx->h_ctrl;
+    e.status = ST_RUNNING;
+    e.pause = 0;
+    e.viol = 0;
+    e.eval_only = 1;
+    e.kick3 = 0.0;
+    e.ticket = 0;
+    HIPCHK(hipMemcpyAsync(ctx->ctrl, &e, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    launch_forces(ctx, s, h.precision, true);
+    HIPCHK(hipMemcpyAsync(ctx->h_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rc = check_status_error(ctx, ctx->h_ctrl->status);
+    if (rc) return rc;
+    h.energy = ctx->h_ctrl->energy;
+  }
   if (out) {
     memset(out, 0, sizeof(*out));
     out->stop_reason = h.status;
@@ -1572,10 +2123,10 @@ int dev_remove_mean(fire_ctx* ctx, hipStream_t s, double* a) {
 void launch_hvp(fire_ctx* ctx, hipStream_t s, const double* u, double* hu, double* pre) {
   const int n = ctx->n, nb = nblocks(n);
   if (ctx->pot.kind == FIRE_POT_GUPTA)
-    hipLaunchKernelGGL(k_gupta_hvp_pre, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, ctx->kcap,
-                       ctx->ncap, ctx->box, ctx->pot, u, pre);
-  hipLaunchKernelGGL(k_hvp, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, ctx->kcap, ctx->ncap,
-                     ctx->box, ctx->pot, u, (const double*)pre, hu);
+    hipLaunchKernelGGL(k_gupta_hvp_pre, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, ctx->real_of, n,
+                       ctx->kcap, ctx->ncap, ctx->pot, u, pre);
+  hipLaunchKernelGGL(k_hvp, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, ctx->real_of, n, ctx->kcap,
+                     ctx->ncap, ctx->pot, u, (const double*)pre, hu);
 }
 
 // Smallest eigenvalue of the symmetric tridiagonal matrix (a diagonal, b off-diagonal) by Sturm bisection.
@@ -1665,8 +2216,13 @@ int fire_init(fire_ctx** out, int device, const fire_params* params) {
     HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipMalloc((void**)&ctx->ctrl, sizeof(Ctrl)));
-    HIPCHK(hipMalloc((void**)&ctx->flags, 4 * sizeof(int)));
-    HIPCHK(hipHostMalloc((void**)&ctx->h_flags, 4 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipMalloc((void**)&ctx->flags, 8 * sizeof(int)));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_flags, 8 * sizeof(int), hipHostMallocDefault));
+    // LDS-staged neighbour passes are opt-in: with halos of ~2-3k atoms per
+    // 256-atom tile they fit one block per CU and measure slower than the
+    // global-gather passes on the bulk workloads
+    ctx->lds_limit = 0;
+    if (getenv("FIRE_LDS")) ctx->lds_limit = prop.sharedMemPerBlock > 4096 ? prop.sharedMemPerBlock - 4096 : 0;
     HIPCHK(hipHostMalloc((void**)&ctx->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_status, 16 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_zero, sizeof(double), hipHostMallocDefault));
@@ -1694,6 +2250,8 @@ void fire_finalize(fire_ctx* ctx) {
   hipFree(ctx->cell_count);
   hipFree(ctx->cell_start);
   hipFree(ctx->cell_cursor);
+  hipFree(ctx->cell_rank);
+  hipFree(ctx->rank_cell);
   hipFree(ctx->aux);
   hipFree(ctx->ctrl);
   hipFree(ctx->flags);
@@ -1974,7 +2532,7 @@ int fire_repeat_forces_dev(fire_ctx* ctx, int reps, void* stream) {
   HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   const int prec = ctx->params.precision == FIRE_FP64 ? 0 : 1;
-  for (int r = 0; r < reps; ++r) launch_forces(ctx, s, prec);
+  for (int r = 0; r < reps; ++r) launch_forces(ctx, s, prec, false);
   return FIRE_OK;
 }
 

@@ -191,3 +191,20 @@ def test_hvp_matches_oracle(ctx, name):
     hu = ctx.fire_hvp(s.pos, u, s.box, s.potential)
     ref = oracle.hvp(s.pos, u, s.box, s.potential)
     assert np.abs(hu - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["lj_6", "gupta_5", "gupta_slab", "gupta_cluster"])
+def test_lds_staged_path_matches_oracle(api, name, monkeypatch):
+    """The opt-in passes that stage each tile's halo in LDS agree with the
+    oracle as well."""
+    s = SMALL[name]()
+    monkeypatch.setenv("FIRE_LDS", "1")
+    c = api.Context(0)
+    e, f = c.fire_energy_forces(s.pos, s.box, s.potential)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 20)
+    c.close()
+    e_ref, f_ref = oracle.energy_forces(s.pos, s.box, s.potential)
+    assert abs(e - e_ref) <= 1e-13 * abs(e_ref) + 1e-14
+    assert np.abs(f - f_ref).max() <= 1e-12 * np.abs(f_ref).max()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 0.0, 20)
+    assert np.abs(min_image_diff(r["pos"], ref["pos"], s.box)).max() <= 1e-12
