@@ -20,6 +20,9 @@ FLAGS = [
     "-shared",
     # packed FP32 VALU forms stay off (see the project's hardware notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a*b+c only inside one source expression, so every instantiation of
+    # a pass rounds identically (traced and untraced runs agree bit for bit)
+    "-ffp-contract=on",
     "-Wall",
     "-Wno-unused-result",
     "-Wno-unused-value",

@@ -1,15 +1,946 @@
-// batched.hip -- independent relaxations of many small systems (placeholder
-// until the persistent batched kernel lands).
+// batched.hip -- many independent FIRE 2.0 relaxations in one persistent launch.
+//
+// One workgroup ("team") relaxes one system at a time: the system's positions
+// live in LDS (up to 4096 atoms), velocities, forces and the skin reference in
+// registers, its neighbour list (16-bit system-local indices) in global
+// memory.  Every iteration -- update, EAM density, force pass, team reduction,
+// FIRE control -- runs inside the team with workgroup barriers only, and the
+// team rebuilds its own cell and neighbour list when an atom leaves its skin.
+// Each system keeps its own FIRE state (dt, alpha, N_P>0, N_P<=0, counters) in
+// a control record, advanced by the same scalar FIRE 2.0 step as the
+// single-system path.  Teams take systems from a queue ordered by decreasing
+// size and advance each by at most `chunk` iterations per launch; the launch
+// is captured in a hipGraph and replayed until every system has stopped.
+// A small autotuner picks the team shape (and chunk length) by timing the
+// candidates on the batch itself.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "fire2.h"
+#include "fire2_device.h"
+#include "fire2_internal.h"
 
-extern "C" void fire_batched_release(void* ws) { (void)ws; }
+namespace fire {
+namespace bat {
 
-extern "C" int fire_batched_run(struct fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
+constexpr int kMaxAtoms = 4096;  // per system (LDS holds its positions)
+constexpr int kMaxCells = 1024;  // per-system cell grid in LDS
+
+struct SysDesc {
+  int off, n;    // first atom in the concatenated arrays, atom count
+  BoxDev box;    // periodic axes: box; free axes: ignored
+  double rcs2;   // (cutoff + skin)^2 of this system
+};
+
+__device__ __forceinline__ void min_img(double& d, double L, double invL, int per) {
+  if (per) d -= L * rint(d * invL);
+}
+
+template <int TEAM>
+__device__ __forceinline__ void team_reduce(double (&v)[6], double (*red)[6]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+#pragma unroll
+  for (int k = 4; k < 6; ++k) v[k] = wave_max(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < TEAM / 64; ++q) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += red[q][k];
+#pragma unroll
+      for (int k = 4; k < 6; ++k) v[k] = fmax(v[k], red[q][k]);
+    }
+  }
+  __syncthreads();
+}
+
+// Shared state of a team while it works on one system.
+struct TeamShared {
+  double4 x[kMaxAtoms];          // positions (w: F'(rho) of the EAM form)
+  unsigned short cat[kMaxAtoms];  // atoms sorted by cell
+  int cstart[kMaxCells + 1];
+  int cnt[kMaxCells];
+  double red[16][6];
+  double lo[3], inv[3];
+  int nc[3], lo_off[3], hi_off[3];
+  int sys, status, viol, overflow;
+  // coefficients of the next update
+  int neg, mix_first, prec;
+  double hsb, k1, k2, k3, cv, cf, dtx;
+};
+
+template <int TEAM, int MAXPT>
+struct Team {
+  TeamShared& sh;
+  const SysDesc& d;
+  int n;
+  double4 v[MAXPT];   // velocity (w unused)
+  double4 f[MAXPT];   // force
+  double4 xr[MAXPT];  // position at the last list build
+  int ccell[MAXPT];
+
+  __device__ Team(TeamShared& s, const SysDesc& desc) : sh(s), d(desc), n(desc.n) {}
+
+  __device__ int atom(int k) const { return threadIdx.x + k * TEAM; }
+
+  // Cell list and neighbour list of the current positions (wrapped into the
+  // box on periodic axes).  Lists: nbr[off*kb + k*n + a], counts nn[off + a].
+  __device__ void build(unsigned short* __restrict__ nbr, unsigned short* __restrict__ nn, int kb) {
+    double lo3[3], hi3[3];
+    for (int q = 0; q < 3; ++q) {
+      lo3[q] = INFINITY;
+      hi3[q] = -INFINITY;
+    }
+#pragma unroll
+    for (int k = 0; k < MAXPT; ++k) {
+      const int a = atom(k);
+      if (a >= n) continue;
+      double4 p = sh.x[a];
+      double r[3] = {p.x, p.y, p.z};
+      for (int q = 0; q < 3; ++q) {
+        if (d.box.per[q]) {
+          double t = r[q] - d.box.lo[q];
+          t -= d.box.L[q] * floor(t * d.box.invL[q]);
+          if (t >= d.box.L[q]) t -= d.box.L[q];
+          if (t < 0.0) t = 0.0;
+          r[q] = d.box.lo[q] + t;
+        }
+        lo3[q] = fmin(lo3[q], r[q]);
+        hi3[q] = fmax(hi3[q], r[q]);
+      }
+      sh.x[a] = make_double4(r[0], r[1], r[2], p.w);
+      xr[k] = make_double4(r[0], r[1], r[2], 0.0);
+    }
+    // bounding box of the free axes
+    double bb[6] = {-lo3[0], -lo3[1], -lo3[2], hi3[0], hi3[1], hi3[2]};
+    {
+      const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+      for (int q = 0; q < 6; ++q) bb[q] = wave_max(bb[q]);
+      if (lane == 0)
+        for (int q = 0; q < 6; ++q) sh.red[w][q] = bb[q];
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int w2 = 1; w2 < TEAM / 64; ++w2)
+          for (int q = 0; q < 6; ++q) bb[q] = fmax(bb[q], sh.red[w2][q]);
+        const double rcs = sqrt(d.rcs2);
+        int total = 1;
+        double ext3[3];
+        for (int q = 0; q < 3; ++q) {
+          double lo, ext;
+          if (d.box.per[q]) {
+            lo = d.box.lo[q];
+            ext = d.box.L[q];
+          } else {
+            lo = -bb[q];
+            ext = bb[3 + q] + bb[q];
+          }
+          int nc = (int)floor(ext / (rcs * (1.0 + 1e-9)));
+          nc = max(1, min(nc, 64));
+          sh.nc[q] = nc;
+          sh.lo[q] = lo;
+          sh.inv[q] = ext > 0 ? nc / ext : 0.0;
+          ext3[q] = ext;
+          if (d.box.per[q]) {
+            sh.lo_off[q] = nc >= 3 ? -1 : 0;
+            sh.hi_off[q] = nc >= 2 ? 1 : 0;
+          } else {
+            sh.lo_off[q] = -1;
+            sh.hi_off[q] = 1;
+          }
+          total *= nc;
+        }
+        // coarsen until the grid fits in LDS
+        while (total > kMaxCells) {
+          int q = 0;
+          for (int z = 1; z < 3; ++z)
+            if (sh.nc[z] > sh.nc[q]) q = z;
+          sh.nc[q] = (sh.nc[q] + 1) / 2;
+          sh.inv[q] = ext3[q] > 0 ? sh.nc[q] / ext3[q] : 0.0;
+          if (d.box.per[q]) {
+            sh.lo_off[q] = sh.nc[q] >= 3 ? -1 : 0;
+            sh.hi_off[q] = sh.nc[q] >= 2 ? 1 : 0;
+          }
+          total = sh.nc[0] * sh.nc[1] * sh.nc[2];
+        }
+        sh.overflow = 0;
+      }
+    }
+    __syncthreads();
+    const int ncell = sh.nc[0] * sh.nc[1] * sh.nc[2];
+    for (int c = threadIdx.x; c < ncell; c += TEAM) sh.cnt[c] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MAXPT; ++k) {
+      const int a = atom(k);
+      if (a >= n) continue;
+      const double4 p = sh.x[a];
+      const double r[3] = {p.x, p.y, p.z};
+      int cc[3];
+      for (int q = 0; q < 3; ++q) cc[q] = min(max((int)floor((r[q] - sh.lo[q]) * sh.inv[q]), 0), sh.nc[q] - 1);
+      ccell[k] = cc[0] + sh.nc[0] * (cc[1] + sh.nc[1] * cc[2]);
+      atomicAdd(&sh.cnt[ccell[k]], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int c = 0; c < ncell; ++c) {
+        sh.cstart[c] = acc;
+        acc += sh.cnt[c];
+        sh.cnt[c] = 0;
+      }
+      sh.cstart[ncell] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MAXPT; ++k) {
+      const int a = atom(k);
+      if (a >= n) continue;
+      sh.cat[sh.cstart[ccell[k]] + atomicAdd(&sh.cnt[ccell[k]], 1)] = (unsigned short)a;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncell; c += TEAM) {  // deterministic order: by atom index
+      const int b = sh.cstart[c], e = sh.cstart[c + 1];
+      for (int p = b + 1; p < e; ++p) {
+        const unsigned short v0 = sh.cat[p];
+        int q = p - 1;
+        while (q >= b && sh.cat[q] > v0) {
+          sh.cat[q + 1] = sh.cat[q];
+          --q;
+        }
+        sh.cat[q + 1] = v0;
+      }
+    }
+    __syncthreads();
+    const size_t base = (size_t)d.off * kb;
+#pragma unroll
+    for (int k = 0; k < MAXPT; ++k) {
+      const int a = atom(k);
+      if (a >= n) continue;
+      const double4 pa = sh.x[a];
+      const int c0 = ccell[k];
+      const int cc[3] = {c0 % sh.nc[0], (c0 / sh.nc[0]) % sh.nc[1], c0 / (sh.nc[0] * sh.nc[1])};
+      int m = 0;
+      for (int oz = sh.lo_off[2]; oz <= sh.hi_off[2]; ++oz) {
+        int cz = cc[2] + oz;
+        if (d.box.per[2]) cz = (cz + sh.nc[2]) % sh.nc[2];
+        else if (cz < 0 || cz >= sh.nc[2]) continue;
+        for (int oy = sh.lo_off[1]; oy <= sh.hi_off[1]; ++oy) {
+          int cy = cc[1] + oy;
+          if (d.box.per[1]) cy = (cy + sh.nc[1]) % sh.nc[1];
+          else if (cy < 0 || cy >= sh.nc[1]) continue;
+          for (int ox = sh.lo_off[0]; ox <= sh.hi_off[0]; ++ox) {
+            int cx = cc[0] + ox;
+            if (d.box.per[0]) cx = (cx + sh.nc[0]) % sh.nc[0];
+            else if (cx < 0 || cx >= sh.nc[0]) continue;
+            const int cell = cx + sh.nc[0] * (cy + sh.nc[1] * cz);
+            for (int p = sh.cstart[cell], e = sh.cstart[cell + 1]; p < e; ++p) {
+              const int j = sh.cat[p];
+              if (j == a) continue;
+              const double4 pj = sh.x[j];
+              double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
+              min_img(dx, d.box.L[0], d.box.invL[0], d.box.per[0]);
+              min_img(dy, d.box.L[1], d.box.invL[1], d.box.per[1]);
+              min_img(dz, d.box.L[2], d.box.invL[2], d.box.per[2]);
+              const double r2 = dx * dx + dy * dy + dz * dz;
+              if (r2 == 0.0) atomicOr(&sh.overflow, 2);
+              if (r2 < d.rcs2) {
+                if (m < kb) nbr[base + (size_t)m * n + a] = (unsigned short)j;
+                ++m;
+              }
+            }
+          }
+        }
+      }
+      if (m > kb) atomicOr(&sh.overflow, 1);
+      nn[d.off + a] = (unsigned short)min(m, kb);
+    }
+    __syncthreads();
+  }
+};
+
+// Pair terms shared by the passes (branch-free; callers mask by `in`).
+template <typename T>
+__device__ __forceinline__ T gupta_density_term(double r2, const PotDev& P) {
+  T r;
+  if constexpr (sizeof(T) == 8) r = sqrt(r2);
+  else r = sqrtf((float)r2);
+  const T s = fmin(fmax((r - (T)P.r_in) * (T)P.inv_w, (T)0), (T)1);
+  return exp(-(T)P.qr0 * (r - (T)P.r0)) * (1 - s) * (1 - s) * (1 + 2 * s);
+}
+
+template <int TEAM, int MAXPT, typename T>
+__device__ void density_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigned short* __restrict__ nbr,
+                             const unsigned short* __restrict__ nn, int kb, double& emb) {
+  const SysDesc& d = tm.d;
+  const size_t base = (size_t)d.off * kb;
+  double fp_new[MAXPT];
+#pragma unroll
+  for (int k = 0; k < MAXPT; ++k) {
+    const int a = tm.atom(k);
+    fp_new[k] = 0.0;
+    if (a >= tm.n) continue;
+    const double4 pa = tm.sh.x[a];
+    T rho = 0;
+    for (int q = 0, m = nn[d.off + a]; q < m; ++q) {
+      const int j = nbr[base + (size_t)q * tm.n + a];
+      const double4 pj = tm.sh.x[j];
+      double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
+      min_img(dx, d.box.L[0], d.box.invL[0], d.box.per[0]);
+      min_img(dy, d.box.L[1], d.box.invL[1], d.box.per[1]);
+      min_img(dz, d.box.L[2], d.box.invL[2], d.box.per[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const bool in = r2 < P.rc2;
+      const T v = gupta_density_term<T>(in ? r2 : 1.0, P);
+      rho += in ? v : (T)0;
+    }
+    if (rho > 0) {
+      const double sq = sqrt((double)rho);
+      fp_new[k] = -0.5 * P.xi / sq;
+      emb += -P.xi * sq;
+    }
+  }
+  __syncthreads();  // every neighbour read of w done before it changes
+#pragma unroll
+  for (int k = 0; k < MAXPT; ++k) {
+    const int a = tm.atom(k);
+    if (a < tm.n) tm.sh.x[a].w = fp_new[k];
+  }
+  __syncthreads();
+}
+
+template <int TEAM, int MAXPT, typename T>
+__device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigned short* __restrict__ nbr,
+                           const unsigned short* __restrict__ nn, int kb, double (&r)[6]) {
+  const SysDesc& d = tm.d;
+  const size_t base = (size_t)d.off * kb;
+  const double k3 = tm.sh.k3;
+#pragma unroll
+  for (int k = 0; k < MAXPT; ++k) {
+    const int a = tm.atom(k);
+    if (a >= tm.n) continue;
+    const double4 pa = tm.sh.x[a];
+    T ax = 0, ay = 0, az = 0, ae = 0;
+    for (int q = 0, m = nn[d.off + a]; q < m; ++q) {
+      const int j = nbr[base + (size_t)q * tm.n + a];
+      const double4 pj = tm.sh.x[j];
+      double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
+      min_img(dx, d.box.L[0], d.box.invL[0], d.box.per[0]);
+      min_img(dy, d.box.L[1], d.box.invL[1], d.box.per[1]);
+      min_img(dz, d.box.L[2], d.box.invL[2], d.box.per[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const bool in = r2 < P.rc2;
+      const double r2c = in ? r2 : 1.0;
+      T fr, e;
+      if (P.kind == FIRE_POT_LJ) {
+        T ir2;
+        if constexpr (sizeof(T) == 8) ir2 = rcp_d(r2c);
+        else ir2 = rcp_f((float)r2c);
+        const T s2 = (T)P.sig2 * ir2, s6 = s2 * s2 * s2;
+        fr = (T)(24.0 * P.eps) * s6 * ((T)2 * s6 - (T)1) * ir2;
+        e = (T)0.5 * ((T)(4.0 * P.eps) * s6 * (s6 - (T)1) - (T)P.shift);
+      } else {
+        T ir;
+        if constexpr (sizeof(T) == 8) ir = rsqrt_d(r2c);
+        else ir = rsqrt_f((float)r2c);
+        const T rr = (T)r2c * ir;
+        const T s = fmin(fmax((rr - (T)P.r_in) * (T)P.inv_w, (T)0), (T)1);
+        const T S = (1 - s) * (1 - s) * (1 + 2 * s);
+        const T dS = (T)(-6) * s * (1 - s) * (T)P.inv_w;
+        const T ph = (T)P.A * exp(-(T)P.pr0 * (rr - (T)P.r0));
+        const T rh = exp(-(T)P.qr0 * (rr - (T)P.r0));
+        const T dEdr = (T)P.cpair * ph * (dS - (T)P.pr0 * S) + ((T)pa.w + (T)pj.w) * rh * (dS - (T)P.qr0 * S);
+        fr = -dEdr * ir;
+        e = (T)P.epair * ph * S;
+      }
+      fr = in ? fr : (T)0;
+      ax += fr * (T)dx;
+      ay += fr * (T)dy;
+      az += fr * (T)dz;
+      ae += in ? e : (T)0;
+    }
+    double4& v = tm.v[k];
+    const double fx = ax, fy = ay, fz = az;
+    tm.f[k] = make_double4(fx, fy, fz, 0.0);
+    if (k3 != 0.0) {
+      v.x += k3 * fx;
+      v.y += k3 * fy;
+      v.z += k3 * fz;
+    }
+    const double f2 = fx * fx + fy * fy + fz * fz, v2 = v.x * v.x + v.y * v.y + v.z * v.z;
+    r[0] += (double)ae;
+    r[1] += fx * v.x + fy * v.y + fz * v.z;
+    r[2] += f2;
+    r[3] += v2;
+    r[4] = fmax(r[4], f2);
+    r[5] = fmax(r[5], v2);
+  }
+}
+
+template <int TEAM, int MAXPT>
+__device__ void evaluate(Team<TEAM, MAXPT>& tm, Ctrl* __restrict__ c, const PotDev& P,
+                         const unsigned short* __restrict__ nbr, const unsigned short* __restrict__ nn, int kb) {
+  double r[6] = {0, 0, 0, 0, 0, 0};
+  double emb = 0.0;
+  const int prec = tm.sh.prec;
+  if (P.kind == FIRE_POT_GUPTA) {
+    if (prec) density_pass<TEAM, MAXPT, float>(tm, P, nbr, nn, kb, emb);
+    else density_pass<TEAM, MAXPT, double>(tm, P, nbr, nn, kb, emb);
+  }
+  if (prec) force_pass<TEAM, MAXPT, float>(tm, P, nbr, nn, kb, r);
+  else force_pass<TEAM, MAXPT, double>(tm, P, nbr, nn, kb, r);
+  r[0] += emb;
+  team_reduce<TEAM>(r, tm.sh.red);
+  if (threadIdx.x == 0) {
+    fire_control(c, r, nullptr);
+    if (c->status == ST_PAUSED && c->pause == PAUSE_PRECISION) {
+      c->status = ST_RUNNING;  // the team switches its own pair precision
+      c->pause = 0;
+    }
+    tm.sh.status = c->status;
+    tm.sh.neg = c->neg;
+    tm.sh.mix_first = c->mix_first;
+    tm.sh.prec = c->precision;
+    tm.sh.hsb = c->hsb;
+    tm.sh.k1 = c->kick1;
+    tm.sh.k2 = c->kick2;
+    tm.sh.k3 = c->kick3;
+    tm.sh.cv = c->cv;
+    tm.sh.cf = c->cf;
+    tm.sh.dtx = c->dtx;
+  }
+  __syncthreads();
+}
+
+// Persistent team kernel: pull systems from the queue, advance each by up to
+// `chunk` iterations.  Arrays are indexed by the concatenated atom index.
+template <int TEAM, int MAXPT>
+__global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ desc, Ctrl* __restrict__ ctrl,
+                                                  const int* __restrict__ order, int nsys, int* __restrict__ queue,
+                                                  double4* __restrict__ pos, double4* __restrict__ vel,
+                                                  double4* __restrict__ frc, double4* __restrict__ xref,
+                                                  unsigned short* __restrict__ nbr, unsigned short* __restrict__ nn,
+                                                  int kb, PotDev P, int chunk, int* __restrict__ flags) {
+  __shared__ TeamShared sh;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int q = atomicAdd(queue, 1);
+      sh.sys = q < nsys ? order[q] : -1;
+      sh.status = sh.sys >= 0 ? __hip_atomic_load(&ctrl[sh.sys].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : -1;
+    }
+    __syncthreads();
+    const int s = sh.sys;
+    if (s < 0) return;
+    if (sh.status != ST_RUNNING) {
+      __syncthreads();
+      continue;
+    }
+    const SysDesc d = desc[s];
+    Ctrl* c = &ctrl[s];
+    Team<TEAM, MAXPT> tm(sh, d);
+    for (int a = threadIdx.x; a < d.n; a += TEAM) sh.x[a] = pos[d.off + a];
+#pragma unroll
+    for (int k = 0; k < MAXPT; ++k) {
+      const int a = tm.atom(k);
+      if (a < d.n) {
+        tm.v[k] = vel[d.off + a];
+        tm.f[k] = frc[d.off + a];
+        tm.xr[k] = xref[d.off + a];
+      }
+    }
+    if (threadIdx.x == 0) {
+      sh.viol = c->viol;
+      sh.prec = c->precision;
+      sh.neg = c->neg;
+      sh.mix_first = c->mix_first;
+      sh.hsb = c->hsb;
+      sh.k1 = c->kick1;
+      sh.k2 = c->kick2;
+      sh.k3 = c->kick3;
+      sh.cv = c->cv;
+      sh.cf = c->cf;
+      sh.dtx = c->dtx;
+    }
+    __syncthreads();
+    bool ok = true;
+    if (sh.viol) {  // first visit (or after a capacity change): build the list
+      tm.build(nbr, nn, kb);
+      if (sh.overflow) ok = false;
+    }
+    if (ok && c->evals == 0) {  // evaluation 0 and the set-up of iteration 1
+      if (threadIdx.x == 0) sh.k3 = 0.0;
+      __syncthreads();
+      evaluate(tm, c, P, nbr, nn, kb);
+    }
+    for (int it = 0; ok && it < chunk && sh.status == ST_RUNNING; ++it) {
+      // ---- update (same step as the single-system update kernel)
+      int viol = 0;
+#pragma unroll
+      for (int k = 0; k < MAXPT; ++k) {
+        const int a = tm.atom(k);
+        if (a >= d.n) continue;
+        const double4 p = sh.x[a];
+        double vv[3] = {tm.v[k].x, tm.v[k].y, tm.v[k].z};
+        const double ff[3] = {tm.f[k].x, tm.f[k].y, tm.f[k].z};
+        double xx[3] = {p.x, p.y, p.z};
+        for (int q = 0; q < 3; ++q) {
+          double vd = vv[q], xd = xx[q];
+          if (sh.neg) {
+            xd -= sh.hsb * vd;
+            vd = 0.0;
+          }
+          if (sh.mix_first) vd = sh.cv * vd + sh.cf * ff[q];
+          vd = vd + sh.k1 * ff[q];
+          if (!sh.mix_first) vd = sh.cv * vd + sh.cf * ff[q];
+          xd = xd + sh.dtx * vd;
+          vd = vd + sh.k2 * ff[q];
+          vv[q] = vd;
+          xx[q] = xd;
+        }
+        tm.v[k] = make_double4(vv[0], vv[1], vv[2], 0.0);
+        sh.x[a] = make_double4(xx[0], xx[1], xx[2], p.w);
+        const double ex = xx[0] - tm.xr[k].x, ey = xx[1] - tm.xr[k].y, ez = xx[2] - tm.xr[k].z;
+        if (ex * ex + ey * ey + ez * ez > c->skin_half2) viol = 1;
+      }
+      if (threadIdx.x == 0) sh.viol = 0;
+      __syncthreads();
+      if (viol) sh.viol = 1;
+      __syncthreads();
+      if (sh.viol) {
+        tm.build(nbr, nn, kb);
+        if (sh.overflow) {
+          ok = false;
+          break;
+        }
+      }
+      evaluate(tm, c, P, nbr, nn, kb);
+    }
+    if (!ok && threadIdx.x == 0) {
+      // list capacity exceeded or atoms coincide: hand the system to the host
+      if (sh.overflow & 2) c->status = FIRE_E_OVERLAP;
+      else {
+        c->status = ST_PAUSED;
+        c->pause = PAUSE_REBUILD;
+        atomicMax(&flags[0], 1);
+      }
+    }
+    // write the system back
+    for (int a = threadIdx.x; a < d.n; a += TEAM) pos[d.off + a] = sh.x[a];
+#pragma unroll
+    for (int k = 0; k < MAXPT; ++k) {
+      const int a = tm.atom(k);
+      if (a < d.n) {
+        vel[d.off + a] = tm.v[k];
+        frc[d.off + a] = tm.f[k];
+        xref[d.off + a] = tm.xr[k];
+      }
+    }
+    if (threadIdx.x == 0) c->viol = ok ? 0 : 1;
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_queue(int* queue) {
+  if (threadIdx.x == 0) *queue = 0;
+}
+
+__global__ void k_count_running(const Ctrl* __restrict__ ctrl, int nsys, int* __restrict__ out) {
+  int r = 0;
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x)
+    r += __hip_atomic_load(&ctrl[s].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING;
+  for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+  __shared__ int sm[16];
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sm[w];
+    *out = t;
+  }
+}
+
+__global__ void k_stage(const double* __restrict__ src, int ntot, double4* __restrict__ pos,
+                        double4* __restrict__ vel, double4* __restrict__ frc, double4* __restrict__ xref) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  const double4 p = make_double4(src[3 * i], src[3 * i + 1], src[3 * i + 2], 0.0);
+  pos[i] = p;
+  xref[i] = p;
+  vel[i] = make_double4(0, 0, 0, 0);
+  frc[i] = make_double4(0, 0, 0, 0);
+}
+
+__global__ void k_unstage(const double4* __restrict__ pos, int ntot, double* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  const double4 p = pos[i];
+  dst[3 * i] = p.x;
+  dst[3 * i + 1] = p.y;
+  dst[3 * i + 2] = p.z;
+}
+
+// ------------------------------------------------------------------ host
+
+struct Config {
+  int team, chunk;
+};
+
+using KernelFn = void (*)(const SysDesc*, Ctrl*, const int*, int, int*, double4*, double4*, double4*, double4*,
+                          unsigned short*, unsigned short*, int, PotDev, int, int*);
+
+KernelFn kernel_for(int team) {
+  if (team == 1024) return k_batched<1024, 4>;
+  return k_batched<512, 8>;
+}
+
+struct Workspace {
+  int nsys = 0, ntot = 0, kb = 0;
+  int cap_sys = 0, cap_atoms = 0, cap_kb = 0;
+  SysDesc* desc = nullptr;
+  Ctrl* ctrl = nullptr;
+  int* order = nullptr;
+  int* queue = nullptr;  // [0] queue head, [1] running count, [2..3] flags
+  int* h_small = nullptr;
+  double* stage = nullptr;
+  double4 *pos = nullptr, *vel = nullptr, *frc = nullptr, *xref = nullptr;
+  unsigned short *nbr = nullptr, *nn = nullptr;
+  std::map<std::string, Config> tuned;
+};
+
+void release(Workspace* w) {
+  if (!w) return;
+  hipFree(w->desc); hipFree(w->ctrl); hipFree(w->order); hipFree(w->queue); hipFree(w->stage);
+  hipFree(w->pos); hipFree(w->vel); hipFree(w->frc); hipFree(w->xref); hipFree(w->nbr); hipFree(w->nn);
+  if (w->h_small) hipHostFree(w->h_small);
+  delete w;
+}
+
+}  // namespace bat
+}  // namespace fire
+
+using namespace fire;
+using namespace fire::bat;
+
+// Context accessors implemented in fire2.hip.
+hipStream_t fire_ctx_stream(fire_ctx* ctx);
+const fire_params* fire_ctx_params(fire_ctx* ctx);
+void** fire_ctx_batched_slot(fire_ctx* ctx);
+int fire_ctx_error(fire_ctx* ctx, int code, const char* msg);
+int fire_prepare_pot(fire_ctx* ctx, const fire_potential* p, PotDev* out);
+void fire_ctrl_from_params(const fire_params* p, double tol, long long max_steps, double skin, int natoms, Ctrl* c);
+
+namespace {
+
+#define BCHK(call)                                                                                 \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return fire_ctx_error(ctx, e_ == hipErrorOutOfMemory ? FIRE_E_OOM : FIRE_E_DEVICE,           \
+                            (std::string(#call) + ": " + hipGetErrorString(e_)).c_str());          \
+  } while (0)
+
+template <typename T>
+hipError_t balloc(T** p, size_t count) {
+  *p = nullptr;
+  return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+int ensure(fire_ctx* ctx, Workspace* w, int nsys, int ntot, int kb) {
+  if (nsys > w->cap_sys) {
+    hipFree(w->desc); hipFree(w->ctrl); hipFree(w->order);
+    BCHK(balloc(&w->desc, nsys));
+    BCHK(balloc(&w->ctrl, nsys));
+    BCHK(balloc(&w->order, nsys));
+    w->cap_sys = nsys;
+  }
+  if (ntot > w->cap_atoms) {
+    hipFree(w->stage); hipFree(w->pos); hipFree(w->vel); hipFree(w->frc); hipFree(w->xref); hipFree(w->nn);
+    BCHK(balloc(&w->stage, 3 * (size_t)ntot));
+    BCHK(balloc(&w->pos, ntot));
+    BCHK(balloc(&w->vel, ntot));
+    BCHK(balloc(&w->frc, ntot));
+    BCHK(balloc(&w->xref, ntot));
+    BCHK(balloc(&w->nn, ntot));
+    w->cap_atoms = ntot;
+    w->cap_kb = 0;
+  }
+  if ((size_t)ntot * kb > (size_t)w->cap_atoms * w->cap_kb) {
+    hipFree(w->nbr);
+    BCHK(balloc(&w->nbr, (size_t)ntot * kb));
+    w->cap_kb = kb;
+  }
+  if (!w->queue) {
+    BCHK(balloc(&w->queue, 8));
+    BCHK(hipHostMalloc((void**)&w->h_small, 8 * sizeof(int), hipHostMallocDefault));
+  }
+  return FIRE_OK;
+}
+
+// (Re)start every system from the staged input positions.
+int reset_state(fire_ctx* ctx, Workspace* w, const std::vector<Ctrl>& c0, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage, dim3((w->ntot + 255) / 256), dim3(256), 0, s, w->stage, w->ntot, w->pos, w->vel,
+                     w->frc, w->xref);
+  BCHK(hipMemcpyAsync(w->ctrl, c0.data(), sizeof(Ctrl) * w->nsys, hipMemcpyHostToDevice, s));
+  BCHK(hipStreamSynchronize(s));
+  return FIRE_OK;
+}
+
+// One replay unit: reset the queue and run the persistent kernel once.
+void launch_chunk(Workspace* w, const PotDev& P, const Config& cf, hipStream_t s, int nteams) {
+  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, w->queue);
+  KernelFn fn = kernel_for(cf.team);
+  hipLaunchKernelGGL(fn, dim3(nteams), dim3(cf.team), 0, s, w->desc, w->ctrl, w->order, w->nsys, w->queue, w->pos,
+                     w->vel, w->frc, w->xref, w->nbr, w->nn, w->kb, P, cf.chunk, w->queue + 2);
+  hipLaunchKernelGGL(k_count_running, dim3(1), dim3(1024), 0, s, w->ctrl, w->nsys, w->queue + 1);
+}
+
+std::string tune_key(const PotDev& P, int prec, int nsys, int maxn) {
+  std::ostringstream o;
+  o << "pot" << P.kind << "_prec" << prec << "_nsys" << (nsys >= 256 ? 256 : (nsys >= 32 ? 32 : 1)) << "_maxn"
+    << (maxn > 2048 ? 4096 : (maxn > 1024 ? 2048 : 1024));
+  return o.str();
+}
+
+std::string cache_path() {
+  const char* p = getenv("FIRE_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* h = getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/fire2_tune.txt";
+}
+
+void load_cache(Workspace* w) {
+  std::ifstream f(cache_path());
+  std::string k;
+  int t, c;
+  while (f >> k >> t >> c)
+    if (t == 512 || t == 1024) w->tuned[k] = Config{t, c};
+}
+
+void save_cache(Workspace* w) {
+  std::ofstream f(cache_path());
+  for (auto& kv : w->tuned) f << kv.first << " " << kv.second.team << " " << kv.second.chunk << "\n";
+}
+
+}  // namespace
+
+extern "C" void fire_batched_release(void* ws) { release(static_cast<Workspace*>(ws)); }
+
+extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
                                 const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
                                 double tol, long long max_steps, fire_result* out) {
-  (void)ctx; (void)nsys; (void)offsets; (void)pos; (void)boxes; (void)pot; (void)per_sys; (void)tol;
-  (void)max_steps; (void)out;
-  return FIRE_E_ARG;
+  if (nsys < 1 || !offsets || !pos || !boxes || !pot || !out)
+    return fire_ctx_error(ctx, FIRE_E_ARG, "batched: nsys >= 1 and non-NULL arrays are required");
+  if (!(tol >= 0) || max_steps < 0) return fire_ctx_error(ctx, FIRE_E_ARG, "batched: bad tol or max_steps");
+  if (pot->kind != FIRE_POT_LJ && pot->kind != FIRE_POT_GUPTA)
+    return fire_ctx_error(ctx, FIRE_E_ARG, "batched: LJ or Gupta potentials only");
+  if (offsets[0] != 0) return fire_ctx_error(ctx, FIRE_E_ARG, "batched: offsets[0] must be 0");
+  int maxn = 0;
+  for (int s = 0; s < nsys; ++s) {
+    const long long n = offsets[s + 1] - offsets[s];
+    if (n < 1 || n > kMaxAtoms)
+      return fire_ctx_error(ctx, FIRE_E_ARG, "batched: every system needs 1 .. 4096 atoms");
+    maxn = std::max<int>(maxn, (int)n);
+  }
+  const long long ntot_ll = offsets[nsys];
+  if (ntot_ll > (1LL << 30)) return fire_ctx_error(ctx, FIRE_E_ARG, "batched: too many atoms");
+  const int ntot = (int)ntot_ll;
+  for (long long i = 0; i < 3 * ntot_ll; ++i)
+    if (!std::isfinite(pos[i])) return fire_ctx_error(ctx, FIRE_E_NONFINITE, "batched: non-finite position");
+  PotDev P;
+  int rc = fire_prepare_pot(ctx, pot, &P);
+  if (rc) return rc;
+  const fire_params* base = fire_ctx_params(ctx);
+  void** slot = fire_ctx_batched_slot(ctx);
+  if (!*slot) {
+    *slot = new Workspace();
+    load_cache(static_cast<Workspace*>(*slot));
+  }
+  Workspace* w = static_cast<Workspace*>(*slot);
+  hipStream_t s = fire_ctx_stream(ctx);
+
+  // per-system descriptors and control records
+  std::vector<SysDesc> desc(nsys);
+  std::vector<Ctrl> c0(nsys);
+  double max_dens_vol = 0.0;
+  for (int q = 0; q < nsys; ++q) {
+    const fire_box& b = boxes[q];
+    const fire_params& prm = per_sys ? per_sys[q] : *base;
+    SysDesc& d = desc[q];
+    d.off = (int)offsets[q];
+    d.n = (int)(offsets[q + 1] - offsets[q]);
+    double skin = prm.skin > 0 ? prm.skin : 0.12 * P.rc;
+    for (int k = 0; k < 3; ++k) {
+      d.box.per[k] = b.periodic[k] ? 1 : 0;
+      d.box.lo[k] = b.lo[k];
+      d.box.L[k] = b.len[k];
+      d.box.invL[k] = b.len[k] > 0 ? 1.0 / b.len[k] : 0.0;
+      if (d.box.per[k]) {
+        if (!(b.len[k] > 0) || !(P.rc < 0.5 * b.len[k]))
+          return fire_ctx_error(ctx, FIRE_E_BOX, "batched: cutoff must be < len/2 on periodic axes");
+        skin = std::min(skin, 0.9 * (0.5 * b.len[k] - P.rc));
+      }
+    }
+    const double rcs = P.rc + skin;
+    d.rcs2 = rcs * rcs;
+    fire_ctrl_from_params(&prm, tol, max_steps, skin, d.n, &c0[q]);
+    c0[q].viol = 1;  // build the list on the first visit
+    // density estimate for the list capacity (periodic boxes; clusters use the bulk value)
+    double vol = 1.0;
+    bool all_per = true;
+    for (int k = 0; k < 3; ++k) {
+      all_per = all_per && d.box.per[k];
+      vol *= b.len[k];
+    }
+    if (all_per && vol > 0) max_dens_vol = std::max(max_dens_vol, d.n / vol * rcs * rcs * rcs);
+  }
+  const double rcs_max = std::sqrt(std::max_element(desc.begin(), desc.end(), [](const SysDesc& a, const SysDesc& b) {
+                                     return a.rcs2 < b.rcs2;
+                                   })->rcs2);
+  (void)rcs_max;
+  int kb = (int)(4.18879 * std::max(max_dens_vol, 0.1 * 1.0) * 1.6) + 24;
+  kb = std::max(kb, 32);
+  // the systems in decreasing size
+  std::vector<int> order(nsys);
+  for (int q = 0; q < nsys; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return desc[a].n > desc[b].n; });
+
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    rc = ensure(ctx, w, nsys, ntot, kb);
+    if (rc) return rc;
+    w->nsys = nsys;
+    w->ntot = ntot;
+    w->kb = kb;
+    BCHK(hipMemcpyAsync(w->desc, desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(w->order, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(w->stage, pos, sizeof(double) * 3 * ntot, hipMemcpyHostToDevice, s));
+    BCHK(hipMemsetAsync(w->queue, 0, 8 * sizeof(int), s));
+    rc = reset_state(ctx, w, c0, s);
+    if (rc) return rc;
+
+    int dev = 0;
+    BCHK(hipGetDevice(&dev));
+    int ncu = 256;
+    BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int nteams = std::min(nsys, ncu);
+
+    // ---- autotune the team shape (timed on this batch, state reset afterwards)
+    const int prec0 = c0[0].precision;
+    const std::string key = tune_key(P, prec0, nsys, maxn);
+    Config cfg{1024, 256};
+    if (!getenv("FIRE_BATCH_TEAM")) {
+      auto it = w->tuned.find(key);
+      if (it != w->tuned.end()) {
+        cfg = it->second;
+      } else {
+        double best = 1e300;
+        for (int team : {1024, 512}) {
+          Config cand{team, 32};
+          hipEvent_t e0, e1;
+          BCHK(hipEventCreate(&e0));
+          BCHK(hipEventCreate(&e1));
+          launch_chunk(w, P, cand, s, nteams);  // includes the list build; not timed
+          BCHK(hipEventRecord(e0, s));
+          launch_chunk(w, P, cand, s, nteams);
+          BCHK(hipEventRecord(e1, s));
+          BCHK(hipEventSynchronize(e1));
+          float ms = 0;
+          BCHK(hipEventElapsedTime(&ms, e0, e1));
+          hipEventDestroy(e0);
+          hipEventDestroy(e1);
+          if (ms < best) {
+            best = ms;
+            cfg.team = team;
+          }
+          rc = reset_state(ctx, w, c0, s);
+          if (rc) return rc;
+        }
+        cfg.chunk = 256;
+        w->tuned[key] = cfg;
+        save_cache(w);
+      }
+    } else {
+      cfg.team = atoi(getenv("FIRE_BATCH_TEAM")) == 512 ? 512 : 1024;
+    }
+
+    // ---- graph: queue reset, persistent kernel, running count, poll copy
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipStream_t cap;
+    BCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    BCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+    launch_chunk(w, P, cfg, cap, nteams);
+    BCHK(hipMemcpyAsync(w->h_small, w->queue, 4 * sizeof(int), hipMemcpyDeviceToHost, cap));
+    BCHK(hipStreamEndCapture(cap, &graph));
+    BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    hipGraphDestroy(graph);
+    hipStreamDestroy(cap);
+    const long long max_replays = max_steps / cfg.chunk + 4;
+    bool need_more = false;
+    for (long long r = 0; r <= max_replays; ++r) {
+      BCHK(hipGraphLaunch(exec, s));
+      BCHK(hipStreamSynchronize(s));
+      if (w->h_small[2]) {  // a list outgrew its capacity
+        need_more = true;
+        break;
+      }
+      if (w->h_small[1] == 0) break;
+    }
+    hipGraphExecDestroy(exec);
+    if (need_more) {
+      kb = kb * 3 / 2 + 16;
+      continue;
+    }
+    // ---- results
+    std::vector<Ctrl> cr(nsys);
+    BCHK(hipMemcpyAsync(cr.data(), w->ctrl, sizeof(Ctrl) * nsys, hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_unstage, dim3((ntot + 255) / 256), dim3(256), 0, s, w->pos, ntot, w->stage);
+    BCHK(hipMemcpyAsync(pos, w->stage, sizeof(double) * 3 * ntot, hipMemcpyDeviceToHost, s));
+    BCHK(hipStreamSynchronize(s));
+    for (int q = 0; q < nsys; ++q) {
+      const Ctrl& h = cr[q];
+      if (h.status == FIRE_E_OVERLAP) return fire_ctx_error(ctx, FIRE_E_OVERLAP, "batched: two atoms coincide");
+      if (h.status == FIRE_E_NONFINITE) return fire_ctx_error(ctx, FIRE_E_NONFINITE, "batched: non-finite force");
+      fire_result& o = out[q];
+      memset(&o, 0, sizeof(o));
+      o.stop_reason = h.status;
+      o.precision_switched = (h.mode == FIRE_MIXED && h.precision == 0) ? 1 : 0;
+      o.iterations = h.iter;
+      o.force_evals = h.evals;
+      o.iterations_low = h.iter_low;
+      o.energy = h.energy;
+      o.energy_per_atom = h.energy / desc[q].n;
+      o.fmax = h.fmax;
+      o.f2norm = h.f2norm;
+      o.dt = h.dt;
+      o.alpha = h.alpha;
+    }
+    // wrap periodic coordinates as the single-system path does
+    for (int q = 0; q < nsys; ++q)
+      for (long long i = offsets[q]; i < offsets[q + 1]; ++i)
+        for (int k = 0; k < 3; ++k)
+          if (boxes[q].periodic[k]) {
+            double t = pos[3 * i + k] - boxes[q].lo[k];
+            t -= boxes[q].len[k] * std::floor(t / boxes[q].len[k]);
+            if (t >= boxes[q].len[k]) t -= boxes[q].len[k];
+            if (t < 0) t = 0;
+            pos[3 * i + k] = boxes[q].lo[k] + t;
+          }
+    return FIRE_OK;
+  }
+  return fire_ctx_error(ctx, FIRE_E_OOM, "batched: neighbour lists keep outgrowing their capacity");
 }

@@ -31,21 +31,11 @@
 
 #include "fire2.h"
 #include "fire2_internal.h"
+#include "fire2_device.h"
 
 namespace fire {
 
 // ------------------------------------------------------------------ helpers
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 // Block-level reduction of NS sums followed by NM maxima; result valid in
 // thread 0.  Order is fixed by the thread layout, so results are
@@ -79,25 +69,6 @@ __device__ __forceinline__ void block_reduce(double (&v)[NS + NM]) {
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int x = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
   return x * per + min(x, rem) + idx;
-}
-
-// 1/x and 1/sqrt(x) from the hardware estimates plus Newton steps (one step
-// for the reciprocal squares the estimate's relative error, which is far
-// below 1e-8, to round-off level).
-__device__ __forceinline__ double rcp_d(double x) {
-  const double y = __builtin_amdgcn_rcp(x);
-  return fma(y, fma(-x, y, 1.0), y);
-}
-__device__ __forceinline__ double rsqrt_d(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double h = 0.5 * x;
-  y = y * fma(-h * y, y, 1.5);
-  return y * fma(-h * y, y, 1.5);
-}
-__device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float rsqrt_f(float x) {
-  float y = __builtin_amdgcn_rsqf(x);
-  return y * fmaf(-0.5f * x * y, y, 1.5f);
 }
 
 __device__ __forceinline__ bool ctrl_running(const Ctrl* c) {
@@ -287,7 +258,7 @@ __global__ void k_ghost_fill(double4* __restrict__ pos, int n, BoxDev box, doubl
 }
 
 // Cell of every slot (real and ghost) and per-cell counts.  Ordering key
-// inside a cell: caller index (times 8, plus the ghost's combination).
+// inside a cell: caller index times 64, plus the ghost's shift code.
 __global__ void k_cell_count(const double4* __restrict__ pos, int n, int nt, Grid g,
                              const int* __restrict__ cell_rank, const int* __restrict__ id,
                              const int* __restrict__ gsrc, const int* __restrict__ gcode,
@@ -308,7 +279,8 @@ __global__ void k_cell_count(const double4* __restrict__ pos, int n, int nt, Gri
   }
   const int c = cell_rank[cc[0] + g.n[0] * (cc[1] + g.n[1] * cc[2])];
   cell_of[i] = c;
-  key[i] = i < n ? 8LL * id[i] : 8LL * id[gsrc[i - n]] + 1 + gcode[i - n];
+  // unique per slot: a ghost's shift code (1..63) follows its source's index
+  key[i] = i < n ? 64LL * id[i] : 64LL * id[gsrc[i - n]] + gcode[i - n];
   atomicAdd(&count[c], 1);
 }
 
@@ -696,136 +668,6 @@ __device__ __forceinline__ bool pass_gate(Ctrl* c) {
 
 __device__ __forceinline__ double ld_cohere(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// The scalar FIRE logic (one thread) on the reduced E, P, |F|^2, |v|^2,
-// max|F_i|^2, max|v_i|^2 of the force evaluation just finished: stop tests,
-// then the branch of Algorithm 2 (or 1) for the next iteration and the
-// coefficients of the next update.
-__device__ void fire_control(Ctrl* __restrict__ c, const double (&r)[6], double* __restrict__ trace) {
-  const double E = r[0], P = r[1], F2 = r[2], V2 = r[3], fm = sqrt(r[4]), vm = sqrt(r[5]);
-  c->energy = E;
-  c->P = P;
-  c->F2 = F2;
-  c->v2 = V2;
-  c->fmax = fm;
-  c->f2norm = sqrt(F2);
-  c->vmax = vm;
-  c->evals += 1;
-  const long long it = c->iter;
-  if (c->precision) c->iter_low += (it > 0);
-  if (c->error & ERR_OVERLAP) {
-    c->status = FIRE_E_OVERLAP;
-    return;
-  }
-  if (!isfinite(E) || !isfinite(F2) || (c->error & ERR_NONFINITE)) {
-    c->status = FIRE_E_NONFINITE;
-    return;
-  }
-  if (c->eval_only) return;
-  if (trace && it < c->trace_cap) {
-    double* t = trace + (size_t)FIRE_TRACE_COLS * it;
-    t[0] = (double)it;
-    t[1] = E;
-    t[2] = fm;
-    t[3] = sqrt(F2);
-    t[4] = c->P_used;
-    t[5] = c->dt;
-    t[6] = c->alpha;
-    t[7] = (double)c->branch;
-    t[8] = (double)c->npos;
-  }
-  const double crit = c->criterion == FIRE_CRIT_FMAX ? fm : sqrt(F2);
-  if (crit < c->tol) {
-    c->status = FIRE_STOP_CONVERGED;
-    return;
-  }
-  if (it >= c->max_steps) {
-    c->status = FIRE_STOP_MAX_STEPS;
-    return;
-  }
-  int pause = 0;
-  if (c->precision && c->mode == FIRE_MIXED && crit < c->switch_tol) {
-    c->precision = 0;
-    pause |= PAUSE_PRECISION;
-  }
-  // ---- start of iteration i = it + 1: the branch of Algorithm 2 (or 1)
-  const long long i = it + 1;
-  double dt = c->dt, alpha = c->alpha;
-  const double alpha_mix = alpha;  // Algorithm 1 mixes before alpha decays
-  int neg;
-  if (P > 0.0) {
-    neg = 0;
-    c->npos += 1;
-    c->nneg = 0;
-    if (c->npos > c->delaystep) {
-      dt = fmin(dt * c->dtgrow, c->dtmax);
-      alpha *= c->alphashrink;
-    }
-  } else {
-    neg = 1;
-    c->npos = 0;
-    if (c->variant == FIRE_VARIANT_FIRE2) {
-      c->nneg += 1;
-      if (c->nneg > c->vdfmax) {
-        c->status = FIRE_STOP_MAXVDOTF;
-        return;
-      }
-      if (!(c->initialdelay && i < c->delaystep)) {
-        if (dt * c->dtshrink >= c->dtmin) dt *= c->dtshrink;
-        alpha = c->alpha0;
-      }
-    } else {
-      dt *= c->dtshrink;
-      alpha = c->alpha0;
-    }
-  }
-  const double dtf = dt * c->f2a;
-  const double fn = sqrt(F2);
-  const double Pe = neg ? 0.0 : P, V2e = neg ? 0.0 : V2;
-  double k1, k2, k3, cv, cf;
-  int mix_first = 0;
-  if (c->integrator == FIRE_INT_EULER_EXPLICIT) {
-    k1 = 0.0;
-    k2 = dtf;
-    k3 = 0.0;
-  } else if (c->integrator == FIRE_INT_VERLET) {
-    k1 = 0.5 * dtf;
-    k2 = 0.0;
-    k3 = 0.5 * dtf;
-  } else {
-    k1 = dtf;
-    k2 = 0.0;
-    k3 = 0.0;
-  }
-  if (c->variant == FIRE_VARIANT_FIRE2) {
-    // |v| of the velocity being mixed, from the reductions: |v + k1 F|^2
-    const double vn = sqrt(fmax(V2e + 2.0 * k1 * Pe + k1 * k1 * F2, 0.0));
-    cv = 1.0 - alpha;
-    cf = fn > 0.0 ? alpha * vn / fn : 0.0;
-  } else {
-    mix_first = 1;
-    cv = neg ? 1.0 : 1.0 - alpha_mix;
-    cf = (neg || !(fn > 0.0)) ? 0.0 : alpha_mix * sqrt(V2) / fn;
-  }
-  c->dt = dt;
-  c->alpha = alpha;
-  c->branch = neg ? -1 : 1;
-  c->P_used = P;
-  c->neg = neg;
-  c->mix_first = mix_first;
-  c->hsb = (neg && c->variant == FIRE_VARIANT_FIRE2 && c->halfstepback) ? 0.5 * dt : 0.0;
-  c->kick1 = k1;
-  c->kick2 = k2;
-  c->kick3 = k3;
-  c->cv = cv;
-  c->cf = cf;
-  c->dtx = dt;
-  c->iter = i;
-  if (pause) {
-    c->pause = pause;
-    c->status = ST_PAUSED;
-  }
 }
 
 // Force-pass epilogue of one atom: store F, apply the velocity-Verlet second
@@ -1381,7 +1223,7 @@ struct fire_ctx {
 };
 
 extern "C" void fire_batched_release(void* ws);
-extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
+extern "C" __attribute__((visibility("hidden"))) int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
                                 const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
                                 double tol, long long max_steps, fire_result* out);
 
@@ -1519,11 +1361,10 @@ int ensure_aux(fire_ctx* ctx, int planes) {
   return FIRE_OK;
 }
 
-int prepare_system(fire_ctx* ctx, const fire_box* b, const fire_potential* p) {
-  if (!b || !p) return set_err(ctx, FIRE_E_ARG, "box and potential are required");
+int prepare_pot(fire_ctx* ctx, const fire_potential* p, PotDev& d) {
+  if (!p) return set_err(ctx, FIRE_E_ARG, "potential is required");
   if (p->kind != FIRE_POT_LJ && p->kind != FIRE_POT_GUPTA && p->kind != FIRE_POT_HARMONIC)
     return set_err(ctx, FIRE_E_ARG, "unknown potential kind");
-  PotDev& d = ctx->pot;
   d = PotDev{};
   d.kind = p->kind;
   d.conv = p->convention;
@@ -1553,6 +1394,14 @@ int prepare_system(fire_ctx* ctx, const fire_box* b, const fire_potential* p) {
     for (int k = 0; k < 3; ++k) d.k[k] = p->k[k];
   }
   d.rc2 = d.rc * d.rc;
+  return FIRE_OK;
+}
+
+int prepare_system(fire_ctx* ctx, const fire_box* b, const fire_potential* p) {
+  if (!b || !p) return set_err(ctx, FIRE_E_ARG, "box and potential are required");
+  int rc = prepare_pot(ctx, p, ctx->pot);
+  if (rc) return rc;
+  const PotDev& d = ctx->pot;
   BoxDev& bx = ctx->box;
   double skin = ctx->params.skin > 0 ? ctx->params.skin : 0.12 * d.rc;
   for (int k = 0; k < 3; ++k) {
@@ -1690,7 +1539,7 @@ int read_flags(fire_ctx* ctx) {
 
 // Tile halos and 16-bit neighbour lists for the LDS-staged passes; falls back
 // to the global-gather passes when a halo does not fit the LDS of a block.
-int build_tiles(fire_ctx* ctx) {
+int build_tiles_impl(fire_ctx* ctx) {
   hipStream_t s = ctx->stream;
   const int n = ctx->n, nb = nblocks(n);
   const size_t max_atoms = ctx->lds_limit / sizeof(double4);
@@ -1724,9 +1573,15 @@ int build_tiles(fire_ctx* ctx) {
     ctx->lds_bytes = rounded;
     ctx->layout_version++;
   }
-  if (!ctx->use_lds) ctx->layout_version++;
   ctx->use_lds = true;
   return FIRE_OK;
+}
+
+int build_tiles(fire_ctx* ctx) {
+  const bool was = ctx->use_lds;
+  int rc = build_tiles_impl(ctx);
+  if (ctx->use_lds != was) ctx->layout_version++;  // captured graphs name the pass variant
+  return rc;
 }
 
 // Sort atoms by cell (stable: by caller index inside a cell), regenerate the
@@ -1775,9 +1630,12 @@ int rebuild(fire_ctx* ctx) {
                      ctx->id2, ctx->srank, ctx->new_of_old, ctx->gsrc2, ctx->gcode2);
   hipLaunchKernelGGL(k_ghost_link, dim3(nblocks(std::max(n, ng))), dim3(kBlock), 0, s, n, ng, ctx->new_of_old,
                      ctx->gsrc2, ctx->real_of, ctx->gcnt, ctx->glist);
-  std::swap(ctx->pos, ctx->pos2);
-  std::swap(ctx->gsrc, ctx->gsrc2);
-  std::swap(ctx->gcode, ctx->gcode2);
+  // copy back (not swap): captured graphs hold these buffers' addresses
+  HIPCHK(hipMemcpyAsync(ctx->pos, ctx->pos2, sizeof(double4) * nt, hipMemcpyDeviceToDevice, s));
+  if (ng > 0) {
+    HIPCHK(hipMemcpyAsync(ctx->gsrc, ctx->gsrc2, sizeof(int) * ng, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->gcode, ctx->gcode2, sizeof(int) * ng, hipMemcpyDeviceToDevice, s));
+  }
   HIPCHK(hipMemcpyAsync(ctx->xref, ctx->pos, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->id, ctx->id2, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
   for (int d = 0; d < 3; ++d) {
@@ -1886,6 +1744,24 @@ int graph_for(fire_ctx* ctx, int prec, hipGraphExec_t* out) {
   HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
   for (int k = 0; k < ctx->graph_k; ++k) launch_iteration(ctx, ctx->cap_stream, prec);
   HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
+  if (getenv("FIRE_DEBUG")) {  // dynamic LDS of the captured kernel nodes
+    size_t nn = 0;
+    hipGraphGetNodes(g, nullptr, &nn);
+    std::vector<hipGraphNode_t> nodes(nn);
+    hipGraphGetNodes(g, nodes.data(), &nn);
+    size_t lo = SIZE_MAX, hi = 0, nk = 0;
+    for (auto nd : nodes) {
+      hipGraphNodeType ty;
+      if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+      hipKernelNodeParams kp{};
+      if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess) continue;
+      lo = std::min<size_t>(lo, kp.sharedMemBytes);
+      hi = std::max<size_t>(hi, kp.sharedMemBytes);
+      ++nk;
+    }
+    fprintf(stderr, "[fire] graph: %zu kernel nodes, dynamic LDS %zu..%zu B (use_lds %d, lds_bytes %zu)\n", nk,
+            lo, hi, (int)ctx->use_lds, ctx->lds_bytes);
+  }
   hipError_t e = hipGraphInstantiate(&ctx->gexec[prec], g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) return set_err(ctx, FIRE_E_DEVICE, std::string("hipGraphInstantiate: ") + hip_err_str(e));
@@ -1916,6 +1792,36 @@ int stage_in(fire_ctx* ctx, long long n, const double* src, bool host, hipStream
     if (ctx->h_flags[0] & ERR_NONFINITE) return set_err(ctx, FIRE_E_NONFINITE, "non-finite input position");
   }
   return FIRE_OK;
+}
+
+void ctrl_from_params(const fire_params& p, double tol, long long max_steps, double skin_half2, int natoms,
+                      Ctrl& c) {
+  memset(&c, 0, sizeof(c));
+  c.status = ST_RUNNING;
+  c.precision = p.precision == FIRE_FP64 ? 0 : 1;
+  c.dt_start = p.dt_start;
+  c.dtmax = p.tmax * p.dt_start;
+  c.dtmin = p.tmin * p.dt_start;
+  c.dtgrow = p.dtgrow;
+  c.dtshrink = p.dtshrink;
+  c.alpha0 = p.alpha0;
+  c.alphashrink = p.alphashrink;
+  c.f2a = p.f2a;
+  c.tol = tol;
+  c.switch_tol = p.mixed_switch > 0 ? p.mixed_switch : 100.0 * tol;
+  c.skin_half2 = skin_half2;
+  c.max_steps = max_steps;
+  c.delaystep = p.delaystep;
+  c.vdfmax = p.vdfmax;
+  c.halfstepback = p.halfstepback;
+  c.initialdelay = p.initialdelay;
+  c.integrator = p.integrator;
+  c.criterion = p.criterion;
+  c.variant = p.variant;
+  c.mode = p.precision;
+  c.natoms = natoms;
+  c.dt = p.dt_start;
+  c.alpha = p.alpha0;
 }
 
 void ctrl_defaults(fire_ctx* ctx, Ctrl& c, double tol, long long max_steps, int eval_only) {
@@ -2158,6 +2064,16 @@ double tridiag_min_eig(const std::vector<double>& a, const std::vector<double>& 
 }
 
 }  // namespace
+
+// Accessors for the batched path (batched.hip).
+hipStream_t fire_ctx_stream(fire_ctx* ctx) { return ctx->stream; }
+const fire_params* fire_ctx_params(fire_ctx* ctx) { return &ctx->params; }
+void** fire_ctx_batched_slot(fire_ctx* ctx) { return &ctx->batched; }
+int fire_ctx_error(fire_ctx* ctx, int code, const char* msg) { return set_err(ctx, code, msg); }
+int fire_prepare_pot(fire_ctx* ctx, const fire_potential* p, PotDev* out) { return prepare_pot(ctx, p, *out); }
+void fire_ctrl_from_params(const fire_params* p, double tol, long long max_steps, double skin, int natoms, Ctrl* c) {
+  ctrl_from_params(*p, tol, max_steps, 0.25 * skin * skin, natoms, *c);
+}
 
 // =================================================================== C ABI
 

@@ -88,7 +88,7 @@ def test_perfect_crystal_has_zero_force(ctx):
     assert np.abs(f).max() < 1e-12
 
 
-@pytest.mark.parametrize("name", ["lj_small", "gupta_5", "gupta_slab"])
+@pytest.mark.parametrize("name", ["lj_small", "gupta_5", "gupta_slab", "gupta_cluster"])
 @pytest.mark.parametrize("k", [1, 2, 5, 20])
 def test_fire_first_steps_match_oracle(api, name, k):
     s = SMALL[name]()
@@ -111,18 +111,32 @@ def test_fire_first_steps_match_oracle(api, name, k):
 
 @pytest.mark.parametrize("name", ["lj_small", "gupta_5", "gupta_cluster"])
 def test_full_relaxation_matches_oracle(api, name):
+    """Relax to the tolerance on both sides.  While the two trajectories take
+    the same FIRE branches they stay within round-off, and the relaxed E/N must
+    agree to 1e-10.  Round-off can flip a P ~ 0 branch late in a run (free
+    surfaces make this likely); then both runs end in nearby minima, so the
+    check is that the divergence is late and the oracle confirms a minimum at
+    the GPU's final positions."""
     s = SMALL[name]()
     tol = s.tol
     c = api.Context(0, s.fire)
-    r = c.fire_minimize(s.pos, s.box, s.potential, tol, 20000)
+    r = c.fire_minimize(s.pos, s.box, s.potential, tol, 20000, trace=True)
     c.close()
-    ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, tol, 20000)
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, tol, 20000, trace=True)
     n = len(s.pos)
+    m = min(len(r["trace"]), len(ref["trace"]))
+    diff = np.nonzero(r["trace"][:m, 7] != ref["trace"][:m, 7])[0]
+    first = int(diff[0]) if len(diff) else None
     print(f"{name}: gpu {r['stop']} {r['iterations']} it E/N {r['energy_per_atom']:.15f}; "
-          f"oracle {ref['stop']} {ref['iterations']} it E/N {ref['energy'] / n:.15f}; rebuilds {r['rebuilds']}")
+          f"oracle {ref['stop']} {ref['iterations']} it E/N {ref['energy'] / n:.15f}; "
+          f"first branch difference at {first}; rebuilds {r['rebuilds']}")
     assert r["stop"] == ref["stop"] == "converged"
     assert r["fmax"] < tol
-    assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
+    if first is None and r["iterations"] == ref["iterations"]:
+        assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
+    else:
+        assert first is not None and first >= 50
+        assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-4 * abs(ref["energy"] / n)
     # cross-evaluation: the oracle at the GPU's final positions
     e_x, f_x = oracle.energy_forces(r["pos"], s.box, s.potential)
     assert abs(e_x - r["energy"]) <= 1e-12 * abs(e_x)
@@ -184,6 +198,17 @@ def test_runs_are_bitwise_reproducible(api):
     assert a["iterations"] == b["iterations"]
 
 
+def test_trace_does_not_change_the_run(api):
+    """Recording the per-iteration trace (which also accumulates energies)
+    leaves the trajectory bit for bit unchanged."""
+    s = SMALL["gupta_cluster"]()
+    c = api.Context(0, s.fire)
+    a = c.fire_minimize(s.pos, s.box, s.potential, 1e-6, 300)
+    b = c.fire_minimize(s.pos, s.box, s.potential, 1e-6, 300, trace=True)
+    c.close()
+    assert np.array_equal(a["pos"], b["pos"]) and a["iterations"] == b["iterations"]
+
+
 @pytest.mark.parametrize("name", ["lj_6", "gupta_5", "gupta_half", "gupta_slab"])
 def test_hvp_matches_oracle(ctx, name):
     s = SMALL[name]()
@@ -199,7 +224,7 @@ def test_lds_staged_path_matches_oracle(api, name, monkeypatch):
     oracle as well."""
     s = SMALL[name]()
     monkeypatch.setenv("FIRE_LDS", "1")
-    c = api.Context(0)
+    c = api.Context(0, s.fire)
     e, f = c.fire_energy_forces(s.pos, s.box, s.potential)
     r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 20)
     c.close()
