@@ -106,6 +106,96 @@ def kernel_time_ms(ctx, reps: int) -> float:
     return a.elapsed_time(b) / reps
 
 
+def bench_batched(args):
+    """The batched form: 512 independent EAM-form relaxations (500-4000 atoms,
+    clusters and periodic boxes) in one persistent launch, positions resident
+    in HBM, against the plain FP64 single-system path on a sample of the same
+    systems, one relaxation after another."""
+    import torch
+    from paper_1908_02038_amd import api, inputs
+    systems = inputs.batched()
+    pot, fire, tol = systems[0].potential, systems[0].fire, systems[0].tol
+    offs = np.cumsum([0] + [len(s.pos) for s in systems])
+    boxes = [s.box for s in systems]
+    src = torch.tensor(np.concatenate([s.pos for s in systems]), dtype=torch.float64, device="cuda")
+    work = torch.empty_like(src)
+    ctx = api.Context(0, fire)
+    for _ in range(max(1, args.warmup)):  # the first call also autotunes the team shape
+        work.copy_(src)
+        ctx.fire_minimize_batched_dev(work, offs, boxes, pot, tol, args.max_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(args.steps):
+        work.copy_(src)
+        res = ctx.fire_minimize_batched_dev(work, offs, boxes, pot, tol, args.max_steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.close()
+    atom_evals = sum(len(s.pos) * r["force_evals"] for s, r in zip(systems, res))
+    iters = sum(r["iterations"] for r in res)
+    stops = [r["stop"] for r in res]
+    # plain FP64 path, one system after another, on every 16th system
+    sample = list(range(0, len(systems), 16))
+    ctx = api.Context(0, fire, precision="fp64")
+    dev = [torch.tensor(systems[k].pos, dtype=torch.float64, device="cuda") for k in sample]
+    w = [torch.empty_like(d) for d in dev]
+    for d, x in zip(dev, w):
+        x.copy_(d)
+    ctx.fire_minimize_dev(w[0], systems[sample[0]].box, pot, tol, args.max_steps)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_evals = plain_iters = 0
+    for k, d, x in zip(sample, dev, w):
+        x.copy_(d)
+        r = ctx.fire_minimize_dev(x, systems[k].box, pot, tol, args.max_steps)
+        plain_evals += len(systems[k].pos) * r["force_evals"]
+        plain_iters += r["iterations"]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    ctx.close()
+    val = atom_evals / dt
+    plain = plain_evals / tp
+    log(f"[bench] batched: {len(systems)} systems, {offs[-1]} atoms, {dt * 1e3:.1f} ms per batch, "
+        f"{val:.3e} atom-force-evals/s; plain FP64 path on {len(sample)} of them: {plain:.3e}")
+    return {
+        "workload": f"{len(systems)} Gupta systems, {int(offs[-1])} atoms, 500-4000 atoms each",
+        "value": val,
+        "unit": "atom-force-evals/s",
+        "ms_per_batch": dt * 1e3,
+        "steps_per_s": iters / dt,
+        "all_converged": all(x == "converged" for x in stops),
+        "max_iterations": max(r["iterations"] for r in res),
+        "plain_fp64_value": plain,
+        "plain_fp64_steps_per_s": plain_iters / tp,
+        "plain_sample": f"every 16th system ({len(sample)}), relaxed one after another by fire_minimize_dev",
+        "speedup_vs_plain": val / plain,
+    }
+
+
+COPY_BYTES = 256 << 20
+
+
+def kernel_only(args, s, pos0):
+    """Force pass alone (list built from the workload's start positions), then
+    one plain device copy of COPY_BYTES: the copy reads and writes exactly
+    COPY_BYTES each, which calibrates the byte counters of the same run."""
+    import torch
+    from paper_1908_02038_amd import api
+    ctx = api.Context(0, s.fire, precision="fp64")
+    ctx.fire_energy_forces_dev(pos0, s.box, s.potential)
+    torch.cuda.synchronize()
+    kt = kernel_time_ms(ctx, args.kernel_reps)
+    ctx.close()
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_only": args.workload, "atoms": len(s.pos), "ms_per_launch": kt,
+                      "reps": args.kernel_reps, "copy_bytes": COPY_BYTES}), flush=True)
+
+
 def cpu_baseline(s, budget_s: float):
     """The oracle as it stands (brute-force pair sums, OpenMP over atoms) on a
     bounded sample: the first FIRE 2.0 iterations of the same workload."""
@@ -114,7 +204,7 @@ def cpu_baseline(s, budget_s: float):
     t0 = time.perf_counter()
     oracle.energy_forces(s.pos, s.box, s.potential)
     t1 = time.perf_counter() - t0
-    steps = max(0, min(10, int(budget_s / max(t1, 1e-9)) - 2))
+    steps = max(1, min(10, int(budget_s / max(t1, 1e-9)) - 2))
     t0 = time.perf_counter()
     r = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, s.tol, steps)
     dt = time.perf_counter() - t0
@@ -138,9 +228,13 @@ def main():
     ap.add_argument("--workload", default="lj_bulk", choices=["lj_small", "lj_bulk", "gupta_bulk", "gupta_slab"])
     ap.add_argument("--max-steps", type=int, default=100000)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the dominant force pass (reps launches) and a plain copy of known size; "
+                         "for hardware-counter runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -157,6 +251,9 @@ def main():
     kind = s.potential["kind"]
     log(f"[bench] workload {args.workload}: {n} atoms, potential {kind}, tol {s.tol}")
     pos0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    if args.kernel_only:
+        kernel_only(args, s, pos0)
+        return
 
     # ---- FP64 plain path (headline)
     ctx = api.Context(0, s.fire, precision="fp64")
@@ -240,6 +337,9 @@ def main():
         }
         log(f"[bench] mixed: {rm['iterations']} iterations ({rm['iterations_low']} FP32), "
             f"{dtm / args.steps * 1e3:.1f} ms/relaxation, FP32 force pass {ktm * 1e3:.1f} us")
+
+    if not args.no_batched:
+        out["batched"] = bench_batched(args)
 
     if not args.no_cpu:
         log("[bench] cpu oracle baseline ...")

@@ -18,7 +18,8 @@
  *     void* (NULL is the legacy default stream, as in HIP); they enqueue on
  *     that stream, after the work already queued there.
  *     fire_energy_forces_dev and fire_hvp_dev do not synchronise;
- *     fire_minimize_dev polls a small status word and returns when done.
+ *     fire_minimize_dev and fire_minimize_batched_dev poll small status
+ *     words and return when done.
  *   - The caller owns every array it passes; the context owns its device
  *     work buffers and reuses them across calls.  A context is not
  *     thread-safe: calls on one context must not overlap.
@@ -206,6 +207,13 @@ int fire_hvp_dev(fire_ctx* ctx, long long n, const double* d_pos, const double* 
 int fire_minimize_dev(fire_ctx* ctx, long long n, double* d_pos, const fire_box* box,
                       const fire_potential* pot, double tol, long long max_steps, fire_result* out,
                       void* stream);
+/* fire_minimize_batched on device positions d_pos ([offsets[nsys]][3], in
+ * place); offsets, boxes, per_sys and out stay in host memory.  Returns when
+ * every system has stopped.  A non-finite position is not screened on the
+ * host: its system ends with FIRE_E_NONFINITE from its first force pass. */
+int fire_minimize_batched_dev(fire_ctx* ctx, int nsys, const long long* offsets, double* d_pos,
+                              const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
+                              double tol, long long max_steps, fire_result* out, void* stream);
 
 /* Measurement hook: re-run the force evaluation (density and force passes for
  * the EAM form) of the system left by the last call on ctx, at its current

@@ -28,7 +28,7 @@ EXPORTS = [
     "fire_params_default", "fire_init", "fire_finalize", "fire_set_params", "fire_get_params",
     "fire_last_error", "fire_stop_name", "fire_energy_forces", "fire_minimize", "fire_minimize_traced",
     "fire_hvp", "fire_lowest_curvature", "fire_minimize_batched", "fire_energy_forces_dev", "fire_hvp_dev",
-    "fire_minimize_dev", "fire_repeat_forces_dev",
+    "fire_minimize_dev", "fire_minimize_batched_dev", "fire_repeat_forces_dev",
 ]
 
 
@@ -122,6 +122,9 @@ def load(path: str = LIB_PATH):
                                  ctypes.c_void_p, ctypes.c_void_p]
     lib.fire_minimize_dev.argtypes = [ctx_p, ll, ctypes.c_void_p, P(fire_box), P(fire_potential),
                                       ctypes.c_double, ll, P(fire_result), ctypes.c_void_p]
+    lib.fire_minimize_batched_dev.argtypes = [ctx_p, ctypes.c_int, P(ll), ctypes.c_void_p, P(fire_box),
+                                              P(fire_potential), P(fire_params), ctypes.c_double, ll,
+                                              P(fire_result), ctypes.c_void_p]
     lib.fire_repeat_forces_dev.argtypes = [ctx_p, ctypes.c_int, ctypes.c_void_p]
     _lib = lib
     return lib

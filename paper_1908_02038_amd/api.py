@@ -205,6 +205,27 @@ class Context:
         out_pos = [allpos[offs[s]:offs[s + 1]].copy() for s in range(len(systems))]
         return out_pos, [_result(r) for r in res]
 
+    def fire_minimize_batched_dev(self, pos, offsets, boxes, pot, tol: float, max_steps: int,
+                                  per_sys: list | None = None):
+        """pos: (ntot,3) float64 cuda tensor, relaxed in place; offsets: nsys+1
+        atom offsets; boxes: nsys boxes.  Returns the list of result dicts."""
+        import torch
+        assert pos.is_cuda and pos.dtype == torch.float64 and pos.is_contiguous()
+        nsys = len(boxes)
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        assert offs.shape == (nsys + 1,) and offs[-1] == pos.shape[0]
+        bx = (L.fire_box * nsys)(*[make_box(b) for b in boxes])
+        prm = None
+        if per_sys is not None:
+            prm = (L.fire_params * nsys)(*[make_params(f) for f in per_sys])
+        res = (L.fire_result * nsys)()
+        p = make_potential(pot)
+        self._check(self.lib.fire_minimize_batched_dev(
+            self.handle, nsys, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+            ctypes.c_void_p(pos.data_ptr()), bx, ctypes.byref(p), prm, float(tol), int(max_steps), res,
+            self._stream()))
+        return [_result(r) for r in res]
+
     # -------------------------------------------------------- device tensors
     @staticmethod
     def _stream():

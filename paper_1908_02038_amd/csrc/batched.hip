@@ -585,13 +585,28 @@ __global__ void k_stage(const double* __restrict__ src, int ntot, double4* __res
   frc[i] = make_double4(0, 0, 0, 0);
 }
 
-__global__ void k_unstage(const double4* __restrict__ pos, int ntot, double* __restrict__ dst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ntot) return;
-  const double4 p = pos[i];
-  dst[3 * i] = p.x;
-  dst[3 * i + 1] = p.y;
-  dst[3 * i + 2] = p.z;
+// Positions of system blockIdx.x back to the caller's AoS layout; periodic
+// axes wrapped into [lo, lo + len) as the single-system path returns them.
+__global__ void k_unstage(const double4* __restrict__ pos, const SysDesc* __restrict__ desc,
+                          double* __restrict__ dst) {
+  const SysDesc d = desc[blockIdx.x];
+  for (int a = threadIdx.x; a < d.n; a += blockDim.x) {
+    const int i = d.off + a;
+    const double4 p = pos[i];
+    double x[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (d.box.per[k]) {
+        double t = x[k] - d.box.lo[k];
+        t -= d.box.L[k] * floor(t / d.box.L[k]);
+        if (t >= d.box.L[k]) t -= d.box.L[k];
+        if (t < 0) t = 0;
+        x[k] = d.box.lo[k] + t;
+      }
+    dst[3 * i] = x[0];
+    dst[3 * i + 1] = x[1];
+    dst[3 * i + 2] = x[2];
+  }
 }
 
 // ------------------------------------------------------------------ host
@@ -740,9 +755,9 @@ void save_cache(Workspace* w) {
 
 extern "C" void fire_batched_release(void* ws) { release(static_cast<Workspace*>(ws)); }
 
-extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
+extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos, bool host,
                                 const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
-                                double tol, long long max_steps, fire_result* out) {
+                                double tol, long long max_steps, fire_result* out, hipStream_t s) {
   if (nsys < 1 || !offsets || !pos || !boxes || !pot || !out)
     return fire_ctx_error(ctx, FIRE_E_ARG, "batched: nsys >= 1 and non-NULL arrays are required");
   if (!(tol >= 0) || max_steps < 0) return fire_ctx_error(ctx, FIRE_E_ARG, "batched: bad tol or max_steps");
@@ -759,8 +774,9 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
   const long long ntot_ll = offsets[nsys];
   if (ntot_ll > (1LL << 30)) return fire_ctx_error(ctx, FIRE_E_ARG, "batched: too many atoms");
   const int ntot = (int)ntot_ll;
-  for (long long i = 0; i < 3 * ntot_ll; ++i)
-    if (!std::isfinite(pos[i])) return fire_ctx_error(ctx, FIRE_E_NONFINITE, "batched: non-finite position");
+  if (host)  // device positions: a non-finite one ends its system with FIRE_E_NONFINITE
+    for (long long i = 0; i < 3 * ntot_ll; ++i)
+      if (!std::isfinite(pos[i])) return fire_ctx_error(ctx, FIRE_E_NONFINITE, "batched: non-finite position");
   PotDev P;
   int rc = fire_prepare_pot(ctx, pot, &P);
   if (rc) return rc;
@@ -771,7 +787,6 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     load_cache(static_cast<Workspace*>(*slot));
   }
   Workspace* w = static_cast<Workspace*>(*slot);
-  hipStream_t s = fire_ctx_stream(ctx);
 
   // per-system descriptors and control records
   std::vector<SysDesc> desc(nsys);
@@ -827,7 +842,8 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     w->kb = kb;
     BCHK(hipMemcpyAsync(w->desc, desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, s));
     BCHK(hipMemcpyAsync(w->order, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, s));
-    BCHK(hipMemcpyAsync(w->stage, pos, sizeof(double) * 3 * ntot, hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(w->stage, pos, sizeof(double) * 3 * ntot,
+                        host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
     BCHK(hipMemsetAsync(w->queue, 0, 8 * sizeof(int), s));
     rc = reset_state(ctx, w, c0, s);
     if (rc) return rc;
@@ -908,8 +924,9 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     // ---- results
     std::vector<Ctrl> cr(nsys);
     BCHK(hipMemcpyAsync(cr.data(), w->ctrl, sizeof(Ctrl) * nsys, hipMemcpyDeviceToHost, s));
-    hipLaunchKernelGGL(k_unstage, dim3((ntot + 255) / 256), dim3(256), 0, s, w->pos, ntot, w->stage);
-    BCHK(hipMemcpyAsync(pos, w->stage, sizeof(double) * 3 * ntot, hipMemcpyDeviceToHost, s));
+    // positions back in caller order, periodic axes wrapped into [lo, lo + len)
+    hipLaunchKernelGGL(k_unstage, dim3(nsys), dim3(256), 0, s, w->pos, w->desc, host ? w->stage : pos);
+    if (host) BCHK(hipMemcpyAsync(pos, w->stage, sizeof(double) * 3 * ntot, hipMemcpyDeviceToHost, s));
     BCHK(hipStreamSynchronize(s));
     for (int q = 0; q < nsys; ++q) {
       const Ctrl& h = cr[q];
@@ -929,17 +946,6 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
       o.dt = h.dt;
       o.alpha = h.alpha;
     }
-    // wrap periodic coordinates as the single-system path does
-    for (int q = 0; q < nsys; ++q)
-      for (long long i = offsets[q]; i < offsets[q + 1]; ++i)
-        for (int k = 0; k < 3; ++k)
-          if (boxes[q].periodic[k]) {
-            double t = pos[3 * i + k] - boxes[q].lo[k];
-            t -= boxes[q].len[k] * std::floor(t / boxes[q].len[k]);
-            if (t >= boxes[q].len[k]) t -= boxes[q].len[k];
-            if (t < 0) t = 0;
-            pos[3 * i + k] = boxes[q].lo[k] + t;
-          }
     return FIRE_OK;
   }
   return fire_ctx_error(ctx, FIRE_E_OOM, "batched: neighbour lists keep outgrowing their capacity");

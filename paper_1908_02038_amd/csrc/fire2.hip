@@ -1223,9 +1223,9 @@ struct fire_ctx {
 };
 
 extern "C" void fire_batched_release(void* ws);
-extern "C" __attribute__((visibility("hidden"))) int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
+extern "C" __attribute__((visibility("hidden"))) int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos, bool host,
                                 const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
-                                double tol, long long max_steps, fire_result* out);
+                                double tol, long long max_steps, fire_result* out, hipStream_t s);
 
 namespace {
 
@@ -2457,7 +2457,16 @@ int fire_minimize_batched(fire_ctx* ctx, int nsys, const long long* offsets, dou
                           fire_result* out) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
-  return fire_batched_run(ctx, nsys, offsets, pos, boxes, pot, per_sys, tol, max_steps, out);
+  return fire_batched_run(ctx, nsys, offsets, pos, true, boxes, pot, per_sys, tol, max_steps, out, ctx->stream);
+}
+
+int fire_minimize_batched_dev(fire_ctx* ctx, int nsys, const long long* offsets, double* d_pos,
+                              const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
+                              double tol, long long max_steps, fire_result* out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return fire_batched_run(ctx, nsys, offsets, d_pos, false, boxes, pot, per_sys, tol, max_steps, out,
+                          pick_stream(ctx, stream));
 }
 
 }  // extern "C"

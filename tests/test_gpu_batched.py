@@ -121,3 +121,22 @@ def test_full_batched_workload_converges(api):
         e_x, f_x = oracle.energy_forces(pos[k], s.box, s.potential)
         assert abs(e_x - res[k]["energy"]) <= 1e-12 * abs(e_x)
         assert np.linalg.norm(f_x, axis=1).max() < 1e-6 * (1 + 1e-6)
+
+
+def test_device_entry_point_matches_host_entry_point(api):
+    """fire_minimize_batched_dev relaxes device positions in place to the same
+    bits as the host-pointer call."""
+    import torch
+    systems = small_batch(nsys=5, seed=11)
+    c = api.Context(0, systems[0].fire)
+    pos_h, res_h = c.fire_minimize_batched([(s.pos, s.box) for s in systems], systems[0].potential, 1e-6, 20000)
+    offs = np.cumsum([0] + [len(s.pos) for s in systems])
+    d = torch.tensor(np.concatenate([s.pos for s in systems]), dtype=torch.float64, device="cuda")
+    res_d = c.fire_minimize_batched_dev(d, offs, [s.box for s in systems], systems[0].potential, 1e-6, 20000)
+    torch.cuda.synchronize()
+    c.close()
+    got = d.cpu().numpy()
+    for k in range(len(systems)):
+        assert res_d[k]["iterations"] == res_h[k]["iterations"]
+        assert res_d[k]["energy"] == res_h[k]["energy"]
+        assert np.array_equal(got[offs[k]:offs[k + 1]], pos_h[k])
