@@ -1,0 +1,108 @@
+"""GPU parity of the method's variants against the oracle: the explicit-Euler
+and velocity-Verlet integrators (Algorithms 3 and 6), the original FIRE
+(Algorithm 1), the paper's f2norm stopping criterion (Sec. 3.4), and a batched
+sweep over alpha0 x tmax x dt_start in the spirit of the parameter study
+(Sec. 5.4, Fig. 3): every system of the sweep relaxes with its own
+parameters in one launch and is checked against its own oracle run."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_02038_amd import inputs
+from systems import SMALL, min_image_diff
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {
+    "ee": {"integrator": "eulerexplicit"},
+    "vv": {"integrator": "verlet"},
+    "fire1": {"variant": "fire1"},
+    "fire1_ee": {"variant": "fire1", "integrator": "eulerexplicit"},
+}
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1908_02038_amd import api as a
+    return a
+
+
+@pytest.mark.parametrize("var", list(VARIANTS))
+@pytest.mark.parametrize("name", ["lj_small", "gupta_5", "gupta_slab"])
+def test_variant_first_steps_match_oracle(api, var, name):
+    s = SMALL[name]()
+    fire = dict(s.fire, **VARIANTS[var])
+    c = api.Context(0, fire)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 20, trace=True)
+    c.close()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 0.0, 20, trace=True)
+    assert r["iterations"] == ref["iterations"] == 20
+    assert np.abs(min_image_diff(r["pos"], ref["pos"], s.box)).max() <= 1e-12
+    np.testing.assert_array_equal(r["trace"][:, 7], ref["trace"][:, 7])  # branches
+    np.testing.assert_allclose(r["trace"][:, [5, 6]], ref["trace"][:, [5, 6]], rtol=1e-15)  # dt, alpha
+    np.testing.assert_allclose(r["trace"][:, 1], ref["trace"][:, 1], rtol=1e-12)  # E
+
+
+@pytest.mark.parametrize("var", list(VARIANTS))
+@pytest.mark.parametrize("name", ["lj_small", "gupta_5"])
+def test_variant_relaxation_matches_oracle(api, var, name):
+    s = SMALL[name]()
+    fire = dict(s.fire, **VARIANTS[var])
+    c = api.Context(0, fire)
+    r = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000, trace=True)
+    c.close()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, fire, s.tol, 50000, trace=True)
+    n = len(s.pos)
+    m = min(len(r["trace"]), len(ref["trace"]))
+    diff = np.nonzero(r["trace"][:m, 7] != ref["trace"][:m, 7])[0]
+    first = int(diff[0]) if len(diff) else None
+    print(f"{name}/{var}: gpu {r['stop']} {r['iterations']} it, oracle {ref['stop']} {ref['iterations']} it, "
+          f"first branch difference {first}")
+    assert r["stop"] == ref["stop"]
+    if first is None and r["iterations"] == ref["iterations"]:
+        assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
+    else:
+        assert first is not None and first >= 50
+    e_x, f_x = oracle.energy_forces(r["pos"], s.box, s.potential)
+    assert abs(e_x - r["energy"]) <= 1e-12 * abs(e_x)
+    if r["stop"] == "converged":
+        assert np.linalg.norm(f_x, axis=1).max() < s.tol * (1 + 1e-6)
+
+
+def test_f2norm_criterion(api):
+    s = SMALL["gupta_5"]()
+    fire = dict(s.fire, criterion="f2norm")
+    c = api.Context(0, fire)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 1e-5, 50000)
+    c.close()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 1e-5, 50000)
+    assert r["stop"] == ref["stop"] == "converged"
+    assert r["f2norm"] < 1e-5 and r["iterations"] == ref["iterations"]
+    _, f_x = oracle.energy_forces(r["pos"], s.box, s.potential)
+    assert np.linalg.norm(f_x) < 1e-5 * (1 + 1e-6)
+
+
+def test_batched_parameter_sweep(api):
+    """27 copies of one crystal, alpha0 x tmax x dt_start, one launch."""
+    s = inputs.gupta_box(4, nvac=2, noise=0.08, seed=51)
+    grid = list(itertools.product((0.05, 0.1, 0.25), (5.0, 10.0, 20.0), (0.0005, 0.001, 0.002)))
+    params = [dict(s.fire, alpha0=a, tmax=t, dt_start=d) for a, t, d in grid]
+    c = api.Context(0, s.fire)
+    pos, res = c.fire_minimize_batched([(s.pos, s.box)] * len(grid), s.potential, 1e-6, 50000, per_sys=params)
+    c.close()
+    n = len(s.pos)
+    its = []
+    for prm, p, r in zip(params, pos, res):
+        ref = oracle.fire_minimize(s.pos, s.box, s.potential, prm, 1e-6, 50000)
+        its.append((r["iterations"], ref["iterations"]))
+        assert r["stop"] == ref["stop"] == "converged"
+        if r["iterations"] == ref["iterations"]:
+            assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
+        e_x, f_x = oracle.energy_forces(p, s.box, s.potential)
+        assert abs(e_x - r["energy"]) <= 1e-12 * abs(e_x)
+        assert np.linalg.norm(f_x, axis=1).max() < 1e-6 * (1 + 1e-6)
+    print("iterations (gpu, oracle) per (alpha0, tmax, dt_start):", list(zip(grid, its)))
+    # the sweep is not degenerate: the parameters change the iteration count
+    assert len({g for g, _ in its}) > 3
