@@ -280,7 +280,9 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": hbm_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": hbm_ach / PEAK_HBM_GBS}
-    roof.update({"traffic": traffic, "kernel": kname + "<double, false, false>", "ms_per_launch": kt,
+    staged = os.environ.get("FIRE_LDS", "1") != "0"  # LDS-staged tiles unless switched off
+    roof.update({"traffic": traffic, "kernel": kname + ("<double, true, false>" if staged else "<double, false, false>"),
+                 "ms_per_launch": kt,
                  "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops_launch,
                  "hbm_achieved_GBs": hbm_ach, "hbm_frac": hbm_ach / PEAK_HBM_GBS,
                  "arithmetic_intensity": ai, "ridge": ridge})

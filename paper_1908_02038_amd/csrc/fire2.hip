@@ -284,29 +284,79 @@ __global__ void k_cell_count(const double4* __restrict__ pos, int n, int nt, Gri
   atomicAdd(&count[c], 1);
 }
 
-// Exclusive scan of count[0..m) into start[0..m], one block.
-__global__ void k_scan(const int* __restrict__ count, int m, int* __restrict__ start) {
-  __shared__ int sm[1024];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < m; base += 1024) {
-    int i = base + threadIdx.x;
-    int v = i < m ? count[i] : 0;
-    sm[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      int t = (int)threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
-      __syncthreads();
-      sm[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < m) start[i] = carry + sm[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += sm[1023];
-    __syncthreads();
+// Exclusive prefix sum start[0..m] of count[0..m) (start[m] = total) in three
+// launches: per-chunk totals, a scan of the totals, and per-chunk scans with
+// the chunk's offset.  A chunk is 4096 counts: 1024 threads x 4 consecutive.
+constexpr int kScanThreads = 1024;
+constexpr int kScanChunk = 4 * kScanThreads;
+
+// Inclusive scan over the block (blockDim.x = kScanThreads); *total = sum.
+__device__ __forceinline__ int block_scan_incl(int v, int* total) {
+  __shared__ int wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
   }
-  if (threadIdx.x == 0) start[m] = carry;
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+    off += q < w ? wsum[q] : 0;
+    tot += wsum[q];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + v;
+}
+
+__device__ __forceinline__ int4 load_counts(const int* __restrict__ count, int m, int i) {
+  if (i + 3 < m) return *reinterpret_cast<const int4*>(count + i);
+  return make_int4(i < m ? count[i] : 0, i + 1 < m ? count[i + 1] : 0, i + 2 < m ? count[i + 2] : 0,
+                   i + 3 < m ? count[i + 3] : 0);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_part(const int* __restrict__ count, int m,
+                                                            int* __restrict__ part) {
+  const int i = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  const int4 c = load_counts(count, m, i);
+  int tot;
+  block_scan_incl(c.x + c.y + c.z + c.w, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of part[0..np) in place, part[np] = total, and
+// start[m] = total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int* __restrict__ part, int np, int* __restrict__ start,
+                                                           int m) {
+  int carry = 0;
+  for (int base = 0; base < np; base += kScanThreads) {
+    const int q = base + threadIdx.x;
+    const int v = q < np ? part[q] : 0;
+    int tot;
+    const int inc = block_scan_incl(v, &tot);
+    if (q < np) part[q] = carry + inc - v;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    part[np] = carry;
+    start[m] = carry;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int* __restrict__ count, int m,
+                                                             const int* __restrict__ part,
+                                                             int* __restrict__ start) {
+  const int i = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  const int4 c = load_counts(count, m, i);
+  const int t = c.x + c.y + c.z + c.w;
+  int tot;
+  const int e = part[blockIdx.x] + block_scan_incl(t, &tot) - t;
+  if (i < m) start[i] = e;
+  if (i + 1 < m) start[i + 1] = e + c.x;
+  if (i + 2 < m) start[i + 2] = e + c.x + c.y;
+  if (i + 3 < m) start[i + 3] = e + c.x + c.y + c.z;
 }
 
 __global__ void k_cell_fill(const int* __restrict__ cell_of, int n, const int* __restrict__ start,
@@ -360,6 +410,32 @@ __global__ void k_permute(const int* __restrict__ order, int n, int nt, int ncap
   }
 }
 
+// Copy the sorted slots back into the arrays the captured graphs read (their
+// addresses must not change), and record the build positions for the skin
+// test: one launch over max(nt, n) slots instead of one copy per array.
+__global__ void k_commit(int n, int nt, int ng, int ncap, const double4* __restrict__ pos2,
+                         const int* __restrict__ gsrc2, const int* __restrict__ gcode2,
+                         const int* __restrict__ id2, const double* __restrict__ vel2,
+                         const double* __restrict__ frc2, double4* __restrict__ pos, int* __restrict__ gsrc,
+                         int* __restrict__ gcode, int* __restrict__ id, double* __restrict__ vel,
+                         double* __restrict__ frc, double4* __restrict__ xref) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nt) pos[s] = pos2[s];
+  if (s < ng) {
+    gsrc[s] = gsrc2[s];
+    gcode[s] = gcode2[s];
+  }
+  if (s < n) {
+    xref[s] = pos2[s];
+    id[s] = id2[s];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      vel[d * ncap + s] = vel2[d * ncap + s];
+      frc[d * ncap + s] = frc2[d * ncap + s];
+    }
+  }
+}
+
 // Link ghosts to the new slots of their sources: real_of[] (slot -> real
 // slot, identity for real atoms) and the per-atom ghost lists (at most 7).
 __global__ void k_ghost_link(int n, int ng, const int* __restrict__ new_of_old, int* __restrict__ gsrc,
@@ -383,6 +459,9 @@ __device__ __forceinline__ int wave_max_i(int v) {
 // Neighbour k of lane `lane` of wave w: groups of four consecutive neighbours
 // of one atom are adjacent, so a lane fetches a group with one vector load and
 // a wave's group loads are contiguous.
+// Dynamic LDS of the kernels that size it at launch.
+extern __shared__ __align__(16) unsigned char dyn_lds[];
+
 __device__ __forceinline__ size_t lidx(int w, int k, int lane, int kcap) {
   return (((size_t)w * (kcap >> 2) + (k >> 2)) * 64 + lane) * 4 + (k & 3);
 }
@@ -454,48 +533,27 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
   if (overlap) atomicOr(&flags[0], ERR_OVERLAP);
 }
 
-// Per-tile halo for the LDS-staged passes.  Tile b is the 256 slots of block
-// b; its halo is every atom of every cell in the stencil of a cell the tile
-// occupies (a superset of the tile's neighbours), as the sorted list of those
-// cells' slot runs.  The kernel writes the halo's slot list (hslot, at most
-// hcap entries), its size (tile_h), and rewrites the tile's neighbour lists
-// as 16-bit halo indices (nbr16; padding -> index H, an LDS slot set to a far
-// position).  A halo that does not fit sets flags[3]; flags[2] = max H.
+// Candidates of tile b (the 256 slots of block b): the stencil cells of the
+// tile's cells, sorted by rank and made unique, with the offsets of their atom
+// runs (hoff, hoff[nu] = number of candidate atoms).  Returns nu, or -1 if
+// the tile has more than kCandMax / 27 distinct cells.
 constexpr int kCandMax = 4096;
-__global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ srank, const int* __restrict__ start,
-                                                      const int* __restrict__ rank_cell,
-                                                      const int* __restrict__ cell_rank, int n, Grid g,
-                                                      const int* __restrict__ nbr, const int* __restrict__ wcnt,
-                                                      int kcap, int hcap, int dummy, int* __restrict__ tile_h,
-                                                      int* __restrict__ hslot, unsigned short* __restrict__ nbr16,
-                                                      int* __restrict__ flags) {
-  __shared__ int cand[kCandMax];
-  __shared__ int hoff[kCandMax + 1];
-  __shared__ int dcell[kBlock];
-  __shared__ int s_ndc, s_nu, s_H, s_bad;
+__device__ int tile_candidates(const int* __restrict__ srank, const int* __restrict__ start,
+                               const int* __restrict__ rank_cell, const int* __restrict__ cell_rank, int n,
+                               const Grid& g, int* cand, int* hoff, int* dcell, int* s_shared) {
   const int b = blockIdx.x, t = threadIdx.x;
-  const int s0 = b * kBlock;
-  if (s0 >= n) {
-    if (t == 0) tile_h[b] = 0;
-    return;
-  }
-  const int s1 = min(s0 + kBlock, n);
-  if (t == 0) {  // distinct occupied cells (slots are sorted by cell rank)
-    int nd = 0;
-    for (int s = s0; s < s1; ++s)
-      if (s == s0 || srank[s] != srank[s - 1]) dcell[nd++] = srank[s];
-    s_ndc = nd;
-    s_bad = nd * 27 > kCandMax;
+  const int s0 = b * kBlock, s1 = min(s0 + kBlock, n);
+  int tot;
+  {
+    const int sl = s0 + t;
+    const int f = (sl < s1 && (t == 0 || srank[sl] != srank[sl - 1])) ? 1 : 0;
+    const int p = block_scan_incl(f, &tot) - f;
+    if (f) dcell[p] = srank[sl];
   }
   __syncthreads();
-  if (s_bad) {
-    if (t == 0) {
-      tile_h[b] = -1;
-      atomicOr(&flags[3], 1);
-    }
-    return;
-  }
-  const int ncand = s_ndc * 27;
+  const int nd = tot;
+  if (nd * 27 > kCandMax) return -1;
+  const int ncand = nd * 27;
   int P = 1;
   while (P < ncand) P <<= 1;
   for (int q = t; q < P; q += blockDim.x) {
@@ -512,8 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
     cand[q] = v;
   }
   __syncthreads();
-  // bitonic sort of cand[0..P)
-  for (int k = 2; k <= P; k <<= 1)
+  for (int k = 2; k <= P; k <<= 1)  // bitonic sort of cand[0..P)
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int q = t; q < P; q += blockDim.x) {
         const int p = q ^ j;
@@ -528,64 +585,141 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
       }
       __syncthreads();
     }
-  if (t == 0) {  // unique cells and their offsets in the halo
-    int nu = 0, H = 0, prev = -1;
-    for (int q = 0; q < P; ++q) {
-      const int r = cand[q];
-      if (r == INT_MAX) break;
-      if (r == prev) continue;
-      prev = r;
-      cand[nu] = r;
-      hoff[nu] = H;
-      H += start[r + 1] - start[r];
-      ++nu;
+  // unique cells and their run offsets; thread t owns 16 consecutive entries
+  constexpr int kPer = kCandMax / kBlock;
+  int r[kPer], nu_t = 0, len_t = 0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int q = kPer * t + u;
+    r[u] = (q < P && cand[q] != INT_MAX && (q == 0 || cand[q] != cand[q - 1])) ? cand[q] : -1;
+    if (r[u] >= 0) {
+      ++nu_t;
+      len_t += start[r[u] + 1] - start[r[u]];
     }
-    hoff[nu] = H;
-    s_nu = nu;
-    s_H = H;
+  }
+  int tu, tl;
+  int pu = block_scan_incl(nu_t, &tu) - nu_t;
+  int pl = block_scan_incl(len_t, &tl) - len_t;
+  __syncthreads();  // all of cand[] read before it is compacted
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    if (r[u] >= 0) {
+      cand[pu] = r[u];
+      hoff[pu] = pl;
+      ++pu;
+      pl += start[r[u] + 1] - start[r[u]];
+    }
+  if (t == 0) {
+    hoff[tu] = tl;
+    *s_shared = tu;
   }
   __syncthreads();
-  const int nu = s_nu, H = s_H;
+  return *s_shared;
+}
+
+// Per-tile halo for the LDS-staged passes.  Tile b is the 256 slots of block
+// b.  Its halo is the set of atoms that occur in the tile's neighbour lists:
+// every list entry marks its candidate (tile_candidates) in a bitmap, and the
+// marked candidates, in candidate order, are the halo.  The kernel writes the
+// halo's slot list (hslot, at most hcap entries), its size (tile_h), and
+// rewrites the tile's lists as 16-bit halo indices (nbr16; padding -> index H,
+// an LDS slot set to a far position).  A halo that does not fit sets
+// flags[3] bit 4; flags[2] = max H.
+constexpr int kHaloCandMax = 16384;   // candidate atoms of one tile (bitmap bits)
+__global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ srank, const int* __restrict__ start,
+                                                      const int* __restrict__ rank_cell,
+                                                      const int* __restrict__ cell_rank, int n, Grid g,
+                                                      const int* __restrict__ nbr, const int* __restrict__ wcnt,
+                                                      int kcap, int hcap, int dummy, int* __restrict__ tile_h,
+                                                      int* __restrict__ hslot, unsigned short* __restrict__ nbr16,
+                                                      int* __restrict__ flags) {
+  __shared__ int cand[kCandMax];
+  __shared__ int hoff[kCandMax + 1];
+  __shared__ int dcell[kBlock];
+  __shared__ unsigned int used[kHaloCandMax / 32];
+  __shared__ int wpre[kHaloCandMax / 32];
+  __shared__ int s_nu;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int nu = tile_candidates(srank, start, rank_cell, cell_rank, n, g, cand, hoff, dcell, &s_nu);
+  int* cslot = cand;  // below, cand[h] is replaced by the first slot of run h (runs ascend in slot order)
+  if (nu < 0 || hoff[nu] > kHaloCandMax) {
+    if (t == 0) {
+      tile_h[b] = -1;
+      atomicOr(&flags[3], 4);
+    }
+    return;
+  }
+  const int Hc = hoff[nu];
+  const int nwords = (Hc + 31) >> 5;
+  for (int q = t; q < nwords; q += blockDim.x) used[q] = 0u;
+  for (int h = t; h < nu; h += blockDim.x) cslot[h] = start[cand[h]];
+  __syncthreads();
+  auto run_of_slot = [&](int j) {  // last run h with cslot[h] <= j
+    int lo = 0, hi = nu - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cslot[mid] <= j) lo = mid;
+      else hi = mid - 1;
+    }
+    return lo;
+  };
+  // pass 1: candidate index of every list entry, marked in the bitmap and
+  // kept in nbr16 until the halo numbering is known (padding: 0xFFFF)
+  const int i = b * kBlock + t;
+  const int w = i >> 6, lane = t & 63;
+  const int kw = wcnt[w];
+  for (int k = 0; k < kw; ++k) {
+    const int j = nbr[lidx(w, k, lane, kcap)];
+    int q = 0xFFFF;
+    if (j != dummy) {
+      const int h = run_of_slot(j);
+      q = hoff[h] + (j - cslot[h]);
+      if (j < cslot[h] || q >= hoff[h + 1]) {  // not among the candidates: cannot happen for valid lists
+        atomicOr(&flags[3], 4);
+        q = 0;
+      }
+      atomicOr(&used[q >> 5], 1u << (q & 31));
+    }
+    nbr16[lidx(w, k, lane, kcap)] = (unsigned short)q;
+  }
+  __syncthreads();
+  // halo index of the first marked candidate of each bitmap word
+  int tot = 0;
+  for (int base = 0; base < nwords; base += kBlock) {
+    const int q = base + t;
+    const int pc = q < nwords ? __popc(used[q]) : 0;
+    int part;
+    const int ex = block_scan_incl(pc, &part) - pc;
+    if (q < nwords) wpre[q] = tot + ex;
+    tot += part;
+  }
+  __syncthreads();
+  const int H = tot;
   if (H + 1 > hcap) {
     if (t == 0) {
       tile_h[b] = -1;
-      atomicOr(&flags[3], 1);
+      atomicOr(&flags[3], 4);
       atomicMax(&flags[2], H);
     }
     return;
   }
-  auto find = [&](int r) {  // index of cell rank r in cand[0..nu)
-    int lo = 0, hi = nu - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (cand[mid] < r) lo = mid + 1;
-      else hi = mid;
-    }
-    return lo;
-  };
+  auto halo_index = [&](int q) { return wpre[q >> 5] + __popc(used[q >> 5] & ((1u << (q & 31)) - 1u)); };
   int* hs = hslot + (size_t)b * hcap;
-  for (int q = t; q < H; q += blockDim.x) {
-    int lo = 0, hi = nu - 1;  // last h with hoff[h] <= q
+  for (int q = t; q < Hc; q += blockDim.x) {
+    if (!(used[q >> 5] & (1u << (q & 31)))) continue;
+    int lo = 0, hi = nu - 1;  // last run h with hoff[h] <= q
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (hoff[mid] <= q) lo = mid;
       else hi = mid - 1;
     }
-    hs[q] = start[cand[lo]] + (q - hoff[lo]);
+    hs[halo_index(q)] = cslot[lo] + (q - hoff[lo]);
   }
-  const int i = s0 + t;
-  const int w = i >> 6, lane = t & 63;
-  const int kw = wcnt[w];
+  // pass 2: candidate index -> halo index
   for (int k = 0; k < kw; ++k) {
-    const int j = nbr[lidx(w, k, lane, kcap)];
-    int l = H;
-    if (j != dummy) {
-      const int r = srank[j];
-      const int h = find(r);
-      if (cand[h] != r) atomicOr(&flags[3], 2);  // not in the halo: fall back to global gathers
-      l = hoff[h] + (j - start[r]);
-    }
-    nbr16[lidx(w, k, lane, kcap)] = (unsigned short)l;
+    const size_t e = lidx(w, k, lane, kcap);
+    const int q = nbr16[e];
+    nbr16[e] = (unsigned short)(q == 0xFFFF ? H : halo_index(q));
   }
   if (t == 0) {
     tile_h[b] = H;
@@ -611,15 +745,21 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
                                                    const double4* __restrict__ xref, const int* __restrict__ gcnt,
                                                    const int* __restrict__ glist, const int* __restrict__ gcode,
                                                    BoxDev box, int n, int ncap, Ctrl* __restrict__ ctrl) {
-  if (!ctrl_running(ctrl)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // same block -> atoms map as the force passes, so each XCD updates the
+  // atoms whose forces it just wrote (they are in its L2)
+  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  // the atom's own data does not depend on the control record: load it
+  // first, so its latency overlaps the wait for the record
+  const double4 p = pos[i];
+  double v[3] = {vel[i], vel[ncap + i], vel[2 * ncap + i]};
+  const double f[3] = {frc[i], frc[ncap + i], frc[2 * ncap + i]};
+  const double4 r = xref[i];
+  const int gc = gcnt[i];
+  if (!ctrl_running(ctrl)) return;
   const int neg = ctrl->neg, mix_first = ctrl->mix_first;
   const double hsb = ctrl->hsb, k1 = ctrl->kick1, k2 = ctrl->kick2, cv = ctrl->cv, cf = ctrl->cf,
                dtx = ctrl->dtx;
-  double4 p = pos[i];
-  double v[3] = {vel[i], vel[ncap + i], vel[2 * ncap + i]};
-  const double f[3] = {frc[i], frc[ncap + i], frc[2 * ncap + i]};
   double x[3] = {p.x, p.y, p.z};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -640,12 +780,11 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
   vel[i] = v[0];
   vel[ncap + i] = v[1];
   vel[2 * ncap + i] = v[2];
-  for (int k = 0, gc = gcnt[i]; k < gc; ++k) {  // periodic images move along
+  for (int k = 0; k < gc; ++k) {  // periodic images move along
     const int g = glist[8 * i + k], code = gcode[g - n];
     pos[g] = make_double4(x[0] + ghost_shift(code, 0, box), x[1] + ghost_shift(code, 1, box),
                           x[2] + ghost_shift(code, 2, box), p.w);
   }
-  const double4 r = xref[i];
   const double ex = x[0] - r.x, ey = x[1] - r.y, ez = x[2] - r.z;
   if (ex * ex + ey * ey + ez * ez > ctrl->skin_half2) atomicOr(&ctrl->viol, 1);
 }
@@ -745,16 +884,25 @@ struct Tiles {
   int hcap;
 };
 
-extern __shared__ __align__(16) unsigned char dyn_lds[];
 
 // Position of the list padding slot: far outside any system, finite in FP32.
 constexpr double kFar = 1.0e20;
 
-// Copy tile b's halo positions into LDS (plus the far entry for the padding);
-// four entries per thread and round, so their loads are in flight together.
-__device__ __forceinline__ const double4* stage_halo(const double4* __restrict__ pos, const Tiles& tl, int b) {
-  double4* h = reinterpret_cast<double4*>(dyn_lds);
+// A tile's halo in LDS as structure of arrays: x at [0, S), y at [S, 2S),
+// z at [2S, 3S) and, for the EAM force pass, F'(rho) at [3S, 4S); S = H + 1,
+// entry H is the far padding atom.
+struct Halo {
+  const double* a;
+  int S;
+};
+
+// Copy tile b's halo into LDS; W: also F'(rho) (pos.w).  Four entries per
+// thread and round, so their loads are in flight together.
+template <bool W>
+__device__ __forceinline__ Halo stage_halo(const double4* __restrict__ pos, const Tiles& tl, int b) {
+  double* h = reinterpret_cast<double*>(dyn_lds);
   const int H = tl.tile_h[b];
+  const int S = H + 1;
   const int* hs = tl.hslot + (size_t)b * tl.hcap;
   const int step = blockDim.x;
   for (int q0 = threadIdx.x; q0 < H; q0 += 4 * step) {
@@ -767,20 +915,33 @@ __device__ __forceinline__ const double4* stage_halo(const double4* __restrict__
       if (idx[u] >= 0) v[u] = pos[idx[u]];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (idx[u] >= 0) h[q0 + u * step] = v[u];
+      if (idx[u] >= 0) {
+        const int q = q0 + u * step;
+        h[q] = v[u].x;
+        h[S + q] = v[u].y;
+        h[2 * S + q] = v[u].z;
+        if constexpr (W) h[3 * S + q] = v[u].w;
+      }
   }
-  if (threadIdx.x == 0) h[H] = make_double4(kFar, kFar, kFar, 0.0);
+  if (threadIdx.x == 0) {
+    h[H] = kFar;
+    h[S + H] = kFar;
+    h[2 * S + H] = kFar;
+    if constexpr (W) h[3 * S + H] = 0.0;
+  }
   __syncthreads();
-  return h;
+  return Halo{h, S};
 }
 
-// Neighbour loop shared by the pair kernels: wave-uniform trip count, four
-// neighbours per step, software-pipelined: index groups are fetched two steps
-// ahead (one 8- or 16-byte load per lane), and for global gathers the
-// positions one step ahead.  LDS: positions from the tile's halo in LDS by
-// 16-bit index; otherwise gathered from global memory by slot index.
-template <bool LDS, typename F>
-__device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, const double4* __restrict__ halo,
+// Neighbour loop shared by the pair kernels: one lane per atom, wave-uniform
+// trip count, four neighbours per step, software-pipelined: index groups are
+// fetched two steps ahead (one 8- or 16-byte load per lane), and for global
+// gathers the positions one step ahead.  Neighbouring lanes hold neighbouring
+// atoms, so at each step they gather nearby (often identical) neighbours.
+// LDS: positions from the tile's halo in LDS by 16-bit index (W: with
+// F'(rho) in .w); otherwise gathered from global memory by slot index.
+template <bool LDS, bool W, typename F>
+__device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, const Halo& halo,
                                                const int* __restrict__ nbr, const Tiles& tl,
                                                const int* __restrict__ wcnt, int kcap, int i, F&& pair) {
   const int w = i >> 6, lane = threadIdx.x & 63;
@@ -788,6 +949,11 @@ __device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, 
   const size_t base = (size_t)w * (kcap >> 2) * 64 + lane;
   if constexpr (LDS) {
     const ushort4* l4 = reinterpret_cast<const ushort4*>(tl.nbr16) + base;
+    const double* hx = halo.a;
+    const double* hy = halo.a + halo.S;
+    const double* hz = halo.a + 2 * halo.S;
+    const double* hw = halo.a + 3 * halo.S;
+    auto at = [&](int c) { return make_double4(hx[c], hy[c], hz[c], W ? hw[c] : 0.0); };
     ushort4 a = make_ushort4(0, 0, 0, 0), b = a;
     if (ng > 0) a = l4[0];
     if (ng > 1) b = l4[64];
@@ -795,7 +961,7 @@ __device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, 
       const ushort4 c = a;
       a = b;
       if (g + 2 < ng) b = l4[(size_t)(g + 2) * 64];
-      const double4 p0 = halo[c.x], p1 = halo[c.y], p2 = halo[c.z], p3 = halo[c.w];
+      const double4 p0 = at(c.x), p1 = at(c.y), p2 = at(c.z), p3 = at(c.w);
       pair(p0);
       pair(p1);
       pair(p2);
@@ -843,13 +1009,13 @@ __global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__
                                                      Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
   if (!pass_gate(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const double4* halo = LDS ? stage_halo(pos, tl, b) : nullptr;
+  const Halo halo = LDS ? stage_halo<false>(pos, tl, b) : Halo{nullptr, 0};
   const int i = b * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   T ax = 0, ay = 0, az = 0, ae = 0;
   const double4 pi = pos[i];
   const T eps24 = (T)(24.0 * pot.eps), eps4 = (T)(4.0 * pot.eps), sig2 = (T)pot.sig2, sh = (T)pot.shift;
-  for_neighbours<LDS>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
+  for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
     const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     // branch-free: out-of-range lanes (including the far padding) evaluate at
@@ -879,13 +1045,13 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
                                                           double* __restrict__ part_emb, Ctrl* __restrict__ ctrl) {
   if (!pass_gate(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const double4* halo = LDS ? stage_halo(pos, tl, b) : nullptr;
+  const Halo halo = LDS ? stage_halo<false>(pos, tl, b) : Halo{nullptr, 0};
   const int i = b * blockDim.x + threadIdx.x;
   double emb = 0.0;
   const double4 pi = pos[i];
   const T qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in, inv_w = (T)pot.inv_w;
   T rho = 0;
-  for_neighbours<LDS>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
+  for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
     const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     const bool in = r2 < pot.rc2;
@@ -923,14 +1089,14 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
                                                         Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
   if (!pass_gate(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const double4* halo = LDS ? stage_halo(pos, tl, b) : nullptr;
+  const Halo halo = LDS ? stage_halo<true>(pos, tl, b) : Halo{nullptr, 0};
   const int i = b * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   T ax = 0, ay = 0, az = 0, ae = 0;
   const double4 pi = pos[i];
   const T A = (T)pot.A, pr0 = (T)pot.pr0, qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in,
           inv_w = (T)pot.inv_w, cpair = (T)pot.cpair, epair = (T)pot.epair, fpi = (T)pi.w;
-  for_neighbours<LDS>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
+  for_neighbours<LDS, true>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
     const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     const bool in = r2 < pot.rc2;
@@ -1191,12 +1357,14 @@ struct fire_ctx {
   unsigned short* nbr16 = nullptr;
   int hcap = 0;
   bool use_lds = false;
-  size_t lds_bytes = 0, lds_limit = 0;
+  size_t lds_atoms = 0, lds_limit = 0;  // halo capacity per tile block; byte limit per block
   double *part = nullptr, *part_emb = nullptr, *bbox_part = nullptr;
   double* aux = nullptr;  // HVP / Lanczos planes
   int aux_planes = 0;
   Ctrl* ctrl = nullptr;
   int* flags = nullptr;       // device: [0] error bits, [1] max neighbour count
+  int* scan_part = nullptr;   // chunk totals of the prefix sums
+  int scan_cap = 0;
   int* h_flags = nullptr;     // pinned
   Ctrl* h_ctrl = nullptr;     // pinned
   int* h_status = nullptr;    // pinned, 2 slots x 8 ints
@@ -1428,6 +1596,21 @@ int prepare_system(fire_ctx* ctx, const fire_box* b, const fire_potential* p) {
 // each side, on free axes the bounding box of the atoms.  Cells inside the
 // box get the first ranks (Morton order), the ghost layers the rest, so a
 // sort by rank puts real atoms before ghosts.
+// start[0..m] = exclusive prefix sum of count[0..m), start[m] = total.
+int launch_scan(fire_ctx* ctx, hipStream_t s, const int* count, int m, int* start) {
+  const int np = std::max(1, (m + kScanChunk - 1) / kScanChunk);
+  if (np + 1 > ctx->scan_cap) {
+    hipFree(ctx->scan_part);
+    ctx->scan_part = nullptr;
+    HIPCHK(dalloc(&ctx->scan_part, (size_t)np + 1));
+    ctx->scan_cap = np + 1;
+  }
+  hipLaunchKernelGGL(k_scan_part, dim3(np), dim3(kScanThreads), 0, s, count, m, ctx->scan_part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, ctx->scan_part, np, start, m);
+  hipLaunchKernelGGL(k_scan_apply, dim3(np), dim3(kScanThreads), 0, s, count, m, ctx->scan_part, start);
+  return FIRE_OK;
+}
+
 int make_grid(fire_ctx* ctx, int n) {
   Grid& g = ctx->grid;
   double bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
@@ -1537,51 +1720,67 @@ int read_flags(fire_ctx* ctx) {
   return FIRE_OK;
 }
 
-// Tile halos and 16-bit neighbour lists for the LDS-staged passes; falls back
-// to the global-gather passes when a halo does not fit the LDS of a block.
-int build_tiles_impl(fire_ctx* ctx) {
-  hipStream_t s = ctx->stream;
-  const int n = ctx->n, nb = nblocks(n);
-  const size_t max_atoms = ctx->lds_limit / sizeof(double4);
-  const int hcap = (int)std::min<size_t>(max_atoms, 65535);
-  ctx->use_lds = false;
-  if (hcap < 64) return FIRE_OK;
-  if (!ctx->nbr16) HIPCHK(dalloc(&ctx->nbr16, (size_t)ctx->kcap * ctx->ncap));
-  if (!ctx->hslot || ctx->hcap != hcap) {
-    hipFree(ctx->hslot);
-    ctx->hslot = nullptr;
-    HIPCHK(dalloc(&ctx->hslot, (size_t)hcap * (ctx->ncap / kBlock)));
-    ctx->hcap = hcap;
-    ctx->layout_version++;
-  }
-  const Grid& g = ctx->grid;
-  HIPCHK(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), s));
-  hipLaunchKernelGGL(k_tile_halo, dim3(nb), dim3(kBlock), 0, s, ctx->srank, ctx->cell_start, ctx->rank_cell,
-                     ctx->cell_rank, n, g, ctx->nbr, ctx->wcnt, ctx->kcap, ctx->hcap, ctx->tcap - 1, ctx->tile_h,
-                     ctx->hslot, ctx->nbr16, ctx->flags);
-  int rc = read_flags(ctx);
-  if (rc) return rc;
-  if (ctx->h_flags[3]) return FIRE_OK;  // some halo too large: global gathers
-  const size_t bytes = sizeof(double4) * (size_t)(ctx->h_flags[2] + 1);
-  if (bytes > ctx->lds_limit) return FIRE_OK;
-  // round up so small changes of the largest halo do not force a new graph
-  const size_t rounded = std::min(ctx->lds_limit, (bytes + 4095) & ~(size_t)4095);
-  if (getenv("FIRE_DEBUG"))
-    fprintf(stderr, "[fire] rebuild: n %d, kcap %d, max halo %d atoms, %zu B LDS per tile block\n", n, ctx->kcap,
-            ctx->h_flags[2], rounded);
-  if (rounded != ctx->lds_bytes) {
-    ctx->lds_bytes = rounded;
-    ctx->layout_version++;
-  }
-  ctx->use_lds = true;
-  return FIRE_OK;
-}
+// LDS bytes per halo atom of the largest staged pass: x, y, z, plus F'(rho)
+// for the EAM force pass.
+size_t halo_bytes_per_atom(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_POT_GUPTA ? 32 : 24; }
 
-int build_tiles(fire_ctx* ctx) {
+
+
+// Neighbour lists (and, with the LDS budget, tile halos) of the current
+// slots; one flag read for both kernels.  Grows the list capacity until every
+// list fits.
+int build_lists(fire_ctx* ctx) {
+  hipStream_t s = ctx->stream;
+  const int n = ctx->n, nb = nblocks(n), dummy = ctx->tcap - 1;
+  const double rcs2 = ctx->rcs * ctx->rcs;
   const bool was = ctx->use_lds;
-  int rc = build_tiles_impl(ctx);
+  const int hcap = (int)std::min<size_t>(ctx->lds_limit / halo_bytes_per_atom(ctx), 65535);
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    if (!ctx->nbr16) HIPCHK(dalloc(&ctx->nbr16, (size_t)ctx->kcap * ctx->ncap));
+    if (hcap >= 64 && (!ctx->hslot || ctx->hcap != hcap)) {
+      hipFree(ctx->hslot);
+      ctx->hslot = nullptr;
+      HIPCHK(dalloc(&ctx->hslot, (size_t)hcap * (ctx->ncap / kBlock)));
+      ctx->hcap = hcap;
+      ctx->layout_version++;
+    }
+    HIPCHK(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), s));
+    hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, n, ctx->grid,
+                       ctx->cell_rank, ctx->cell_start, rcs2, ctx->kcap, dummy, ctx->nbr, ctx->wcnt, ctx->flags);
+    if (hcap >= 64)
+      hipLaunchKernelGGL(k_tile_halo, dim3(nb), dim3(kBlock), 0, s, ctx->srank, ctx->cell_start, ctx->rank_cell,
+                         ctx->cell_rank, n, ctx->grid, ctx->nbr, ctx->wcnt, ctx->kcap, hcap, dummy, ctx->tile_h,
+                         ctx->hslot, ctx->nbr16, ctx->flags);
+    int rc = read_flags(ctx);
+    if (rc) return rc;
+    if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
+    if (ctx->h_flags[1] <= ctx->kcap) break;
+    if (attempt == 5) return set_err(ctx, FIRE_E_OOM, "neighbour lists keep outgrowing their capacity");
+    const int kmax = ctx->h_flags[1];
+    hipFree(ctx->nbr);
+    ctx->nbr = nullptr;
+    ctx->kcap = ((kmax + kmax / 8 + 8) + 3) & ~3;
+    HIPCHK(dalloc(&ctx->nbr, (size_t)ctx->kcap * ctx->ncap));
+    hipFree(ctx->nbr16);
+    ctx->nbr16 = nullptr;
+    ctx->layout_version++;
+  }
+  ctx->use_lds = false;
+  if (hcap >= 64 && !(ctx->h_flags[3] & 4)) {
+    // round up so small changes of the largest halo do not force a new graph
+    const size_t atoms = (size_t)ctx->h_flags[2] + 1;
+    const size_t rounded = std::min((size_t)hcap, (atoms + 127) & ~(size_t)127);
+    if (getenv("FIRE_DEBUG"))
+      fprintf(stderr, "[fire] rebuild: n %d, kcap %d, max halo %d atoms, LDS for %zu atoms per tile block\n", n,
+              ctx->kcap, ctx->h_flags[2], rounded);
+    if (rounded != ctx->lds_atoms) {
+      ctx->lds_atoms = rounded;
+      ctx->layout_version++;
+    }
+    ctx->use_lds = true;
+  }
   if (ctx->use_lds != was) ctx->layout_version++;  // captured graphs name the pass variant
-  return rc;
+  return FIRE_OK;
 }
 
 // Sort atoms by cell (stable: by caller index inside a cell), regenerate the
@@ -1600,11 +1799,12 @@ int rebuild(fire_ctx* ctx) {
   const int nb = nblocks(n);
   // ---- periodic images
   hipLaunchKernelGGL(k_ghost_count, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, ctx->rcs, ctx->gcount);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctx->gcount, n, ctx->goff);
+  int rc = launch_scan(ctx, s, ctx->gcount, n, ctx->goff);
+  if (rc) return rc;
   HIPCHK(hipMemcpyAsync(ctx->h_flags, ctx->goff + n, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const int ng = ctx->h_flags[0];
-  int rc = ensure_slots(ctx, n + ng, n);
+  rc = ensure_slots(ctx, n + ng, n);
   if (rc) return rc;
   ctx->ng = ng;
   const int nt = n + ng;
@@ -1620,7 +1820,8 @@ int rebuild(fire_ctx* ctx) {
   const int nbt = nblocks(nt);
   hipLaunchKernelGGL(k_cell_count, dim3(nbt), dim3(kBlock), 0, s, ctx->pos, n, nt, g, ctx->cell_rank, ctx->id,
                      ctx->gsrc, ctx->gcode, ctx->cell_of, ctx->key, ctx->cell_count);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctx->cell_count, g.ncell, ctx->cell_start);
+  rc = launch_scan(ctx, s, ctx->cell_count, g.ncell, ctx->cell_start);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_cell_fill, dim3(nbt), dim3(kBlock), 0, s, ctx->cell_of, nt, ctx->cell_start,
                      ctx->cell_cursor, ctx->bucket);
   hipLaunchKernelGGL(k_cell_rank, dim3(nbt), dim3(kBlock), 0, s, ctx->cell_of, ctx->cell_start, ctx->bucket, nt,
@@ -1631,19 +1832,9 @@ int rebuild(fire_ctx* ctx) {
   hipLaunchKernelGGL(k_ghost_link, dim3(nblocks(std::max(n, ng))), dim3(kBlock), 0, s, n, ng, ctx->new_of_old,
                      ctx->gsrc2, ctx->real_of, ctx->gcnt, ctx->glist);
   // copy back (not swap): captured graphs hold these buffers' addresses
-  HIPCHK(hipMemcpyAsync(ctx->pos, ctx->pos2, sizeof(double4) * nt, hipMemcpyDeviceToDevice, s));
-  if (ng > 0) {
-    HIPCHK(hipMemcpyAsync(ctx->gsrc, ctx->gsrc2, sizeof(int) * ng, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(ctx->gcode, ctx->gcode2, sizeof(int) * ng, hipMemcpyDeviceToDevice, s));
-  }
-  HIPCHK(hipMemcpyAsync(ctx->xref, ctx->pos, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(ctx->id, ctx->id2, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
-  for (int d = 0; d < 3; ++d) {
-    HIPCHK(hipMemcpyAsync(ctx->vel + (size_t)d * ctx->ncap, ctx->vel2 + (size_t)d * ctx->ncap, sizeof(double) * n,
-                          hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(ctx->frc + (size_t)d * ctx->ncap, ctx->frc2 + (size_t)d * ctx->ncap, sizeof(double) * n,
-                          hipMemcpyDeviceToDevice, s));
-  }
+  hipLaunchKernelGGL(k_commit, dim3(nbt), dim3(kBlock), 0, s, n, nt, ng, ctx->ncap, ctx->pos2, ctx->gsrc2,
+                     ctx->gcode2, ctx->id2, ctx->vel2, ctx->frc2, ctx->pos, ctx->gsrc, ctx->gcode, ctx->id, ctx->vel,
+                     ctx->frc, ctx->xref);
   const int dummy = ctx->tcap - 1;
   hipLaunchKernelGGL(k_set_pos, dim3(1), dim3(64), 0, s, ctx->pos, dummy, kFar);
   // ---- neighbour lists
@@ -1658,25 +1849,10 @@ int rebuild(fire_ctx* ctx) {
     HIPCHK(dalloc(&ctx->nbr, (size_t)ctx->kcap * ctx->ncap));
     ctx->layout_version++;
   }
-  for (int attempt = 0; attempt < 3; ++attempt) {
-    HIPCHK(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), s));
-    hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, n, g, ctx->cell_rank,
-                       ctx->cell_start, rcs2, ctx->kcap, dummy, ctx->nbr, ctx->wcnt, ctx->flags);
-    rc = read_flags(ctx);
-    if (rc) return rc;
-    if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
-    const int kmax = ctx->h_flags[1];
-    if (kmax <= ctx->kcap) break;
-    hipFree(ctx->nbr);
-    ctx->nbr = nullptr;
-    ctx->kcap = ((kmax + kmax / 8 + 8) + 3) & ~3;
-    HIPCHK(dalloc(&ctx->nbr, (size_t)ctx->kcap * ctx->ncap));
-    hipFree(ctx->nbr16);
-    ctx->nbr16 = nullptr;
-    ctx->layout_version++;
-  }
+  rc = build_lists(ctx);
+  if (rc) return rc;
   ctx->have_list = true;
-  return build_tiles(ctx);
+  return FIRE_OK;
 }
 
 template <typename T, bool LDS, bool WE>
@@ -1684,14 +1860,15 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s) {
   const int n = ctx->n, nb = nblocks(n), kc = ctx->kcap, nc = ctx->ncap;
   const PotDev& P = ctx->pot;
   const Tiles tl{ctx->tile_h, ctx->hslot, ctx->nbr16, ctx->hcap};
-  const size_t sm = LDS ? ctx->lds_bytes : 0;
+  const size_t sm = LDS ? ctx->lds_atoms * 24 : 0;     // x, y, z
+  const size_t smw = LDS ? ctx->lds_atoms * 32 : 0;    // x, y, z, F'(rho)
   if (P.kind == FIRE_POT_LJ) {
     hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt,
                        n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
   } else {
     hipLaunchKernelGGL((k_gupta_density<T, LDS>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl,
                        ctx->wcnt, n, kc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl);
-    hipLaunchKernelGGL((k_gupta_force<T, LDS, WE>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl,
+    hipLaunchKernelGGL((k_gupta_force<T, LDS, WE>), dim3(nb), dim3(kBlock), smw, s, ctx->pos, ctx->nbr, tl,
                        ctx->wcnt, n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl,
                        ctx->trace);
   }
@@ -1759,8 +1936,8 @@ int graph_for(fire_ctx* ctx, int prec, hipGraphExec_t* out) {
       hi = std::max<size_t>(hi, kp.sharedMemBytes);
       ++nk;
     }
-    fprintf(stderr, "[fire] graph: %zu kernel nodes, dynamic LDS %zu..%zu B (use_lds %d, lds_bytes %zu)\n", nk,
-            lo, hi, (int)ctx->use_lds, ctx->lds_bytes);
+    fprintf(stderr, "[fire] graph: %zu kernel nodes, dynamic LDS %zu..%zu B (use_lds %d, halo capacity %zu atoms)\n",
+            nk, lo, hi, (int)ctx->use_lds, ctx->lds_atoms);
   }
   hipError_t e = hipGraphInstantiate(&ctx->gexec[prec], g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
@@ -2137,8 +2314,14 @@ int fire_init(fire_ctx** out, int device, const fire_params* params) {
     // LDS-staged neighbour passes are opt-in: with halos of ~2-3k atoms per
     // 256-atom tile they fit one block per CU and measure slower than the
     // global-gather passes on the bulk workloads
-    ctx->lds_limit = 0;
-    if (getenv("FIRE_LDS")) ctx->lds_limit = prop.sharedMemPerBlock > 4096 ? prop.sharedMemPerBlock - 4096 : 0;
+    // LDS-staged pair passes with at most 52 KB per block (three blocks per
+    // CU); FIRE_LDS=0: global gathers only; FIRE_LDS=<bytes>: another limit
+    {
+      const char* e = getenv("FIRE_LDS");
+      const long v = e ? atol(e) : 1;
+      const size_t cap = prop.sharedMemPerBlock > 4096 ? prop.sharedMemPerBlock - 4096 : 0;
+      ctx->lds_limit = v <= 0 ? 0 : std::min<size_t>(cap, v == 1 ? 52 * 1024 : (size_t)v);
+    }
     HIPCHK(hipHostMalloc((void**)&ctx->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_status, 16 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_zero, sizeof(double), hipHostMallocDefault));
@@ -2171,6 +2354,7 @@ void fire_finalize(fire_ctx* ctx) {
   hipFree(ctx->aux);
   hipFree(ctx->ctrl);
   hipFree(ctx->flags);
+  hipFree(ctx->scan_part);
   hipFree(ctx->trace);
   if (ctx->h_flags) hipHostFree(ctx->h_flags);
   if (ctx->h_ctrl) hipHostFree(ctx->h_ctrl);
