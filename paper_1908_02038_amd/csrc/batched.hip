@@ -43,8 +43,32 @@ struct SysDesc {
   double rcs2;   // (cutoff + skin)^2 of this system
 };
 
-__device__ __forceinline__ void min_img(double& d, double L, double invL, int per) {
-  if (per) d -= L * rint(d * invL);
+// Minimum image along one axis; on free axes L = invL = 0 and d is unchanged.
+__device__ __forceinline__ void min_img(double& d, double L, double invL) { d -= L * rint(d * invL); }
+
+// Per-axis image shifts of a system: the box on periodic axes, zero on free ones.
+struct Img {
+  double L[3], iL[3];
+  __device__ explicit Img(const SysDesc& d) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      L[q] = d.box.per[q] ? d.box.L[q] : 0.0;
+      iL[q] = d.box.per[q] ? d.box.invL[q] : 0.0;
+    }
+  }
+  __device__ void apply(double& dx, double& dy, double& dz) const {
+    min_img(dx, L[0], iL[0]);
+    min_img(dy, L[1], iL[1]);
+    min_img(dz, L[2], iL[2]);
+  }
+};
+
+// Neighbour list of atom a (system-local 16-bit indices) in groups of four:
+// group g of atom a is the 8 bytes at nbr + base + (g * n + a) * 4, so the
+// atoms of a wave read consecutive 8-byte words.  Lists are padded to a
+// multiple of four with the atom's own index; nn[a] is the true length.
+__device__ __forceinline__ size_t nidx(size_t base, int n, int a, int q) {
+  return base + ((size_t)(q >> 2) * n + a) * 4 + (q & 3);
 }
 
 template <int TEAM>
@@ -89,12 +113,14 @@ struct Team {
   TeamShared& sh;
   const SysDesc& d;
   int n;
-  double4 v[MAXPT];   // velocity (w unused)
-  double4 f[MAXPT];   // force
-  double4 xr[MAXPT];  // position at the last list build
-  int ccell[MAXPT];
+  // velocity, force and the skin reference live in the global per-atom
+  // arrays (indexed d.off + a), read and written coalesced
+  double4* __restrict__ vel;
+  double4* __restrict__ frc;
+  double4* __restrict__ xref;
 
-  __device__ Team(TeamShared& s, const SysDesc& desc) : sh(s), d(desc), n(desc.n) {}
+  __device__ Team(TeamShared& s, const SysDesc& desc, double4* v, double4* f, double4* xr)
+      : sh(s), d(desc), n(desc.n), vel(v + desc.off), frc(f + desc.off), xref(xr + desc.off) {}
 
   __device__ int atom(int k) const { return threadIdx.x + k * TEAM; }
 
@@ -106,7 +132,7 @@ struct Team {
       lo3[q] = INFINITY;
       hi3[q] = -INFINITY;
     }
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < MAXPT; ++k) {
       const int a = atom(k);
       if (a >= n) continue;
@@ -124,7 +150,7 @@ struct Team {
         hi3[q] = fmax(hi3[q], r[q]);
       }
       sh.x[a] = make_double4(r[0], r[1], r[2], p.w);
-      xr[k] = make_double4(r[0], r[1], r[2], 0.0);
+      xref[a] = make_double4(r[0], r[1], r[2], 0.0);
     }
     // bounding box of the free axes
     double bb[6] = {-lo3[0], -lo3[1], -lo3[2], hi3[0], hi3[1], hi3[2]};
@@ -182,18 +208,20 @@ struct Team {
     }
     __syncthreads();
     const int ncell = sh.nc[0] * sh.nc[1] * sh.nc[2];
+    auto cell_of = [&](const double4& p) {
+      const double r[3] = {p.x, p.y, p.z};
+      int cc[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) cc[q] = min(max((int)floor((r[q] - sh.lo[q]) * sh.inv[q]), 0), sh.nc[q] - 1);
+      return cc[0] + sh.nc[0] * (cc[1] + sh.nc[1] * cc[2]);
+    };
     for (int c = threadIdx.x; c < ncell; c += TEAM) sh.cnt[c] = 0;
     __syncthreads();
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < MAXPT; ++k) {
       const int a = atom(k);
       if (a >= n) continue;
-      const double4 p = sh.x[a];
-      const double r[3] = {p.x, p.y, p.z};
-      int cc[3];
-      for (int q = 0; q < 3; ++q) cc[q] = min(max((int)floor((r[q] - sh.lo[q]) * sh.inv[q]), 0), sh.nc[q] - 1);
-      ccell[k] = cc[0] + sh.nc[0] * (cc[1] + sh.nc[1] * cc[2]);
-      atomicAdd(&sh.cnt[ccell[k]], 1);
+      atomicAdd(&sh.cnt[cell_of(sh.x[a])], 1);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -206,11 +234,12 @@ struct Team {
       sh.cstart[ncell] = acc;
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < MAXPT; ++k) {
       const int a = atom(k);
       if (a >= n) continue;
-      sh.cat[sh.cstart[ccell[k]] + atomicAdd(&sh.cnt[ccell[k]], 1)] = (unsigned short)a;
+      const int c = cell_of(sh.x[a]);
+      sh.cat[sh.cstart[c] + atomicAdd(&sh.cnt[c], 1)] = (unsigned short)a;
     }
     __syncthreads();
     for (int c = threadIdx.x; c < ncell; c += TEAM) {  // deterministic order: by atom index
@@ -227,12 +256,13 @@ struct Team {
     }
     __syncthreads();
     const size_t base = (size_t)d.off * kb;
-#pragma unroll
+    const Img img(d);
+#pragma unroll 1
     for (int k = 0; k < MAXPT; ++k) {
       const int a = atom(k);
       if (a >= n) continue;
       const double4 pa = sh.x[a];
-      const int c0 = ccell[k];
+      const int c0 = cell_of(pa);
       const int cc[3] = {c0 % sh.nc[0], (c0 / sh.nc[0]) % sh.nc[1], c0 / (sh.nc[0] * sh.nc[1])};
       int m = 0;
       for (int oz = sh.lo_off[2]; oz <= sh.hi_off[2]; ++oz) {
@@ -253,13 +283,11 @@ struct Team {
               if (j == a) continue;
               const double4 pj = sh.x[j];
               double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
-              min_img(dx, d.box.L[0], d.box.invL[0], d.box.per[0]);
-              min_img(dy, d.box.L[1], d.box.invL[1], d.box.per[1]);
-              min_img(dz, d.box.L[2], d.box.invL[2], d.box.per[2]);
+              img.apply(dx, dy, dz);
               const double r2 = dx * dx + dy * dy + dz * dz;
               if (r2 == 0.0) atomicOr(&sh.overflow, 2);
               if (r2 < d.rcs2) {
-                if (m < kb) nbr[base + (size_t)m * n + a] = (unsigned short)j;
+                if (m < kb) nbr[nidx(base, n, a, m)] = (unsigned short)j;
                 ++m;
               }
             }
@@ -267,6 +295,7 @@ struct Team {
         }
       }
       if (m > kb) atomicOr(&sh.overflow, 1);
+      for (int q = m; q < ((m + 3) & ~3) && q < kb; ++q) nbr[nidx(base, n, a, q)] = (unsigned short)a;
       nn[d.off + a] = (unsigned short)min(m, kb);
     }
     __syncthreads();
@@ -283,70 +312,90 @@ __device__ __forceinline__ T gupta_density_term(double r2, const PotDev& P) {
   return exp(-(T)P.qr0 * (r - (T)P.r0)) * (1 - s) * (1 - s) * (1 + 2 * s);
 }
 
+// Neighbour loop of the team passes: groups of four indices, the next group
+// loaded while the current one is processed; pair(q, m, pj) gets the entry
+// number q (entries q >= m are padding and must be masked) and the position.
+template <int TEAM, int MAXPT, typename F>
+__device__ __forceinline__ void for_team_neighbours(const Team<TEAM, MAXPT>& tm,
+                                                    const unsigned short* __restrict__ nbr,
+                                                    const unsigned short* __restrict__ nn, size_t base, int a,
+                                                    F&& pair) {
+  const int m = nn[tm.d.off + a];
+  const int ng = (m + 3) >> 2;
+  const ushort4* l4 = reinterpret_cast<const ushort4*>(nbr + base) + a;
+  const size_t stride = (size_t)tm.n;  // ushort4 elements between an atom's groups
+  ushort4 cur = ng > 0 ? l4[0] : make_ushort4(0, 0, 0, 0);
+  for (int g = 0; g < ng; ++g) {
+    const ushort4 c = cur;
+    if (g + 1 < ng) cur = l4[(size_t)(g + 1) * stride];
+    const double4 p0 = tm.sh.x[c.x], p1 = tm.sh.x[c.y], p2 = tm.sh.x[c.z], p3 = tm.sh.x[c.w];
+    pair(4 * g, m, p0);
+    pair(4 * g + 1, m, p1);
+    pair(4 * g + 2, m, p2);
+    pair(4 * g + 3, m, p3);
+  }
+}
+
 template <int TEAM, int MAXPT, typename T>
 __device__ void density_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigned short* __restrict__ nbr,
                              const unsigned short* __restrict__ nn, int kb, double& emb) {
   const SysDesc& d = tm.d;
   const size_t base = (size_t)d.off * kb;
-  double fp_new[MAXPT];
-#pragma unroll
+  const Img img(d);
+  // F'(rho) of the team's atoms is parked in frc[a].w (the force pass
+  // rewrites frc) until every neighbour read of the old values is done
+#pragma unroll 1
   for (int k = 0; k < MAXPT; ++k) {
     const int a = tm.atom(k);
-    fp_new[k] = 0.0;
     if (a >= tm.n) continue;
     const double4 pa = tm.sh.x[a];
     T rho = 0;
-    for (int q = 0, m = nn[d.off + a]; q < m; ++q) {
-      const int j = nbr[base + (size_t)q * tm.n + a];
-      const double4 pj = tm.sh.x[j];
+    for_team_neighbours(tm, nbr, nn, base, a, [&](int q, int m, const double4& pj) {
       double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
-      min_img(dx, d.box.L[0], d.box.invL[0], d.box.per[0]);
-      min_img(dy, d.box.L[1], d.box.invL[1], d.box.per[1]);
-      min_img(dz, d.box.L[2], d.box.invL[2], d.box.per[2]);
+      img.apply(dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const bool in = r2 < P.rc2;
+      const bool in = q < m && r2 < P.rc2;
       const T v = gupta_density_term<T>(in ? r2 : 1.0, P);
       rho += in ? v : (T)0;
-    }
+    });
+    double fp = 0.0;
     if (rho > 0) {
       const double sq = sqrt((double)rho);
-      fp_new[k] = -0.5 * P.xi / sq;
+      fp = -0.5 * P.xi / sq;
       emb += -P.xi * sq;
     }
+    reinterpret_cast<double*>(&tm.frc[a])[3] = fp;
   }
   __syncthreads();  // every neighbour read of w done before it changes
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < MAXPT; ++k) {
     const int a = tm.atom(k);
-    if (a < tm.n) tm.sh.x[a].w = fp_new[k];
+    if (a < tm.n) tm.sh.x[a].w = reinterpret_cast<const double*>(&tm.frc[a])[3];
   }
   __syncthreads();
 }
 
-template <int TEAM, int MAXPT, typename T>
+template <int TEAM, int MAXPT, int POT, typename T>
 __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigned short* __restrict__ nbr,
                            const unsigned short* __restrict__ nn, int kb, double (&r)[6]) {
   const SysDesc& d = tm.d;
   const size_t base = (size_t)d.off * kb;
+  const Img img(d);
   const double k3 = tm.sh.k3;
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < MAXPT; ++k) {
     const int a = tm.atom(k);
     if (a >= tm.n) continue;
     const double4 pa = tm.sh.x[a];
     T ax = 0, ay = 0, az = 0, ae = 0;
-    for (int q = 0, m = nn[d.off + a]; q < m; ++q) {
-      const int j = nbr[base + (size_t)q * tm.n + a];
-      const double4 pj = tm.sh.x[j];
+    for_team_neighbours(tm, nbr, nn, base, a, [&](int q, int m, const double4& pj) {
       double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
-      min_img(dx, d.box.L[0], d.box.invL[0], d.box.per[0]);
-      min_img(dy, d.box.L[1], d.box.invL[1], d.box.per[1]);
-      min_img(dz, d.box.L[2], d.box.invL[2], d.box.per[2]);
+      img.apply(dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const bool in = r2 < P.rc2;
+      const bool in = q < m && r2 < P.rc2;
       const double r2c = in ? r2 : 1.0;
       T fr, e;
-      if (P.kind == FIRE_POT_LJ) {
+      if constexpr (POT == FIRE_POT_LJ) {
         T ir2;
         if constexpr (sizeof(T) == 8) ir2 = rcp_d(r2c);
         else ir2 = rcp_f((float)r2c);
@@ -372,14 +421,15 @@ __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigne
       ay += fr * (T)dy;
       az += fr * (T)dz;
       ae += in ? e : (T)0;
-    }
-    double4& v = tm.v[k];
+    });
+    double4 v = tm.vel[a];
     const double fx = ax, fy = ay, fz = az;
-    tm.f[k] = make_double4(fx, fy, fz, 0.0);
+    tm.frc[a] = make_double4(fx, fy, fz, 0.0);
     if (k3 != 0.0) {
       v.x += k3 * fx;
       v.y += k3 * fy;
       v.z += k3 * fz;
+      tm.vel[a] = v;
     }
     const double f2 = fx * fx + fy * fy + fz * fz, v2 = v.x * v.x + v.y * v.y + v.z * v.z;
     r[0] += (double)ae;
@@ -391,18 +441,18 @@ __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigne
   }
 }
 
-template <int TEAM, int MAXPT>
+template <int TEAM, int MAXPT, int POT>
 __device__ void evaluate(Team<TEAM, MAXPT>& tm, Ctrl* __restrict__ c, const PotDev& P,
                          const unsigned short* __restrict__ nbr, const unsigned short* __restrict__ nn, int kb) {
   double r[6] = {0, 0, 0, 0, 0, 0};
   double emb = 0.0;
   const int prec = tm.sh.prec;
-  if (P.kind == FIRE_POT_GUPTA) {
+  if constexpr (POT == FIRE_POT_GUPTA) {
     if (prec) density_pass<TEAM, MAXPT, float>(tm, P, nbr, nn, kb, emb);
     else density_pass<TEAM, MAXPT, double>(tm, P, nbr, nn, kb, emb);
   }
-  if (prec) force_pass<TEAM, MAXPT, float>(tm, P, nbr, nn, kb, r);
-  else force_pass<TEAM, MAXPT, double>(tm, P, nbr, nn, kb, r);
+  if (prec) force_pass<TEAM, MAXPT, POT, float>(tm, P, nbr, nn, kb, r);
+  else force_pass<TEAM, MAXPT, POT, double>(tm, P, nbr, nn, kb, r);
   r[0] += emb;
   team_reduce<TEAM>(r, tm.sh.red);
   if (threadIdx.x == 0) {
@@ -428,7 +478,7 @@ __device__ void evaluate(Team<TEAM, MAXPT>& tm, Ctrl* __restrict__ c, const PotD
 
 // Persistent team kernel: pull systems from the queue, advance each by up to
 // `chunk` iterations.  Arrays are indexed by the concatenated atom index.
-template <int TEAM, int MAXPT>
+template <int TEAM, int MAXPT, int POT>
 __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ desc, Ctrl* __restrict__ ctrl,
                                                   const int* __restrict__ order, int nsys, int* __restrict__ queue,
                                                   double4* __restrict__ pos, double4* __restrict__ vel,
@@ -452,17 +502,8 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
     }
     const SysDesc d = desc[s];
     Ctrl* c = &ctrl[s];
-    Team<TEAM, MAXPT> tm(sh, d);
+    Team<TEAM, MAXPT> tm(sh, d, vel, frc, xref);
     for (int a = threadIdx.x; a < d.n; a += TEAM) sh.x[a] = pos[d.off + a];
-#pragma unroll
-    for (int k = 0; k < MAXPT; ++k) {
-      const int a = tm.atom(k);
-      if (a < d.n) {
-        tm.v[k] = vel[d.off + a];
-        tm.f[k] = frc[d.off + a];
-        tm.xr[k] = xref[d.off + a];
-      }
-    }
     if (threadIdx.x == 0) {
       sh.viol = c->viol;
       sh.prec = c->precision;
@@ -485,7 +526,7 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
     if (ok && c->evals == 0) {  // evaluation 0 and the set-up of iteration 1
       if (threadIdx.x == 0) sh.k3 = 0.0;
       __syncthreads();
-      evaluate(tm, c, P, nbr, nn, kb);
+      evaluate<TEAM, MAXPT, POT>(tm, c, P, nbr, nn, kb);
     }
     for (int it = 0; ok && it < chunk && sh.status == ST_RUNNING; ++it) {
       // ---- update (same step as the single-system update kernel)
@@ -495,8 +536,9 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
         const int a = tm.atom(k);
         if (a >= d.n) continue;
         const double4 p = sh.x[a];
-        double vv[3] = {tm.v[k].x, tm.v[k].y, tm.v[k].z};
-        const double ff[3] = {tm.f[k].x, tm.f[k].y, tm.f[k].z};
+        const double4 v0 = tm.vel[a], f0 = tm.frc[a], xr = tm.xref[a];
+        double vv[3] = {v0.x, v0.y, v0.z};
+        const double ff[3] = {f0.x, f0.y, f0.z};
         double xx[3] = {p.x, p.y, p.z};
         for (int q = 0; q < 3; ++q) {
           double vd = vv[q], xd = xx[q];
@@ -512,9 +554,9 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
           vv[q] = vd;
           xx[q] = xd;
         }
-        tm.v[k] = make_double4(vv[0], vv[1], vv[2], 0.0);
+        tm.vel[a] = make_double4(vv[0], vv[1], vv[2], 0.0);
         sh.x[a] = make_double4(xx[0], xx[1], xx[2], p.w);
-        const double ex = xx[0] - tm.xr[k].x, ey = xx[1] - tm.xr[k].y, ez = xx[2] - tm.xr[k].z;
+        const double ex = xx[0] - xr.x, ey = xx[1] - xr.y, ez = xx[2] - xr.z;
         if (ex * ex + ey * ey + ez * ez > c->skin_half2) viol = 1;
       }
       if (threadIdx.x == 0) sh.viol = 0;
@@ -528,7 +570,7 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
           break;
         }
       }
-      evaluate(tm, c, P, nbr, nn, kb);
+      evaluate<TEAM, MAXPT, POT>(tm, c, P, nbr, nn, kb);
     }
     if (!ok && threadIdx.x == 0) {
       // list capacity exceeded or atoms coincide: hand the system to the host
@@ -539,17 +581,8 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
         atomicMax(&flags[0], 1);
       }
     }
-    // write the system back
+    // write the positions back (v, F and the skin reference are in place)
     for (int a = threadIdx.x; a < d.n; a += TEAM) pos[d.off + a] = sh.x[a];
-#pragma unroll
-    for (int k = 0; k < MAXPT; ++k) {
-      const int a = tm.atom(k);
-      if (a < d.n) {
-        vel[d.off + a] = tm.v[k];
-        frc[d.off + a] = tm.f[k];
-        xref[d.off + a] = tm.xr[k];
-      }
-    }
     if (threadIdx.x == 0) c->viol = ok ? 0 : 1;
     __syncthreads();
   }
@@ -618,9 +651,9 @@ struct Config {
 using KernelFn = void (*)(const SysDesc*, Ctrl*, const int*, int, int*, double4*, double4*, double4*, double4*,
                           unsigned short*, unsigned short*, int, PotDev, int, int*);
 
-KernelFn kernel_for(int team) {
-  if (team == 1024) return k_batched<1024, 4>;
-  return k_batched<512, 8>;
+KernelFn kernel_for(int team, int pot) {
+  if (pot == FIRE_POT_LJ) return team == 1024 ? k_batched<1024, 4, FIRE_POT_LJ> : k_batched<512, 8, FIRE_POT_LJ>;
+  return team == 1024 ? k_batched<1024, 4, FIRE_POT_GUPTA> : k_batched<512, 8, FIRE_POT_GUPTA>;
 }
 
 struct Workspace {
@@ -718,7 +751,7 @@ int reset_state(fire_ctx* ctx, Workspace* w, const std::vector<Ctrl>& c0, hipStr
 // One replay unit: reset the queue and run the persistent kernel once.
 void launch_chunk(Workspace* w, const PotDev& P, const Config& cf, hipStream_t s, int nteams) {
   hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, w->queue);
-  KernelFn fn = kernel_for(cf.team);
+  KernelFn fn = kernel_for(cf.team, P.kind);
   hipLaunchKernelGGL(fn, dim3(nteams), dim3(cf.team), 0, s, w->desc, w->ctrl, w->order, w->nsys, w->queue, w->pos,
                      w->vel, w->frc, w->xref, w->nbr, w->nn, w->kb, P, cf.chunk, w->queue + 2);
   hipLaunchKernelGGL(k_count_running, dim3(1), dim3(1024), 0, s, w->ctrl, w->nsys, w->queue + 1);
@@ -828,7 +861,7 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
                                    })->rcs2);
   (void)rcs_max;
   int kb = (int)(4.18879 * std::max(max_dens_vol, 0.1 * 1.0) * 1.6) + 24;
-  kb = std::max(kb, 32);
+  kb = (std::max(kb, 32) + 3) & ~3;  // lists are read in groups of four
   // the systems in decreasing size
   std::vector<int> order(nsys);
   for (int q = 0; q < nsys; ++q) order[q] = q;
@@ -918,7 +951,7 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     }
     hipGraphExecDestroy(exec);
     if (need_more) {
-      kb = kb * 3 / 2 + 16;
+      kb = ((kb * 3 / 2 + 16) + 3) & ~3;
       continue;
     }
     // ---- results
