@@ -38,8 +38,20 @@ PEAK_FP64_TFLOPS = 78.6
 # read for P = F.v, forces written (3 x 8 B each); the EAM form adds F'(rho)
 # written and read (2 x 8 B).
 ALG = {
-    "lj": {"bytes": 72.0, "flops": 27.0 * 25.0, "kernel": "k_lj_force"},
-    "gupta": {"bytes": 88.0, "flops": 21.0 * 125.0, "kernel": "k_gupta_force"},
+    "lj": {"bytes": 72.0, "flops": 27.0 * 25.0, "kernel": "k_lj_force", "tag": "k_lj_force_global"},
+    "gupta": {"bytes": 120.0, "flops": 21.0 * 165.0, "kernel": "k_gupta_density + k_gupta_force",
+              "tag": "k_gupta_global"},
+}
+# The LDS-staged loop folds the update into the first pass of each iteration
+# (the kernel that dominates a relaxation): per atom it also reads the
+# position at the last list build and writes the new position and velocity
+# (x, v, F read; x, v, F written; x_ref read: 7 x 24 B), and does ~20 more flop.
+FUSED = {
+    "lj": {"bytes": 168.0, "flops": 27.0 * 25.0 + 20.0, "kernel": "k_lj_force<double, true, false, true>",
+           "tag": "k_lj_force_fused"},
+    "gupta": {"bytes": 216.0, "flops": 21.0 * 165.0 + 20.0,
+              "kernel": "k_gupta_density<double, true, true> + k_gupta_force<double, true, false>",
+              "tag": "k_gupta_fused"},
 }
 
 
@@ -55,10 +67,10 @@ def source_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def load_traffic(kernel: str, workload: str):
+def load_traffic(tag: str, workload: str):
     """HBM traffic per launch from a committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -265,7 +277,8 @@ def main():
     log(f"[bench] fp64: {args.steps} relaxations in {dt:.3f} s, {r['iterations']} iterations each, "
         f"stop {r['stop']}, E/N {r['energy_per_atom']:.12f}, fmax {r['fmax']:.3e}, rebuilds {r['rebuilds']}")
     kt = kernel_time_ms(ctx, args.kernel_reps)
-    alg = ALG[kind]
+    staged = os.environ.get("FIRE_LDS", "1") != "0"  # LDS-staged tiles (and the folded update) unless switched off
+    alg = FUSED[kind] if staged else ALG[kind]
     bytes_launch = alg["bytes"] * n
     flops_launch = alg["flops"] * n
     hbm_ach = bytes_launch / (kt * 1e-3) / 1e9
@@ -273,15 +286,14 @@ def main():
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
     ai = alg["flops"] / alg["bytes"]
     kname = alg["kernel"]
-    traffic = load_traffic(kname, args.workload)
+    traffic = load_traffic(alg["tag"], args.workload)
     if ai > ridge:
         roof = {"bound": "alu", "achieved": alu_ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": alu_ach / PEAK_FP64_TFLOPS}
     else:
         roof = {"bound": "hbm", "achieved": hbm_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": hbm_ach / PEAK_HBM_GBS}
-    staged = os.environ.get("FIRE_LDS", "1") != "0"  # LDS-staged tiles unless switched off
-    roof.update({"traffic": traffic, "kernel": kname + ("<double, true, false>" if staged else "<double, false, false>"),
+    roof.update({"traffic": traffic, "kernel": kname if staged else kname + "<double, false, false>",
                  "ms_per_launch": kt,
                  "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops_launch,
                  "hbm_achieved_GBs": hbm_ach, "hbm_frac": hbm_ach / PEAK_HBM_GBS,

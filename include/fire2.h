@@ -218,9 +218,11 @@ int fire_minimize_batched_dev(fire_ctx* ctx, int nsys, const long long* offsets,
 /* Measurement hook: re-run the force evaluation (density and force passes for
  * the EAM form) of the system left by the last call on ctx, at its current
  * positions and neighbour list, reps times on stream, with the same kernels
- * and launch shapes as inside fire_minimize and the precision of the
- * context's params.  Forces and reductions are recomputed to the same values;
- * nothing else changes.  FIRE_E_ARG if no system has been evaluated yet. */
+ * and launch shapes as one iteration inside fire_minimize (where the update
+ * is folded into the first pass, that pass with a zero update, writing the
+ * context's second state set) and the precision of the context's params.
+ * The system's positions, velocities, forces and FIRE state do not change.
+ * FIRE_E_ARG if no system has been evaluated yet. */
 int fire_repeat_forces_dev(fire_ctx* ctx, int reps, void* stream);
 
 #ifdef __cplusplus

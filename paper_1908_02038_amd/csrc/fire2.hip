@@ -456,12 +456,12 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-// Neighbour k of lane `lane` of wave w: groups of four consecutive neighbours
-// of one atom are adjacent, so a lane fetches a group with one vector load and
-// a wave's group loads are contiguous.
 // Dynamic LDS of the kernels that size it at launch.
 extern __shared__ __align__(16) unsigned char dyn_lds[];
 
+// Neighbour k of lane `lane` of wave w: groups of four consecutive neighbours
+// of one atom are adjacent, so a lane fetches a group with one vector load and
+// a wave's group loads are contiguous.
 __device__ __forceinline__ size_t lidx(int w, int k, int lane, int kcap) {
   return (((size_t)w * (kcap >> 2) + (k >> 2)) * 64 + lane) * 4 + (k & 3);
 }
@@ -631,8 +631,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
                                                       const int* __restrict__ cell_rank, int n, Grid g,
                                                       const int* __restrict__ nbr, const int* __restrict__ wcnt,
                                                       int kcap, int hcap, int dummy, int* __restrict__ tile_h,
-                                                      int* __restrict__ hslot, unsigned short* __restrict__ nbr16,
-                                                      int* __restrict__ flags) {
+                                                      int* __restrict__ hslot, int* __restrict__ hsrc,
+                                                      const int* __restrict__ real_of,
+                                                      unsigned short* __restrict__ nbr16, int* __restrict__ flags) {
   __shared__ int cand[kCandMax];
   __shared__ int hoff[kCandMax + 1];
   __shared__ int dcell[kBlock];
@@ -705,6 +706,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
   }
   auto halo_index = [&](int q) { return wpre[q >> 5] + __popc(used[q >> 5] & ((1u << (q & 31)) - 1u)); };
   int* hs = hslot + (size_t)b * hcap;
+  int* hr = hsrc + (size_t)b * hcap;
   for (int q = t; q < Hc; q += blockDim.x) {
     if (!(used[q >> 5] & (1u << (q & 31)))) continue;
     int lo = 0, hi = nu - 1;  // last run h with hoff[h] <= q
@@ -713,7 +715,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
       if (hoff[mid] <= q) lo = mid;
       else hi = mid - 1;
     }
-    hs[halo_index(q)] = cslot[lo] + (q - hoff[lo]);
+    const int j = cslot[lo] + (q - hoff[lo]);
+    hs[halo_index(q)] = j;
+    hr[halo_index(q)] = real_of[j];
   }
   // pass 2: candidate index -> halo index
   for (int k = 0; k < kw; ++k) {
@@ -740,6 +744,36 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
 // An atom farther than skin/2 from its position at the last list build sets
 // ctrl->viol; the next force pass then hands control to the host for a
 // rebuild.
+// Coefficients of the pending update, as the control left them.
+struct UpdCoef {
+  int neg, mix_first;
+  double hsb, k1, k2, cv, cf, dtx;
+};
+__device__ __forceinline__ UpdCoef load_coef(const Ctrl* __restrict__ c) {
+  return UpdCoef{c->neg, c->mix_first, c->hsb, c->kick1, c->kick2, c->cv, c->cf, c->dtx};
+}
+// One atom's update (x, v in place) from its force f.  Every caller -- the
+// update kernel, and the passes that apply the update while staging their
+// halo -- runs this same arithmetic, so an atom gets the same bits wherever it
+// is updated.
+__device__ __forceinline__ void fire_step(const UpdCoef& u, double (&x)[3], double (&v)[3], const double (&f)[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double vd = v[d], xd = x[d];
+    if (u.neg) {
+      xd -= u.hsb * vd;
+      vd = 0.0;
+    }
+    if (u.mix_first) vd = u.cv * vd + u.cf * f[d];
+    vd = vd + u.k1 * f[d];
+    if (!u.mix_first) vd = u.cv * vd + u.cf * f[d];
+    xd = xd + u.dtx * vd;
+    vd = vd + u.k2 * f[d];
+    v[d] = vd;
+    x[d] = xd;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, double* __restrict__ vel,
                                                    const double* __restrict__ frc,
                                                    const double4* __restrict__ xref, const int* __restrict__ gcnt,
@@ -757,25 +791,9 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
   const double4 r = xref[i];
   const int gc = gcnt[i];
   if (!ctrl_running(ctrl)) return;
-  const int neg = ctrl->neg, mix_first = ctrl->mix_first;
-  const double hsb = ctrl->hsb, k1 = ctrl->kick1, k2 = ctrl->kick2, cv = ctrl->cv, cf = ctrl->cf,
-               dtx = ctrl->dtx;
+  const UpdCoef u = load_coef(ctrl);
   double x[3] = {p.x, p.y, p.z};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double vd = v[d], xd = x[d];
-    if (neg) {
-      xd -= hsb * vd;
-      vd = 0.0;
-    }
-    if (mix_first) vd = cv * vd + cf * f[d];
-    vd = vd + k1 * f[d];
-    if (!mix_first) vd = cv * vd + cf * f[d];
-    xd = xd + dtx * vd;
-    vd = vd + k2 * f[d];
-    v[d] = vd;
-    x[d] = xd;
-  }
+  fire_step(u, x, v, f);
   pos[i] = make_double4(x[0], x[1], x[2], p.w);
   vel[i] = v[0];
   vel[ncap + i] = v[1];
@@ -789,12 +807,49 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
   if (ex * ex + ey * ey + ez * ez > ctrl->skin_half2) atomicOr(&ctrl->viol, 1);
 }
 
+// The loop that folds the update into the next pass leaves the state in
+// either set (ctrl->cur).  These two kernels make the primary set current and
+// complete: the second set's real atoms are copied over if it holds the state,
+// then every periodic image is rebuilt from its source (that loop does not
+// keep the images of the LJ pass up to date).
+__global__ __launch_bounds__(kBlock) void k_state_home(int n, int ncap, const double4* __restrict__ pos2,
+                                                       const double* __restrict__ vel2,
+                                                       const double* __restrict__ frc2, double4* __restrict__ pos,
+                                                       double* __restrict__ vel, double* __restrict__ frc,
+                                                       const Ctrl* __restrict__ ctrl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || ctrl->cur == 0) return;
+  pos[i] = pos2[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    vel[d * ncap + i] = vel2[d * ncap + i];
+    frc[d * ncap + i] = frc2[d * ncap + i];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ghost_refresh(int n, int ng, double4* __restrict__ pos,
+                                                          const int* __restrict__ real_of,
+                                                          const int* __restrict__ gcode, BoxDev box,
+                                                          Ctrl* __restrict__ ctrl) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) ctrl->cur = 0;
+  if (g >= ng) return;
+  const double4 p = pos[real_of[n + g]];
+  const int code = gcode[g];
+  pos[n + g] = make_double4(p.x + ghost_shift(code, 0, box), p.y + ghost_shift(code, 1, box),
+                            p.z + ghost_shift(code, 2, box), p.w);
+}
+
 // Entry gate of the force-evaluation kernels: run only while the FIRE loop is
 // running and the list is valid; the first block that sees a skin violation
 // hands control to the host.
+// A pass that applies the update itself (UPD) sets the skin flag while it
+// runs: it checks the status only, and its last block acts on the flag.
+template <bool UPD = false>
 __device__ __forceinline__ bool pass_gate(Ctrl* c) {
   const int st = __hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (st != ST_RUNNING) return false;
+  if constexpr (UPD) return true;
   if (__hip_atomic_load(&c->viol, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       c->pause |= PAUSE_REBUILD;
@@ -816,7 +871,8 @@ __device__ __forceinline__ double ld_cohere(const double* p) {
 __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, double fy, double fz, double e,
                                                double* __restrict__ frc, double* __restrict__ vel, int ncap,
                                                double* __restrict__ part, const double* __restrict__ part_emb,
-                                               int rec, Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
+                                               int rec, Ctrl* __restrict__ ctrl, double* __restrict__ trace,
+                                               bool check_viol = false) {
   double r[6] = {0, 0, 0, 0, 0, 0};
   if (valid) {
     frc[i] = fx;
@@ -870,7 +926,14 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
   block_reduce<4, 2>(q);
   if (threadIdx.x == 0) {
     ctrl->ticket = 0;
-    fire_control(ctrl, q, trace);
+    if (check_viol && __hip_atomic_load(&ctrl->viol, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      // the update applied in this pass moved an atom past its skin: these
+      // forces used a stale list; hand over for a rebuild, FIRE state unchanged
+      ctrl->pause |= PAUSE_REBUILD;
+      __hip_atomic_store(&ctrl->status, ST_PAUSED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      fire_control(ctrl, q, trace);
+    }
   }
 }
 
@@ -880,6 +943,7 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
 struct Tiles {
   const int* tile_h;           // halo size per tile
   const int* hslot;            // halo slot lists, hcap per tile
+  const int* hsrc;             // the real atom behind each halo slot (itself, or an image's source)
   const unsigned short* nbr16; // neighbour lists as halo indices
   int hcap;
 };
@@ -998,22 +1062,136 @@ __device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, 
   }
 }
 
+// One set of per-atom state: positions (slots, with periodic images),
+// velocities and forces (3 planes of ncap).  The LDS-staged loop keeps two
+// sets and alternates between them: a pass that applies the update reads one
+// and writes the other.
+struct StateBuf {
+  double4* pos;
+  double* vel;
+  double* frc;
+};
+
+// What a pass that applies the pending update needs besides the state.
+struct UpdArgs {
+  StateBuf src, dst;
+  int dst_index;                  // 1 if dst is the second set
+  const int* real_of;             // slot -> source real slot
+  const int* gcode;               // image shift codes of the periodic images
+  const int* gcnt;                // images per real atom
+  const int* glist;               // their slots
+  const double4* xref;            // positions at the last list build
+  BoxDev box;
+};
+
+// Tile b's halo with the pending update applied on the fly: each halo atom
+// (an image through its source and shift) is advanced from `src` by
+// fire_step, exactly as its owner advances it.
+__device__ __forceinline__ Halo stage_halo_updated(const UpdArgs& ua, const UpdCoef& u, const Tiles& tl, int b,
+                                                   int n, int ncap) {
+  double* h = reinterpret_cast<double*>(dyn_lds);
+  const int H = tl.tile_h[b];
+  const int S = H + 1;
+  const int* hs = tl.hslot + (size_t)b * tl.hcap;
+  const int* hr = tl.hsrc + (size_t)b * tl.hcap;
+  const int step = blockDim.x;
+  for (int q0 = threadIdx.x; q0 < H; q0 += 2 * step) {  // two entries in flight
+    int j[2], r[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int q = q0 + e * step;
+      j[e] = q < H ? hs[q] : -1;
+      r[e] = q < H ? hr[q] : 0;
+    }
+    double x[2][3], v[2][3], f[2][3];
+    int code[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (j[e] < 0) continue;
+      const double4 p = ua.src.pos[r[e]];
+      x[e][0] = p.x;
+      x[e][1] = p.y;
+      x[e][2] = p.z;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        v[e][d] = ua.src.vel[d * ncap + r[e]];
+        f[e][d] = ua.src.frc[d * ncap + r[e]];
+      }
+      code[e] = j[e] >= n ? ua.gcode[j[e] - n] : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (j[e] < 0) continue;
+      fire_step(u, x[e], v[e], f[e]);
+      const int q = q0 + e * step;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) h[d * S + q] = x[e][d] + ghost_shift(code[e], d, ua.box);
+    }
+  }
+  if (threadIdx.x == 0) {
+    h[H] = kFar;
+    h[S + H] = kFar;
+    h[2 * S + H] = kFar;
+  }
+  __syncthreads();
+  return Halo{h, S};
+}
+
+// The pending update of a pass's own atom i (< n): new position (returned,
+// w as in src) and velocity written to dst, skin test against the build
+// positions.
+__device__ __forceinline__ double4 own_update(const UpdArgs& ua, const UpdCoef& u, int i, int ncap, Ctrl* ctrl) {
+  const double4 p = ua.src.pos[i];
+  double x[3] = {p.x, p.y, p.z};
+  double v[3] = {ua.src.vel[i], ua.src.vel[ncap + i], ua.src.vel[2 * ncap + i]};
+  const double f[3] = {ua.src.frc[i], ua.src.frc[ncap + i], ua.src.frc[2 * ncap + i]};
+  fire_step(u, x, v, f);
+  ua.dst.vel[i] = v[0];
+  ua.dst.vel[ncap + i] = v[1];
+  ua.dst.vel[2 * ncap + i] = v[2];
+  const double4 xr = ua.xref[i];
+  const double ex = x[0] - xr.x, ey = x[1] - xr.y, ez = x[2] - xr.z;
+  if (ex * ex + ey * ey + ez * ez > ctrl->skin_half2) atomicOr(&ctrl->viol, 1);
+  return make_double4(x[0], x[1], x[2], p.w);
+}
+
 // Energy-shifted LJ.  Separations and the r^2 < rc^2 test in FP64; the pair
 // terms and per-atom accumulation in T (double, or float for the mixed path).
 // WE: accumulate the energy (the FIRE logic itself needs only forces).
-template <typename T, bool LDS, bool WE>
+// UPD: the pass first applies the pending update (halo atoms on the fly in
+// LDS, own atoms written to ua.dst) and reads and writes ua's state sets
+// instead of pos / frc / vel; requires LDS.
+template <typename T, bool LDS, bool WE, bool UPD = false>
 __global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
                                                      Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
                                                      int ncap, PotDev pot, double* __restrict__ frc,
                                                      double* __restrict__ vel, double* __restrict__ part,
-                                                     Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
-  if (!pass_gate(ctrl)) return;
+                                                     Ctrl* __restrict__ ctrl, double* __restrict__ trace,
+                                                     UpdArgs ua) {
+  static_assert(!UPD || LDS, "the update is applied while staging the LDS halo");
+  if (!pass_gate<UPD>(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const Halo halo = LDS ? stage_halo<false>(pos, tl, b) : Halo{nullptr, 0};
   const int i = b * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   T ax = 0, ay = 0, az = 0, ae = 0;
-  const double4 pi = pos[i];
+  Halo halo{nullptr, 0};
+  double4 pi;
+  if constexpr (UPD) {
+    const UpdCoef u = load_coef(ctrl);
+    if (valid) {
+      pi = own_update(ua, u, i, ncap, ctrl);
+      ua.dst.pos[i] = pi;
+    } else {
+      pi = ua.src.pos[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->cur = ua.dst_index;
+    halo = stage_halo_updated(ua, u, tl, b, n, ncap);
+    frc = ua.dst.frc;
+    vel = ua.dst.vel;
+  } else {
+    if constexpr (LDS) halo = stage_halo<false>(pos, tl, b);
+    pi = pos[i];
+  }
   const T eps24 = (T)(24.0 * pot.eps), eps4 = (T)(4.0 * pot.eps), sig2 = (T)pot.sig2, sh = (T)pot.shift;
   for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
     const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
@@ -1032,23 +1210,38 @@ __global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__
     if constexpr (WE) ae += in ? (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh) : (T)0;
   });
   force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, nullptr, b, ctrl,
-                 trace);
+                 trace, UPD);
 }
 
 // Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
 // F'(rho_i) = -xi / (2 sqrt(rho_i)) in pos[i].w and sums F(rho_i) per block.
-template <typename T, bool LDS>
+// UPD: the pass first applies the pending update (as in k_lj_force) and
+// writes the new positions, with F'(rho) in .w, of its atoms and their
+// periodic images to ua.dst.pos; requires LDS.
+template <typename T, bool LDS, bool UPD = false>
 __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ pos, const int* __restrict__ nbr,
                                                           Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
-                                                          PotDev pot, const int* __restrict__ gcnt,
+                                                          int ncap, PotDev pot, const int* __restrict__ gcnt,
                                                           const int* __restrict__ glist,
-                                                          double* __restrict__ part_emb, Ctrl* __restrict__ ctrl) {
-  if (!pass_gate(ctrl)) return;
+                                                          double* __restrict__ part_emb, Ctrl* __restrict__ ctrl,
+                                                          UpdArgs ua) {
+  static_assert(!UPD || LDS, "the update is applied while staging the LDS halo");
+  if (!pass_gate<UPD>(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const Halo halo = LDS ? stage_halo<false>(pos, tl, b) : Halo{nullptr, 0};
   const int i = b * blockDim.x + threadIdx.x;
   double emb = 0.0;
-  const double4 pi = pos[i];
+  Halo halo{nullptr, 0};
+  double4 pi;
+  if constexpr (UPD) {
+    const UpdCoef u = load_coef(ctrl);
+    pi = i < n ? own_update(ua, u, i, ncap, ctrl) : ua.src.pos[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->cur = ua.dst_index;
+    halo = stage_halo_updated(ua, u, tl, b, n, ncap);
+    pos = ua.dst.pos;
+  } else {
+    if constexpr (LDS) halo = stage_halo<false>(pos, tl, b);
+    pi = pos[i];
+  }
   const T qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in, inv_w = (T)pot.inv_w;
   T rho = 0;
   for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
@@ -1070,8 +1263,17 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
       fp = -0.5 * pot.xi / sq;
       emb = -pot.xi * sq;
     }
-    pos[i].w = fp;
-    for (int k = 0, gc = gcnt[i]; k < gc; ++k) pos[glist[8 * i + k]].w = fp;
+    if constexpr (UPD) {  // new position and its images, with F'(rho)
+      pos[i] = make_double4(pi.x, pi.y, pi.z, fp);
+      for (int k = 0, gc = gcnt[i]; k < gc; ++k) {
+        const int g = glist[8 * i + k], code = ua.gcode[g - n];
+        pos[g] = make_double4(pi.x + ghost_shift(code, 0, ua.box), pi.y + ghost_shift(code, 1, ua.box),
+                              pi.z + ghost_shift(code, 2, ua.box), fp);
+      }
+    } else {
+      pos[i].w = fp;
+      for (int k = 0, gc = gcnt[i]; k < gc; ++k) pos[glist[8 * i + k]].w = fp;
+    }
   }
   double r[1] = {emb};
   block_reduce<1, 0>(r);
@@ -1333,7 +1535,10 @@ struct fire_ctx {
   // ---- single-system workspace
   int n = 0, ncap = 0;        // real atoms and capacity (multiple of the block size)
   int ng = 0, tcap = 0;       // ghosts; slot capacity (real + ghost + padding slot tcap - 1)
-  double4 *pos = nullptr, *pos2 = nullptr;   // slots
+  // slots; pos2 / vel2 / frc2 are the permutation scratch of a rebuild and,
+  // between rebuilds, the second state set of the loop that folds the update
+  // into the next pass (ctrl->cur says which set is current)
+  double4 *pos = nullptr, *pos2 = nullptr;
   double *vel = nullptr, *vel2 = nullptr, *frc = nullptr, *frc2 = nullptr;
   int *id = nullptr, *id2 = nullptr, *cell_of = nullptr, *order = nullptr;
   long long* key = nullptr;                  // in-cell ordering key per slot
@@ -1354,6 +1559,7 @@ struct fire_ctx {
   // LDS-staged tiles
   int* tile_h = nullptr;
   int* hslot = nullptr;
+  int* hsrc = nullptr;
   unsigned short* nbr16 = nullptr;
   int hcap = 0;
   bool use_lds = false;
@@ -1426,13 +1632,13 @@ void free_single(fire_ctx* c) {
   hipFree(c->vel); hipFree(c->vel2); hipFree(c->frc); hipFree(c->frc2);
   hipFree(c->id); hipFree(c->id2); hipFree(c->stage);
   hipFree(c->part); hipFree(c->part_emb); hipFree(c->bbox_part);
-  hipFree(c->xref); hipFree(c->wcnt); hipFree(c->tile_h); hipFree(c->hslot); hipFree(c->nbr16);
+  hipFree(c->xref); hipFree(c->wcnt); hipFree(c->tile_h); hipFree(c->hslot); hipFree(c->hsrc); hipFree(c->nbr16);
   hipFree(c->gcount); hipFree(c->goff); hipFree(c->gcnt); hipFree(c->glist); hipFree(c->new_of_old);
   c->vel = c->vel2 = c->frc = c->frc2 = nullptr;
   c->id = c->id2 = nullptr;
   c->stage = c->part = c->part_emb = c->bbox_part = nullptr;
   c->xref = nullptr;
-  c->wcnt = c->tile_h = c->hslot = nullptr;
+  c->wcnt = c->tile_h = c->hslot = c->hsrc = nullptr;
   c->nbr16 = nullptr;
   c->gcount = c->goff = c->gcnt = c->glist = c->new_of_old = nullptr;
   c->use_lds = false;
@@ -1739,8 +1945,10 @@ int build_lists(fire_ctx* ctx) {
     if (!ctx->nbr16) HIPCHK(dalloc(&ctx->nbr16, (size_t)ctx->kcap * ctx->ncap));
     if (hcap >= 64 && (!ctx->hslot || ctx->hcap != hcap)) {
       hipFree(ctx->hslot);
-      ctx->hslot = nullptr;
+      hipFree(ctx->hsrc);
+      ctx->hslot = ctx->hsrc = nullptr;
       HIPCHK(dalloc(&ctx->hslot, (size_t)hcap * (ctx->ncap / kBlock)));
+      HIPCHK(dalloc(&ctx->hsrc, (size_t)hcap * (ctx->ncap / kBlock)));
       ctx->hcap = hcap;
       ctx->layout_version++;
     }
@@ -1750,7 +1958,7 @@ int build_lists(fire_ctx* ctx) {
     if (hcap >= 64)
       hipLaunchKernelGGL(k_tile_halo, dim3(nb), dim3(kBlock), 0, s, ctx->srank, ctx->cell_start, ctx->rank_cell,
                          ctx->cell_rank, n, ctx->grid, ctx->nbr, ctx->wcnt, ctx->kcap, hcap, dummy, ctx->tile_h,
-                         ctx->hslot, ctx->nbr16, ctx->flags);
+                         ctx->hslot, ctx->hsrc, ctx->real_of, ctx->nbr16, ctx->flags);
     int rc = read_flags(ctx);
     if (rc) return rc;
     if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
@@ -1855,19 +2063,56 @@ int rebuild(fire_ctx* ctx) {
   return FIRE_OK;
 }
 
+StateBuf state_set(fire_ctx* ctx, int k) {
+  return k ? StateBuf{ctx->pos2, ctx->vel2, ctx->frc2} : StateBuf{ctx->pos, ctx->vel, ctx->frc};
+}
+
+UpdArgs upd_args(fire_ctx* ctx, int parity) {
+  UpdArgs u;
+  u.src = state_set(ctx, parity);
+  u.dst = state_set(ctx, parity ^ 1);
+  u.dst_index = parity ^ 1;
+  u.real_of = ctx->real_of;
+  u.gcode = ctx->gcode;
+  u.gcnt = ctx->gcnt;
+  u.glist = ctx->glist;
+  u.xref = ctx->xref;
+  u.box = ctx->box;
+  return u;
+}
+
+// The passes of one force evaluation.  parity < 0: on the primary state set;
+// parity 0 / 1: the first pass also applies the pending update, reading set
+// `parity` and writing the other (LDS-staged passes only).
 template <typename T, bool LDS, bool WE>
-void launch_pair_passes(fire_ctx* ctx, hipStream_t s) {
+void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
   const int n = ctx->n, nb = nblocks(n), kc = ctx->kcap, nc = ctx->ncap;
   const PotDev& P = ctx->pot;
-  const Tiles tl{ctx->tile_h, ctx->hslot, ctx->nbr16, ctx->hcap};
+  const Tiles tl{ctx->tile_h, ctx->hslot, ctx->hsrc, ctx->nbr16, ctx->hcap};
   const size_t sm = LDS ? ctx->lds_atoms * 24 : 0;     // x, y, z
   const size_t smw = LDS ? ctx->lds_atoms * 32 : 0;    // x, y, z, F'(rho)
+  const UpdArgs ua = upd_args(ctx, parity < 0 ? 0 : parity);
+  if constexpr (LDS) {
+    if (parity >= 0) {
+      const StateBuf d = ua.dst;
+      if (P.kind == FIRE_POT_LJ) {
+        hipLaunchKernelGGL((k_lj_force<T, true, WE, true>), dim3(nb), dim3(kBlock), sm, s, ua.src.pos, ctx->nbr, tl,
+                           ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->ctrl, ctx->trace, ua);
+      } else {
+        hipLaunchKernelGGL((k_gupta_density<T, true, true>), dim3(nb), dim3(kBlock), sm, s, ua.src.pos, ctx->nbr,
+                           tl, ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
+        hipLaunchKernelGGL((k_gupta_force<T, true, WE>), dim3(nb), dim3(kBlock), smw, s, d.pos, ctx->nbr, tl,
+                           ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace);
+      }
+      return;
+    }
+  }
   if (P.kind == FIRE_POT_LJ) {
     hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt,
-                       n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
+                       n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua);
   } else {
     hipLaunchKernelGGL((k_gupta_density<T, LDS>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl,
-                       ctx->wcnt, n, kc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl);
+                       ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
     hipLaunchKernelGGL((k_gupta_force<T, LDS, WE>), dim3(nb), dim3(kBlock), smw, s, ctx->pos, ctx->nbr, tl,
                        ctx->wcnt, n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl,
                        ctx->trace);
@@ -1875,13 +2120,13 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s) {
 }
 
 template <bool WE>
-void launch_pairs(fire_ctx* ctx, hipStream_t s, int prec) {
+void launch_pairs(fire_ctx* ctx, hipStream_t s, int prec, int parity) {
   if (ctx->use_lds) {
-    if (prec) launch_pair_passes<float, true, WE>(ctx, s);
-    else launch_pair_passes<double, true, WE>(ctx, s);
+    if (prec) launch_pair_passes<float, true, WE>(ctx, s, parity);
+    else launch_pair_passes<double, true, WE>(ctx, s, parity);
   } else {
-    if (prec) launch_pair_passes<float, false, WE>(ctx, s);
-    else launch_pair_passes<double, false, WE>(ctx, s);
+    if (prec) launch_pair_passes<float, false, WE>(ctx, s, -1);
+    else launch_pair_passes<double, false, WE>(ctx, s, -1);
   }
 }
 
@@ -1894,8 +2139,25 @@ void launch_forces(fire_ctx* ctx, hipStream_t s, int prec, bool with_e = true) {
                        ctx->pot, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
     return;
   }
-  if (with_e) launch_pairs<true>(ctx, s, prec);
-  else launch_pairs<false>(ctx, s, prec);
+  if (with_e) launch_pairs<true>(ctx, s, prec, -1);
+  else launch_pairs<false>(ctx, s, prec, -1);
+}
+
+// Whether the loop folds the update into the next pass: LDS-staged passes,
+// pair potentials, and no velocity-Verlet half kick in the force epilogue
+// (that kick would have to be undone when a rebuild discards the pass).
+bool fold_update(const fire_ctx* ctx) {
+  return ctx->use_lds && ctx->pot.kind != FIRE_POT_HARMONIC && ctx->params.integrator != FIRE_INT_VERLET;
+}
+
+// Primary state set current and its periodic images consistent (see
+// k_state_home); no host synchronisation.
+void materialize(fire_ctx* ctx, hipStream_t s) {
+  const int n = ctx->n;
+  hipLaunchKernelGGL(k_state_home, dim3(nblocks(n)), dim3(kBlock), 0, s, n, ctx->ncap, ctx->pos2, ctx->vel2,
+                     ctx->frc2, ctx->pos, ctx->vel, ctx->frc, ctx->ctrl);
+  hipLaunchKernelGGL(k_ghost_refresh, dim3(nblocks(std::max(ctx->ng, 1))), dim3(kBlock), 0, s, n, ctx->ng, ctx->pos,
+                     ctx->real_of, ctx->gcode, ctx->box, ctx->ctrl);
 }
 
 void launch_update(fire_ctx* ctx, hipStream_t s) {
@@ -1904,7 +2166,13 @@ void launch_update(fire_ctx* ctx, hipStream_t s) {
 }
 
 // One FIRE iteration; energies only when a trace is recorded.
-void launch_iteration(fire_ctx* ctx, hipStream_t s, int prec) {
+// parity: the state set the iteration starts from (iterations alternate).
+void launch_iteration(fire_ctx* ctx, hipStream_t s, int prec, int parity) {
+  if (fold_update(ctx)) {
+    if (ctx->trace) launch_pairs<true>(ctx, s, prec, parity);
+    else launch_pairs<false>(ctx, s, prec, parity);
+    return;
+  }
   launch_update(ctx, s);
   launch_forces(ctx, s, prec, ctx->trace != nullptr);
 }
@@ -1919,7 +2187,7 @@ int graph_for(fire_ctx* ctx, int prec, hipGraphExec_t* out) {
   ctx->gexec[prec] = nullptr;
   hipGraph_t g;
   HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
-  for (int k = 0; k < ctx->graph_k; ++k) launch_iteration(ctx, ctx->cap_stream, prec);
+  for (int k = 0; k < ctx->graph_k; ++k) launch_iteration(ctx, ctx->cap_stream, prec, k & 1);  // graph_k is even
   HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
   if (getenv("FIRE_DEBUG")) {  // dynamic LDS of the captured kernel nodes
     size_t nn = 0;
@@ -2094,6 +2362,7 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
       if (st[8 * cur] != ST_RUNNING) break;
       cur ^= 1;
     }
+    materialize(ctx, s);
     HIPCHK(hipStreamSynchronize(s));
     const int status = st[8 * (cur ^ 1)];
     const int pause = st[8 * (cur ^ 1) + 1];
@@ -2372,6 +2641,7 @@ int fire_set_params(fire_ctx* ctx, const fire_params* p) {
   if (!ctx || !p) return FIRE_E_ARG;
   if (validate_params(p)) return set_err(ctx, FIRE_E_ARG, "invalid FIRE parameters");
   ctx->params = *p;
+  drop_graphs(ctx);  // the captured loop depends on the integrator
   return FIRE_OK;
 }
 
@@ -2632,7 +2902,16 @@ int fire_repeat_forces_dev(fire_ctx* ctx, int reps, void* stream) {
   HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   const int prec = ctx->params.precision == FIRE_FP64 ? 0 : 1;
-  for (int r = 0; r < reps; ++r) launch_forces(ctx, s, prec, false);
+  if (fold_update(ctx)) {
+    // the loop's pass: the (here zero) pending update applied while staging,
+    // from the primary set into the second one, which is scratch outside the
+    // loop; every repeat reads the same primary set
+    for (int r = 0; r < reps; ++r) launch_pairs<false>(ctx, s, prec, 0);
+    hipLaunchKernelGGL(k_ghost_refresh, dim3(1), dim3(kBlock), 0, s, ctx->n, 0, ctx->pos, ctx->real_of, ctx->gcode,
+                       ctx->box, ctx->ctrl);  // ng = 0: only resets ctrl->cur
+  } else {
+    for (int r = 0; r < reps; ++r) launch_forces(ctx, s, prec, false);
+  }
   return FIRE_OK;
 }
 

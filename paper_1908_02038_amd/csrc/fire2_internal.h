@@ -59,7 +59,8 @@ struct Ctrl {
   // FIRE state
   double dt, alpha;
   long long npos, nneg;
-  int branch, neg, mix_first, pad1;
+  int branch, neg, mix_first;
+  int cur;             // which state buffer holds the current positions (0: the primary set)
   double P_used;
   // coefficients of the next update
   double hsb, kick1, kick2, kick3, cv, cf, dtx;
