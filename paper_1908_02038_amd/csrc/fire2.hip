@@ -896,23 +896,29 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
     r[4] = f2;
     r[5] = v2;
   }
+  // every memory operation of this thread (the skin flag's atomic among them)
+  // has completed before the block's ticket is taken
+  __builtin_amdgcn_s_waitcnt(0);
   block_reduce<4, 2>(r);
   __shared__ int is_last;
   if (threadIdx.x == 0) {
+    // The partial record is the only data the last block reads: it is stored
+    // with device-coherent atomic stores, which complete (the wait) before the
+    // ticket is incremented; the last block reads the records, and the skin
+    // flag, with device-coherent loads.  No cache-wide fence is needed, which
+    // matters: such a fence writes back and invalidates the XCD's whole L2
+    // under every other block still running there.  Later kernels see the
+    // rest of this pass's output through the kernel boundary.
     double* o = part + (size_t)kRed * rec;
-    o[R_E] = r[0] + (part_emb ? part_emb[rec] : 0.0);
-    o[R_P] = r[1];
-    o[R_F2] = r[2];
-    o[R_V2] = r[3];
-    o[R_FMAX2] = r[4];
-    o[R_VMAX2] = r[5];
-    __threadfence();
-    const unsigned int t = atomicAdd(&ctrl->ticket, 1u);
+    const double vals[6] = {r[0] + (part_emb ? part_emb[rec] : 0.0), r[1], r[2], r[3], r[4], r[5]};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) __hip_atomic_store(o + k, vals[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    const unsigned int t = __hip_atomic_fetch_add(&ctrl->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (t == gridDim.x - 1);
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   double q[6] = {0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
     const double* o = part + (size_t)kRed * b;
