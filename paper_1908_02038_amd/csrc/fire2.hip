@@ -510,15 +510,25 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
     }
     for (int q = 0; q < nc; ++q) {
       const int cell = cells[q];
-      for (int j = start[cell], e = start[cell + 1]; j < e; ++j) {
-        if (j == i) continue;
-        const double4 pj = pos[j];
-        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 == 0.0) overlap = true;
-        if (r2 < rcs2) {
-          if (cnt < kcap) nbr[lidx(w, cnt, lane, kcap)] = j;
-          ++cnt;
+      // candidates in groups of 8: all loads issued before the tests, so
+      // their latencies overlap; entries are appended in slot order
+      constexpr int kG = 8;
+      for (int j0 = start[cell], e = start[cell + 1]; j0 < e; j0 += kG) {
+        double4 pj[kG];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) pj[u] = pos[min(j0 + u, e - 1)];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) {
+          const int j = j0 + u;
+          if (j >= e) break;
+          if (j == i) continue;
+          const double dx = pi.x - pj[u].x, dy = pi.y - pj[u].y, dz = pi.z - pj[u].z;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) overlap = true;
+          if (r2 < rcs2) {
+            if (cnt < kcap) nbr[lidx(w, cnt, lane, kcap)] = j;
+            ++cnt;
+          }
         }
       }
     }
