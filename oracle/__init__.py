@@ -97,6 +97,8 @@ def _load():
         lib.oracle_hvp.argtypes = [ctypes.c_long, dp, dp, P(_Box), P(_Pot), dp]
         lib.oracle_fire_minimize.argtypes = [ctypes.c_long, dp, P(_Box), P(_Pot), P(_Fire), ctypes.c_double,
                                              ctypes.c_long, P(_Result), dp, dp]
+        lib.oracle_fire_minimize_ex.argtypes = [ctypes.c_long, dp, P(_Box), P(_Pot), P(_Fire), ctypes.c_void_p, dp,
+                                                ctypes.c_double, ctypes.c_long, P(_Result), dp, dp]
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -207,9 +209,11 @@ def hvp(pos, u, box, pot):
 
 
 def fire_minimize(pos, box, pot, fire: dict, tol: float, max_steps: int, trace: bool = False,
-                  want_velocity: bool = False):
+                  want_velocity: bool = False, frozen=None, mass=None):
     """Run FIRE; returns dict(pos, stop, iterations, force_evals, energy, fmax,
-    f2norm, dt, alpha, n_pos, n_neg[, trace][, velocity])."""
+    f2norm, dt, alpha, n_pos, n_neg[, trace][, velocity]).  frozen: optional
+    uint8 per atom (bit d freezes component d); mass: optional per-atom mass
+    relative to the mass f2a implies."""
     lib = _load()
     pos = np.array(pos, dtype=np.float64, copy=True, order="C")
     n = pos.shape[0]
@@ -217,8 +221,15 @@ def fire_minimize(pos, box, pot, fire: dict, tol: float, max_steps: int, trace: 
     tr = np.zeros((max_steps + 1, len(TRACE_COLS))) if trace else None
     vel = np.zeros_like(pos) if want_velocity else None
     b, p, f = _box(box), _pot(pot), _fire(fire)
-    _check(lib.oracle_fire_minimize(n, _ptr(pos), ctypes.byref(b), ctypes.byref(p), ctypes.byref(f),
-                                    float(tol), int(max_steps), ctypes.byref(res), _ptr(tr), _ptr(vel)))
+    fz = None if frozen is None else np.ascontiguousarray(frozen, dtype=np.uint8)
+    ms = None if mass is None else np.ascontiguousarray(mass, dtype=np.float64)
+    if fz is not None:
+        assert fz.shape == (n,)
+    if ms is not None:
+        assert ms.shape == (n,)
+    _check(lib.oracle_fire_minimize_ex(n, _ptr(pos), ctypes.byref(b), ctypes.byref(p), ctypes.byref(f),
+                                       None if fz is None else fz.ctypes.data_as(ctypes.c_void_p), _ptr(ms),
+                                       float(tol), int(max_steps), ctypes.byref(res), _ptr(tr), _ptr(vel)))
     out = {
         "pos": pos,
         "stop": STOP_NAMES.get(res.stop, str(res.stop)),

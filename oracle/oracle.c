@@ -488,6 +488,23 @@ static void mix(long n, double *v, const double *f, double alpha) {
   for (long i = 0; i < 3 * n; ++i) v[i] = (1.0 - alpha) * v[i] + alpha * vn * f[i] / fn;
 }
 
+/* Frozen degrees of freedom (bit d of frozen[i] set: component d of atom i)
+ * have their force held at zero, so FIRE never moves them (the frozen borders
+ * of the test cases in Sec. 5.3). */
+static void apply_frozen(long n, double *f, const unsigned char *frozen) {
+  if (!frozen) return;
+  for (long i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d)
+      if (frozen[i] & (1 << d)) f[3 * i + d] = 0.0;
+}
+
+/* The kick of one component: v += (c s_i) F with c the step's kick factor
+ * (dt f2a, or half of it) and s_i = 1 / m_i the atom's inverse mass relative
+ * to the mass f2a implies (1 without a mass array). */
+static void kick(long n, double *v, const double *f, double c, const double *inv_mass) {
+  for (long k = 0; k < 3 * n; ++k) v[k] += (inv_mass ? c * inv_mass[k / 3] : c) * f[k];
+}
+
 /*
  * Minimise E from pos (in/out).  tol applies to the chosen criterion with a
  * strict "<".  trace (nullable) receives one row per iteration i = 0..it:
@@ -495,10 +512,22 @@ static void mix(long n, double *v, const double *f, double alpha) {
  * where E, fmax, f2norm are those after the force evaluation of row i, and P,
  * dt, alpha, branch are those that led to it.  vel_out (nullable): final v.
  */
-int oracle_fire_minimize(long n, double *pos, const or_box *b, const or_pot *p, const or_fire *fp, double tol,
-                         long max_steps, or_result *res, double *trace, double *vel_out) {
+int oracle_fire_minimize_ex(long n, double *pos, const or_box *b, const or_pot *p, const or_fire *fp,
+                            const unsigned char *frozen, const double *mass, double tol, long max_steps,
+                            or_result *res, double *trace, double *vel_out) {
   int rc = check_inputs(n, pos, b, p);
   if (rc) return rc;
+  double *inv_mass = NULL;
+  if (mass) {
+    inv_mass = (double *)malloc(sizeof(double) * n);
+    for (long i = 0; i < n; ++i) {
+      if (!(mass[i] > 0.0) || !isfinite(mass[i])) {
+        free(inv_mass);
+        return OR_E_ARG;
+      }
+      inv_mass[i] = 1.0 / mass[i];
+    }
+  }
   double *v = (double *)calloc((size_t)(3 * n), sizeof(double));
   double *f = (double *)malloc(sizeof(double) * 3 * n);
   double *fnew = (double *)malloc(sizeof(double) * 3 * n);
@@ -512,6 +541,7 @@ int oracle_fire_minimize(long n, double *pos, const or_box *b, const or_pot *p, 
   rc = oracle_energy_forces(n, pos, b, p, &E, f, NULL, NULL);
   evals++;
   if (rc) goto done;
+  apply_frozen(n, f, frozen);
 
 #define CRIT() (fp->criterion == 0 ? max_atom_norm(n, f) : sqrt(dot3n(n, f, f)))
   if (trace) {
@@ -573,24 +603,27 @@ int oracle_fire_minimize(long n, double *pos, const or_box *b, const or_pot *p, 
     int mixing = (fp->variant == 0);
     if (fp->integrator == 0) {
       /* Algorithm 4: kick, mix, drift */
-      for (long k = 0; k < 3 * n; ++k) v[k] += dtf * f[k];
+      kick(n, v, f, dtf, inv_mass);
       if (mixing) mix(n, v, f, alpha);
       for (long k = 0; k < 3 * n; ++k) pos[k] += dt * v[k];
       rc = oracle_energy_forces(n, pos, b, p, &E, f, NULL, NULL);
+      apply_frozen(n, f, frozen);
     } else if (fp->integrator == 1) {
       /* Algorithm 3: mix, drift with the old v, kick with the old force */
       if (mixing) mix(n, v, f, alpha);
       for (long k = 0; k < 3 * n; ++k) pos[k] += dt * v[k];
-      for (long k = 0; k < 3 * n; ++k) v[k] += dtf * f[k];
+      kick(n, v, f, dtf, inv_mass);
       rc = oracle_energy_forces(n, pos, b, p, &E, f, NULL, NULL);
+      apply_frozen(n, f, frozen);
     } else {
       /* Algorithm 6: half kick, mix, drift, force, half kick */
-      for (long k = 0; k < 3 * n; ++k) v[k] += 0.5 * dtf * f[k];
+      kick(n, v, f, 0.5 * dtf, inv_mass);
       if (mixing) mix(n, v, f, alpha);
       for (long k = 0; k < 3 * n; ++k) pos[k] += dt * v[k];
       rc = oracle_energy_forces(n, pos, b, p, &E, fnew, NULL, NULL);
       memcpy(f, fnew, sizeof(double) * 3 * n);
-      for (long k = 0; k < 3 * n; ++k) v[k] += 0.5 * dtf * f[k];
+      apply_frozen(n, f, frozen);
+      kick(n, v, f, 0.5 * dtf, inv_mass);
     }
     evals++;
     it = i;
@@ -619,5 +652,11 @@ done:
   free(v);
   free(f);
   free(fnew);
+  free(inv_mass);
   return rc;
+}
+
+int oracle_fire_minimize(long n, double *pos, const or_box *b, const or_pot *p, const or_fire *fp, double tol,
+                         long max_steps, or_result *res, double *trace, double *vel_out) {
+  return oracle_fire_minimize_ex(n, pos, b, p, fp, NULL, NULL, tol, max_steps, res, trace, vel_out);
 }

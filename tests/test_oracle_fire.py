@@ -188,3 +188,63 @@ def test_lj_small_relaxes_below_tolerance():
     e1, f1 = oracle.energy_forces(r["pos"], s.box, s.potential)
     assert e1 == r["energy"]
     assert np.abs(f1.sum(0)).max() < 1e-12
+
+
+# ---- frozen degrees of freedom and per-atom masses (the frozen borders and
+# the multi-species systems of the test cases, Sec. 5.3)
+
+def test_unit_masses_and_no_frozen_bits_reproduce_the_plain_run():
+    s = inputs.lj_box(3, nvac=1, noise=0.08, seed=61, rc=2.0)
+    a = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 0.0, 40)
+    b = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 0.0, 40,
+                             frozen=np.zeros(len(s.pos), np.uint8), mass=np.ones(len(s.pos)))
+    assert np.array_equal(a["pos"], b["pos"]) and a["energy"] == b["energy"]
+
+
+def test_mass_scales_the_first_kick():
+    # 1-D well, one atom of mass m: the first iteration is a plain kick and
+    # drift (P = 0, v = 0; mixing is the identity in 1-D), x1 = x0 (1 - k dt^2 / m)
+    k, dt, m, x0 = 2.0, 0.1, 3.5, 0.7
+    pos = np.array([[x0, 0.0, 0.0]])
+    r = oracle.fire_minimize(pos, OPEN, well((k, 0.0, 0.0)), params(), 0.0, 1, mass=np.array([m]))
+    assert r["pos"][0, 0] == pytest.approx(x0 * (1.0 - k * dt * dt / m), rel=1e-15)
+
+
+def test_rescaling_masses_and_time_step_together_leaves_the_trajectory():
+    # Positions evolve through dt^2 / m (kick times drift) and the FIRE state
+    # through dt ratios only: masses x c with dt0 x sqrt(c) is the same run
+    s = inputs.lj_box(3, nvac=1, noise=0.08, seed=62, rc=2.0)
+    m = np.random.default_rng(5).uniform(0.5, 3.0, len(s.pos))
+    c = 4.0
+    a = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 0.0, 60, mass=m)
+    b = oracle.fire_minimize(s.pos, s.box, s.potential, dict(s.fire, dt_start=s.fire["dt_start"] * math.sqrt(c)),
+                             0.0, 60, mass=c * m)
+    assert np.abs(a["pos"] - b["pos"]).max() <= 1e-11
+
+
+def test_frozen_atom_stays_and_its_partner_relaxes_to_the_lj_minimum():
+    box = inputs.Box((-50, -50, -50), (100, 100, 100), (0, 0, 0))
+    pos = np.array([[0.0, 0.0, 0.0], [1.3, 0.2, -0.1]])
+    pot = inputs.lj_potential(rc=2.5)
+    r = oracle.fire_minimize(pos, box, pot, inputs.workload_fire(0.005, 1.0), 1e-10, 100000,
+                             frozen=np.array([7, 0], np.uint8))
+    assert r["stop"] == "converged"
+    assert np.array_equal(r["pos"][0], pos[0])
+    assert np.linalg.norm(r["pos"][1] - r["pos"][0]) == pytest.approx(2.0 ** (1.0 / 6.0), rel=1e-9)
+
+
+def test_frozen_components_never_move_and_the_rest_relaxes():
+    s = inputs.lj_box(3, nvac=1, noise=0.08, seed=63, rc=2.0)
+    n = len(s.pos)
+    frozen = np.zeros(n, np.uint8)
+    frozen[::5] = 1      # x of every 5th atom
+    frozen[1::7] = 6     # y and z of every 7th
+    r = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 1e-7, 100000, frozen=frozen)
+    assert r["stop"] == "converged"
+    moved = r["pos"] != s.pos
+    for d in range(3):
+        assert not moved[(frozen & (1 << d)) > 0, d].any()
+    assert moved[frozen == 0].any()
+    _, f = oracle.energy_forces(r["pos"], s.box, s.potential)
+    f[(frozen[:, None] & (1 << np.arange(3))[None, :]) > 0] = 0.0
+    assert np.linalg.norm(f, axis=1).max() < 1e-7
