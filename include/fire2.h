@@ -144,6 +144,24 @@ typedef struct {
   double alpha;
 } fire_result;
 
+/* Per-atom properties of a minimisation, in the caller's atom order (n
+ * entries each); either pointer may be NULL.
+ *   frozen: bit d (d = 0, 1, 2) of frozen[i] holds component d of atom i
+ *           fixed.  Its force component is set to zero after every force
+ *           evaluation, so its velocity and coordinate never change, and it
+ *           counts as zero in P, |F|, max|F_i| and the stop test (the frozen
+ *           borders of the test cases in Sec. 5.3).  Other bits are ignored.
+ *   mass:   mass[i] > 0 and finite, relative to the mass that f2a implies:
+ *           atom i is kicked with dt f2a / mass[i] instead of dt f2a (the
+ *           m in the update steps of Algorithms 3, 4 and 6).  The mixing of
+ *           Algorithm 2 uses the 3N-vector norms |v| and |F| as without
+ *           masses.
+ * Both arrays are read during the call only. */
+typedef struct {
+  const unsigned char* frozen;
+  const double* mass;
+} fire_atoms;
+
 /* Fill p with the Table 1 defaults (eulerimplicit, tmax 10, tmin 0.02,
  * delaystep 20, dtgrow 1.1, dtshrink 0.5, alpha0 0.25, alphashrink 0.99,
  * vdfmax 2000, halfstepback yes, initialdelay yes), dt_start = f2a = 1,
@@ -178,6 +196,12 @@ int fire_minimize_traced(fire_ctx* ctx, long long n, double* pos, const fire_box
                          const fire_potential* pot, double tol, long long max_steps, fire_result* out,
                          double* trace);
 
+/* fire_minimize with per-atom properties (atoms may be NULL: then exactly
+ * fire_minimize).  trace (NULL: none) is as for fire_minimize_traced and then
+ * requires out.  FIRE_E_ARG if a mass is not positive and finite. */
+int fire_minimize_ex(fire_ctx* ctx, long long n, double* pos, const fire_box* box, const fire_potential* pot,
+                     const fire_atoms* atoms, double tol, long long max_steps, fire_result* out, double* trace);
+
 /* Hessian-vector product hu = (d^2 E / dx dx) u at pos, FP64 (u, hu: [n][3]). */
 int fire_hvp(fire_ctx* ctx, long long n, const double* pos, const double* u, const fire_box* box,
              const fire_potential* pot, double* hu);
@@ -207,6 +231,11 @@ int fire_hvp_dev(fire_ctx* ctx, long long n, const double* d_pos, const double* 
 int fire_minimize_dev(fire_ctx* ctx, long long n, double* d_pos, const fire_box* box,
                       const fire_potential* pot, double tol, long long max_steps, fire_result* out,
                       void* stream);
+/* fire_minimize_ex on device positions; d_atoms is a host record whose
+ * frozen and mass arrays are device pointers (n entries each). */
+int fire_minimize_ex_dev(fire_ctx* ctx, long long n, double* d_pos, const fire_box* box,
+                         const fire_potential* pot, const fire_atoms* d_atoms, double tol, long long max_steps,
+                         fire_result* out, void* stream);
 /* fire_minimize_batched on device positions d_pos ([offsets[nsys]][3], in
  * place); offsets, boxes, per_sys and out stay in host memory.  Returns when
  * every system has stopped.  A non-finite position is not screened on the

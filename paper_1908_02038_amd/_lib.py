@@ -28,7 +28,8 @@ EXPORTS = [
     "fire_params_default", "fire_init", "fire_finalize", "fire_set_params", "fire_get_params",
     "fire_last_error", "fire_stop_name", "fire_energy_forces", "fire_minimize", "fire_minimize_traced",
     "fire_hvp", "fire_lowest_curvature", "fire_minimize_batched", "fire_energy_forces_dev", "fire_hvp_dev",
-    "fire_minimize_dev", "fire_minimize_batched_dev", "fire_repeat_forces_dev",
+    "fire_minimize_dev", "fire_minimize_batched_dev", "fire_repeat_forces_dev", "fire_minimize_ex",
+    "fire_minimize_ex_dev",
 ]
 
 
@@ -66,6 +67,10 @@ class fire_result(ctypes.Structure):
         ("energy", ctypes.c_double), ("energy_per_atom", ctypes.c_double), ("fmax", ctypes.c_double),
         ("f2norm", ctypes.c_double), ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
     ]
+
+
+class fire_atoms(ctypes.Structure):
+    _fields_ = [("frozen", ctypes.c_void_p), ("mass", ctypes.c_void_p)]
 
 
 class FireError(RuntimeError):
@@ -126,5 +131,9 @@ def load(path: str = LIB_PATH):
                                               P(fire_potential), P(fire_params), ctypes.c_double, ll,
                                               P(fire_result), ctypes.c_void_p]
     lib.fire_repeat_forces_dev.argtypes = [ctx_p, ctypes.c_int, ctypes.c_void_p]
+    lib.fire_minimize_ex.argtypes = [ctx_p, ll, dp, P(fire_box), P(fire_potential), P(fire_atoms),
+                                     ctypes.c_double, ll, P(fire_result), dp]
+    lib.fire_minimize_ex_dev.argtypes = [ctx_p, ll, ctypes.c_void_p, P(fire_box), P(fire_potential),
+                                         P(fire_atoms), ctypes.c_double, ll, P(fire_result), ctypes.c_void_p]
     _lib = lib
     return lib

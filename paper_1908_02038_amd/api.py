@@ -148,12 +148,26 @@ class Context:
                                                 ctypes.byref(e), _dp(f) if f is not None else None))
         return (e.value, f) if want_forces else e.value
 
-    def fire_minimize(self, pos, box, pot, tol: float, max_steps: int, trace: bool = False):
+    def fire_minimize(self, pos, box, pot, tol: float, max_steps: int, trace: bool = False,
+                      frozen=None, mass=None):
+        """frozen: optional uint8 per atom (bit d holds component d fixed);
+        mass: optional per-atom mass relative to the one f2a implies."""
         x = np.array(pos, dtype=np.float64, copy=True, order="C")
         n = x.shape[0]
         r = L.fire_result()
         b, p = make_box(box), make_potential(pot)
-        if trace:
+        if frozen is not None or mass is not None:
+            fz = None if frozen is None else np.ascontiguousarray(frozen, dtype=np.uint8)
+            ms = None if mass is None else np.ascontiguousarray(mass, dtype=np.float64)
+            for a in (fz, ms):
+                if a is not None and a.shape != (n,):
+                    raise ValueError("frozen and mass need one entry per atom")
+            at = L.fire_atoms(None if fz is None else fz.ctypes.data, None if ms is None else ms.ctypes.data)
+            tr = np.zeros((max_steps + 1, L.TRACE_COLS)) if trace else None
+            self._check(self.lib.fire_minimize_ex(self.handle, n, _dp(x), ctypes.byref(b), ctypes.byref(p),
+                                                  ctypes.byref(at), float(tol), int(max_steps), ctypes.byref(r),
+                                                  _dp(tr) if trace else None))
+        elif trace:
             tr = np.zeros((max_steps + 1, L.TRACE_COLS))
             self._check(self.lib.fire_minimize_traced(self.handle, n, _dp(x), ctypes.byref(b), ctypes.byref(p),
                                                       float(tol), int(max_steps), ctypes.byref(r), _dp(tr)))
@@ -262,12 +276,24 @@ class Context:
                                           ctypes.c_void_p(hu.data_ptr()), self._stream()))
         return hu
 
-    def fire_minimize_dev(self, pos, box, pot, tol: float, max_steps: int):
-        """Minimise in place on the device tensor pos (n,3) float64."""
+    def fire_minimize_dev(self, pos, box, pot, tol: float, max_steps: int, frozen=None, mass=None):
+        """Minimise in place on the device tensor pos (n,3) float64; frozen
+        (uint8) and mass (float64), if given, are device tensors of n entries."""
         import torch
         assert pos.is_cuda and pos.dtype == torch.float64 and pos.is_contiguous()
         r = L.fire_result()
         b, p = make_box(box), make_potential(pot)
+        if frozen is not None or mass is not None:
+            n = pos.shape[0]
+            for a, dt in ((frozen, torch.uint8), (mass, torch.float64)):
+                if a is not None:
+                    assert a.is_cuda and a.dtype == dt and a.is_contiguous() and a.shape == (n,)
+            at = L.fire_atoms(None if frozen is None else frozen.data_ptr(),
+                              None if mass is None else mass.data_ptr())
+            self._check(self.lib.fire_minimize_ex_dev(self.handle, n, ctypes.c_void_p(pos.data_ptr()),
+                                                      ctypes.byref(b), ctypes.byref(p), ctypes.byref(at),
+                                                      float(tol), int(max_steps), ctypes.byref(r), self._stream()))
+            return _result(r)
         self._check(self.lib.fire_minimize_dev(self.handle, pos.shape[0], ctypes.c_void_p(pos.data_ptr()),
                                                ctypes.byref(b), ctypes.byref(p), float(tol), int(max_steps),
                                                ctypes.byref(r), self._stream()))

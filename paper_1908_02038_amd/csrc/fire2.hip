@@ -91,6 +91,33 @@ __global__ void k_stage_in(const double* __restrict__ src, int n, int ncap, doub
   id[i] = i;
 }
 
+// Caller-order masses and freeze bits (either may be NULL) -> 1/m and 3-bit
+// masks in caller order; a mass that is not positive and finite sets
+// kBadMass in flags[0].
+constexpr int kBadMass = 16;
+__global__ void k_props_in(const double* __restrict__ mass, const unsigned char* __restrict__ frozen, int n,
+                           double* __restrict__ minv, unsigned char* __restrict__ fm, int* __restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (mass) {
+    const double m = mass[i];
+    if (!(m > 0.0) || !isfinite(m)) atomicOr(flags, kBadMass);
+    minv[i] = 1.0 / m;
+  }
+  if (frozen) fm[i] = frozen[i] & 7;
+}
+
+// The properties in slot order: real slot s holds caller atom id[s].
+__global__ void k_props_gather(int n, const int* __restrict__ id, const double* __restrict__ minv,
+                               const unsigned char* __restrict__ fm, double* __restrict__ sinv,
+                               unsigned char* __restrict__ fmask) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int a = id[s];
+  if (minv) sinv[s] = minv[a];
+  if (fm) fmask[s] = fm[a];
+}
+
 __global__ void k_set_pos(double4* __restrict__ pos, int slot, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) pos[slot] = make_double4(v, v, v, 0.0);
 }
@@ -754,6 +781,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
 // An atom farther than skin/2 from its position at the last list build sets
 // ctrl->viol; the next force pass then hands control to the host for a
 // rebuild.
+// Per-atom properties of a minimisation, in slot order (either may be NULL):
+// sinv = 1 / m_i (mass relative to the one f2a implies) scales the atom's
+// kicks; bit d of fmask holds component d of the atom fixed (its force is
+// zeroed in the force epilogue, so v and x never change there).
+struct Props {
+  const double* sinv;
+  const unsigned char* fmask;
+};
+
 // Coefficients of the pending update, as the control left them.
 struct UpdCoef {
   int neg, mix_first;
@@ -762,11 +798,14 @@ struct UpdCoef {
 __device__ __forceinline__ UpdCoef load_coef(const Ctrl* __restrict__ c) {
   return UpdCoef{c->neg, c->mix_first, c->hsb, c->kick1, c->kick2, c->cv, c->cf, c->dtx};
 }
-// One atom's update (x, v in place) from its force f.  Every caller -- the
+// One atom's update (x, v in place) from its force f; s = 1/m_i scales the
+// kicks (1 without masses: then k1 s = k1 exactly).  Every caller -- the
 // update kernel, and the passes that apply the update while staging their
 // halo -- runs this same arithmetic, so an atom gets the same bits wherever it
 // is updated.
-__device__ __forceinline__ void fire_step(const UpdCoef& u, double (&x)[3], double (&v)[3], const double (&f)[3]) {
+__device__ __forceinline__ void fire_step(const UpdCoef& u, double (&x)[3], double (&v)[3], const double (&f)[3],
+                                          double s) {
+  const double k1 = u.k1 * s, k2 = u.k2 * s;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double vd = v[d], xd = x[d];
@@ -775,10 +814,10 @@ __device__ __forceinline__ void fire_step(const UpdCoef& u, double (&x)[3], doub
       vd = 0.0;
     }
     if (u.mix_first) vd = u.cv * vd + u.cf * f[d];
-    vd = vd + u.k1 * f[d];
+    vd = vd + k1 * f[d];
     if (!u.mix_first) vd = u.cv * vd + u.cf * f[d];
     xd = xd + u.dtx * vd;
-    vd = vd + u.k2 * f[d];
+    vd = vd + k2 * f[d];
     v[d] = vd;
     x[d] = xd;
   }
@@ -788,7 +827,8 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
                                                    const double* __restrict__ frc,
                                                    const double4* __restrict__ xref, const int* __restrict__ gcnt,
                                                    const int* __restrict__ glist, const int* __restrict__ gcode,
-                                                   BoxDev box, int n, int ncap, Ctrl* __restrict__ ctrl) {
+                                                   BoxDev box, int n, int ncap, Ctrl* __restrict__ ctrl,
+                                                   Props pr) {
   // same block -> atoms map as the force passes, so each XCD updates the
   // atoms whose forces it just wrote (they are in its L2)
   const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -800,10 +840,11 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
   const double f[3] = {frc[i], frc[ncap + i], frc[2 * ncap + i]};
   const double4 r = xref[i];
   const int gc = gcnt[i];
+  const double sc = pr.sinv ? pr.sinv[i] : 1.0;
   if (!ctrl_running(ctrl)) return;
   const UpdCoef u = load_coef(ctrl);
   double x[3] = {p.x, p.y, p.z};
-  fire_step(u, x, v, f);
+  fire_step(u, x, v, f, sc);
   pos[i] = make_double4(x[0], x[1], x[2], p.w);
   vel[i] = v[0];
   vel[ncap + i] = v[1];
@@ -874,22 +915,31 @@ __device__ __forceinline__ double ld_cohere(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Force-pass epilogue of one atom: store F, apply the velocity-Verlet second
-// half kick, fold E, P, |F|^2, |v|^2, max |F_i|^2, max |v_i|^2 into the
-// block's reduction record; the last block to finish reduces all records in
-// fixed order (second stage) and runs the FIRE control.
+// Force-pass epilogue of one atom: zero the frozen components, store F,
+// apply the velocity-Verlet second half kick, fold E, P, |F|^2, |v|^2,
+// max |F_i|^2, max |v_i|^2 (and, with masses, sum s v.F and sum s^2 F^2)
+// into the block's reduction record; the last block to finish reduces all
+// records in fixed order (second stage) and runs the FIRE control.
 __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, double fy, double fz, double e,
                                                double* __restrict__ frc, double* __restrict__ vel, int ncap,
                                                double* __restrict__ part, const double* __restrict__ part_emb,
                                                int rec, Ctrl* __restrict__ ctrl, double* __restrict__ trace,
-                                               bool check_viol = false) {
+                                               const Props& pr, bool check_viol = false) {
   double r[6] = {0, 0, 0, 0, 0, 0};
+  double rm[2] = {0, 0};
   if (valid) {
+    if (pr.fmask) {
+      const int m = pr.fmask[i];
+      if (m & 1) fx = 0.0;
+      if (m & 2) fy = 0.0;
+      if (m & 4) fz = 0.0;
+    }
     frc[i] = fx;
     frc[ncap + i] = fy;
     frc[2 * ncap + i] = fz;
     double vx = vel[i], vy = vel[ncap + i], vz = vel[2 * ncap + i];
-    const double kick3 = ctrl->kick3;
+    const double sc = pr.sinv ? pr.sinv[i] : 1.0;
+    const double kick3 = ctrl->kick3 * sc;
     if (kick3 != 0.0) {
       vx += kick3 * fx;
       vy += kick3 * fy;
@@ -905,11 +955,14 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
     r[3] = v2;
     r[4] = f2;
     r[5] = v2;
+    rm[0] = sc * r[1];
+    rm[1] = (sc * sc) * f2;
   }
   // every memory operation of this thread (the skin flag's atomic among them)
   // has completed before the block's ticket is taken
   __builtin_amdgcn_s_waitcnt(0);
   block_reduce<4, 2>(r);
+  if (pr.sinv) block_reduce<2, 0>(rm);  // uniform over the block
   __shared__ int is_last;
   if (threadIdx.x == 0) {
     // The partial record is the only data the last block reads: it is stored
@@ -920,9 +973,9 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
     // under every other block still running there.  Later kernels see the
     // rest of this pass's output through the kernel boundary.
     double* o = part + (size_t)kRed * rec;
-    const double vals[6] = {r[0] + (part_emb ? part_emb[rec] : 0.0), r[1], r[2], r[3], r[4], r[5]};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) __hip_atomic_store(o + k, vals[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double vals[kCtl] = {r[0] + (part_emb ? part_emb[rec] : 0.0), r[1], r[2], r[3], r[4], r[5], rm[0], rm[1]};
+    const int nv = pr.sinv ? kCtl : 6;
+    for (int k = 0; k < nv; ++k) __hip_atomic_store(o + k, vals[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_s_waitcnt(0);
     const unsigned int t = __hip_atomic_fetch_add(&ctrl->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (t == gridDim.x - 1);
@@ -940,7 +993,18 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
     q[5] = fmax(q[5], ld_cohere(o + R_VMAX2));
   }
   block_reduce<4, 2>(q);
+  // without masses the mass-weighted sums are P and |F|^2 exactly
+  double qm[2] = {q[R_P], q[R_F2]};
+  if (pr.sinv) {
+    qm[0] = qm[1] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+      qm[0] += ld_cohere(part + (size_t)kRed * b + R_SVF);
+      qm[1] += ld_cohere(part + (size_t)kRed * b + R_SFF);
+    }
+    block_reduce<2, 0>(qm);
+  }
   if (threadIdx.x == 0) {
+    const double qc[kCtl] = {q[0], q[1], q[2], q[3], q[4], q[5], qm[0], qm[1]};
     ctrl->ticket = 0;
     if (check_viol && __hip_atomic_load(&ctrl->viol, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       // the update applied in this pass moved an atom past its skin: these
@@ -948,7 +1012,7 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
       ctrl->pause |= PAUSE_REBUILD;
       __hip_atomic_store(&ctrl->status, ST_PAUSED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      fire_control(ctrl, q, trace);
+      fire_control(ctrl, qc, trace);
     }
   }
 }
@@ -1097,6 +1161,7 @@ struct UpdArgs {
   const int* gcnt;                // images per real atom
   const int* glist;               // their slots
   const double4* xref;            // positions at the last list build
+  const double* sinv;             // 1 / m per real slot, or NULL
   BoxDev box;
 };
 
@@ -1119,7 +1184,7 @@ __device__ __forceinline__ Halo stage_halo_updated(const UpdArgs& ua, const UpdC
       j[e] = q < H ? hs[q] : -1;
       r[e] = q < H ? hr[q] : 0;
     }
-    double x[2][3], v[2][3], f[2][3];
+    double x[2][3], v[2][3], f[2][3], sc[2];
     int code[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -1134,11 +1199,12 @@ __device__ __forceinline__ Halo stage_halo_updated(const UpdArgs& ua, const UpdC
         f[e][d] = ua.src.frc[d * ncap + r[e]];
       }
       code[e] = j[e] >= n ? ua.gcode[j[e] - n] : 0;
+      sc[e] = ua.sinv ? ua.sinv[r[e]] : 1.0;
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       if (j[e] < 0) continue;
-      fire_step(u, x[e], v[e], f[e]);
+      fire_step(u, x[e], v[e], f[e], sc[e]);
       const int q = q0 + e * step;
 #pragma unroll
       for (int d = 0; d < 3; ++d) h[d * S + q] = x[e][d] + ghost_shift(code[e], d, ua.box);
@@ -1161,7 +1227,7 @@ __device__ __forceinline__ double4 own_update(const UpdArgs& ua, const UpdCoef& 
   double x[3] = {p.x, p.y, p.z};
   double v[3] = {ua.src.vel[i], ua.src.vel[ncap + i], ua.src.vel[2 * ncap + i]};
   const double f[3] = {ua.src.frc[i], ua.src.frc[ncap + i], ua.src.frc[2 * ncap + i]};
-  fire_step(u, x, v, f);
+  fire_step(u, x, v, f, ua.sinv ? ua.sinv[i] : 1.0);
   ua.dst.vel[i] = v[0];
   ua.dst.vel[ncap + i] = v[1];
   ua.dst.vel[2 * ncap + i] = v[2];
@@ -1183,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__
                                                      int ncap, PotDev pot, double* __restrict__ frc,
                                                      double* __restrict__ vel, double* __restrict__ part,
                                                      Ctrl* __restrict__ ctrl, double* __restrict__ trace,
-                                                     UpdArgs ua) {
+                                                     UpdArgs ua, Props pr) {
   static_assert(!UPD || LDS, "the update is applied while staging the LDS halo");
   if (!pass_gate<UPD>(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -1226,7 +1292,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__
     if constexpr (WE) ae += in ? (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh) : (T)0;
   });
   force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, nullptr, b, ctrl,
-                 trace, UPD);
+                 trace, pr, UPD);
 }
 
 // Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
@@ -1304,7 +1370,8 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
                                                         int ncap, PotDev pot, double* __restrict__ frc,
                                                         double* __restrict__ vel, double* __restrict__ part,
                                                         const double* __restrict__ part_emb,
-                                                        Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
+                                                        Ctrl* __restrict__ ctrl, double* __restrict__ trace,
+                                                        Props pr) {
   if (!pass_gate(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const Halo halo = LDS ? stage_halo<true>(pos, tl, b) : Halo{nullptr, 0};
@@ -1339,14 +1406,15 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
     if constexpr (WE) ae += in ? epair * ph * S : (T)0;
   });
   force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, part_emb, b, ctrl,
-                 trace);
+                 trace, pr);
 }
 
 // Quadratic test well E = 1/2 sum k_d x_d^2 (no pairs).
 __global__ __launch_bounds__(kBlock) void k_harmonic_force(const double4* __restrict__ pos, int n, int ncap,
                                                            PotDev pot, double* __restrict__ frc,
                                                            double* __restrict__ vel, double* __restrict__ part,
-                                                           Ctrl* __restrict__ ctrl, double* __restrict__ trace) {
+                                                           Ctrl* __restrict__ ctrl, double* __restrict__ trace,
+                                                           Props pr) {
   if (!pass_gate(ctrl)) return;
   const int b = blockIdx.x;
   const int i = b * blockDim.x + threadIdx.x;
@@ -1359,7 +1427,7 @@ __global__ __launch_bounds__(kBlock) void k_harmonic_force(const double4* __rest
     fz = -pot.k[2] * p.z;
     e = 0.5 * (pot.k[0] * p.x * p.x + pot.k[1] * p.y * p.y + pot.k[2] * p.z * p.z);
   }
-  force_epilogue(i, valid, fx, fy, fz, e, frc, vel, ncap, part, nullptr, b, ctrl, trace);
+  force_epilogue(i, valid, fx, fy, fz, e, frc, vel, ncap, part, nullptr, b, ctrl, trace, pr);
 }
 
 // ------------------------------------------------------- Hessian * u (FP64)
@@ -1581,6 +1649,12 @@ struct fire_ctx {
   bool use_lds = false;
   size_t lds_atoms = 0, lds_limit = 0;  // halo capacity per tile block; byte limit per block
   double *part = nullptr, *part_emb = nullptr, *bbox_part = nullptr;
+  // per-atom properties of the running minimisation: 1/m and freeze bits in
+  // caller order (minv_atom, fmask_atom) and in slot order (sinv, fmask),
+  // regathered after every rebuild; used only while with_mass / with_frozen
+  double *minv_atom = nullptr, *sinv = nullptr;
+  unsigned char *fmask_atom = nullptr, *fmask = nullptr;
+  bool with_mass = false, with_frozen = false;
   double* aux = nullptr;  // HVP / Lanczos planes
   int aux_planes = 0;
   Ctrl* ctrl = nullptr;
@@ -1650,6 +1724,10 @@ void free_single(fire_ctx* c) {
   hipFree(c->part); hipFree(c->part_emb); hipFree(c->bbox_part);
   hipFree(c->xref); hipFree(c->wcnt); hipFree(c->tile_h); hipFree(c->hslot); hipFree(c->hsrc); hipFree(c->nbr16);
   hipFree(c->gcount); hipFree(c->goff); hipFree(c->gcnt); hipFree(c->glist); hipFree(c->new_of_old);
+  hipFree(c->minv_atom); hipFree(c->sinv); hipFree(c->fmask_atom); hipFree(c->fmask);
+  c->minv_atom = c->sinv = nullptr;
+  c->fmask_atom = c->fmask = nullptr;
+  c->with_mass = c->with_frozen = false;
   c->vel = c->vel2 = c->frc = c->frc2 = nullptr;
   c->id = c->id2 = nullptr;
   c->stage = c->part = c->part_emb = c->bbox_part = nullptr;
@@ -2011,6 +2089,18 @@ int build_lists(fire_ctx* ctx) {
 // periodic images and build the neighbour list of the current positions;
 // positions on periodic axes are wrapped into the box.  Records the build
 // positions for the skin test.
+Props props_of(const fire_ctx* ctx) {
+  return Props{ctx->with_mass ? ctx->sinv : nullptr, ctx->with_frozen ? ctx->fmask : nullptr};
+}
+
+// Slot-order properties after the atoms were (re)sorted.
+void gather_props(fire_ctx* ctx, hipStream_t s) {
+  if (!ctx->with_mass && !ctx->with_frozen) return;
+  hipLaunchKernelGGL(k_props_gather, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->n, ctx->id,
+                     ctx->with_mass ? ctx->minv_atom : nullptr, ctx->with_frozen ? ctx->fmask_atom : nullptr,
+                     ctx->sinv, ctx->fmask);
+}
+
 int rebuild(fire_ctx* ctx) {
   const int n = ctx->n;
   hipStream_t s = ctx->stream;
@@ -2018,6 +2108,7 @@ int rebuild(fire_ctx* ctx) {
     HIPCHK(hipMemcpyAsync(ctx->xref, ctx->pos, sizeof(double4) * n, hipMemcpyDeviceToDevice, s));
     ctx->ng = 0;
     ctx->have_list = true;
+    gather_props(ctx, s);
     return FIRE_OK;
   }
   const int nb = nblocks(n);
@@ -2076,6 +2167,7 @@ int rebuild(fire_ctx* ctx) {
   rc = build_lists(ctx);
   if (rc) return rc;
   ctx->have_list = true;
+  gather_props(ctx, s);
   return FIRE_OK;
 }
 
@@ -2093,6 +2185,7 @@ UpdArgs upd_args(fire_ctx* ctx, int parity) {
   u.gcnt = ctx->gcnt;
   u.glist = ctx->glist;
   u.xref = ctx->xref;
+  u.sinv = props_of(ctx).sinv;
   u.box = ctx->box;
   return u;
 }
@@ -2108,30 +2201,32 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
   const size_t sm = LDS ? ctx->lds_atoms * 24 : 0;     // x, y, z
   const size_t smw = LDS ? ctx->lds_atoms * 32 : 0;    // x, y, z, F'(rho)
   const UpdArgs ua = upd_args(ctx, parity < 0 ? 0 : parity);
+  const Props pr = props_of(ctx);
   if constexpr (LDS) {
     if (parity >= 0) {
       const StateBuf d = ua.dst;
       if (P.kind == FIRE_POT_LJ) {
         hipLaunchKernelGGL((k_lj_force<T, true, WE, true>), dim3(nb), dim3(kBlock), sm, s, ua.src.pos, ctx->nbr, tl,
-                           ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->ctrl, ctx->trace, ua);
+                           ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
       } else {
         hipLaunchKernelGGL((k_gupta_density<T, true, true>), dim3(nb), dim3(kBlock), sm, s, ua.src.pos, ctx->nbr,
                            tl, ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
         hipLaunchKernelGGL((k_gupta_force<T, true, WE>), dim3(nb), dim3(kBlock), smw, s, d.pos, ctx->nbr, tl,
-                           ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace);
+                           ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace,
+                           pr);
       }
       return;
     }
   }
   if (P.kind == FIRE_POT_LJ) {
     hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt,
-                       n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua);
+                       n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
   } else {
     hipLaunchKernelGGL((k_gupta_density<T, LDS>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl,
                        ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
     hipLaunchKernelGGL((k_gupta_force<T, LDS, WE>), dim3(nb), dim3(kBlock), smw, s, ctx->pos, ctx->nbr, tl,
                        ctx->wcnt, n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl,
-                       ctx->trace);
+                       ctx->trace, pr);
   }
 }
 
@@ -2152,7 +2247,7 @@ void launch_pairs(fire_ctx* ctx, hipStream_t s, int prec, int parity) {
 void launch_forces(fire_ctx* ctx, hipStream_t s, int prec, bool with_e = true) {
   if (ctx->pot.kind == FIRE_POT_HARMONIC) {
     hipLaunchKernelGGL(k_harmonic_force, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->n, ctx->ncap,
-                       ctx->pot, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace);
+                       ctx->pot, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, props_of(ctx));
     return;
   }
   if (with_e) launch_pairs<true>(ctx, s, prec, -1);
@@ -2178,7 +2273,7 @@ void materialize(fire_ctx* ctx, hipStream_t s) {
 
 void launch_update(fire_ctx* ctx, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->vel, ctx->frc, ctx->xref,
-                     ctx->gcnt, ctx->glist, ctx->gcode, ctx->box, ctx->n, ctx->ncap, ctx->ctrl);
+                     ctx->gcnt, ctx->glist, ctx->gcode, ctx->box, ctx->n, ctx->ncap, ctx->ctrl, props_of(ctx));
 }
 
 // One FIRE iteration; energies only when a trace is recorded.
@@ -2194,7 +2289,8 @@ void launch_iteration(fire_ctx* ctx, hipStream_t s, int prec, int parity) {
 }
 
 int graph_for(fire_ctx* ctx, int prec, hipGraphExec_t* out) {
-  const long long key = ctx->layout_version * 1000003LL + (long long)ctx->n * 7 + ctx->graph_k;
+  const long long key = (ctx->layout_version * 1000003LL + (long long)ctx->n * 7 + ctx->graph_k) * 4 +
+                        (ctx->with_mass ? 1 : 0) + (ctx->with_frozen ? 2 : 0);
   if (ctx->gexec[prec] && ctx->graph_key[prec] == key && ctx->trace == nullptr) {
     *out = ctx->gexec[prec];
     return FIRE_OK;
@@ -2252,6 +2348,47 @@ int stage_in(fire_ctx* ctx, long long n, const double* src, bool host, hipStream
     if (rc) return rc;
     if (ctx->h_flags[0] & ERR_NONFINITE) return set_err(ctx, FIRE_E_NONFINITE, "non-finite input position");
   }
+  return FIRE_OK;
+}
+
+// Per-atom masses and freeze bits of a minimisation (after stage_in): into
+// the caller-order device arrays, validated, and switched on for the run.
+// Host arrays are first copied into the slot-order buffers, which the first
+// rebuild overwrites.
+int setup_props(fire_ctx* ctx, const fire_atoms* a, bool host, hipStream_t s) {
+  ctx->with_mass = ctx->with_frozen = false;
+  if (!a || (!a->mass && !a->frozen)) return FIRE_OK;
+  const int n = ctx->n, cap = ctx->ncap;
+  const double* m = a->mass;
+  const unsigned char* fz = a->frozen;
+  if (m && !ctx->sinv) {
+    HIPCHK(dalloc(&ctx->minv_atom, cap));
+    HIPCHK(dalloc(&ctx->sinv, cap));
+  }
+  if (fz && !ctx->fmask) {
+    HIPCHK(dalloc(&ctx->fmask_atom, cap));
+    HIPCHK(dalloc(&ctx->fmask, cap));
+  }
+  if (host) {
+    if (m) {
+      for (int i = 0; i < n; ++i)
+        if (!(m[i] > 0.0) || !std::isfinite(m[i])) return set_err(ctx, FIRE_E_ARG, "masses must be positive and finite");
+      HIPCHK(hipMemcpyAsync(ctx->sinv, m, sizeof(double) * n, hipMemcpyHostToDevice, s));
+      m = ctx->sinv;
+    }
+    if (fz) {
+      HIPCHK(hipMemcpyAsync(ctx->fmask, fz, n, hipMemcpyHostToDevice, s));
+      fz = ctx->fmask;
+    }
+  }
+  HIPCHK(hipMemsetAsync(ctx->flags, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_props_in, dim3(nblocks(n)), dim3(kBlock), 0, s, m, fz, n, ctx->minv_atom, ctx->fmask_atom,
+                     ctx->flags);
+  int rc = read_flags(ctx);
+  if (rc) return rc;
+  if (ctx->h_flags[0] & kBadMass) return set_err(ctx, FIRE_E_ARG, "masses must be positive and finite");
+  ctx->with_mass = m != nullptr;
+  ctx->with_frozen = fz != nullptr;
   return FIRE_OK;
 }
 
@@ -2713,13 +2850,14 @@ int fire_energy_forces_dev(fire_ctx* ctx, long long n, const double* d_pos, cons
 
 static int minimize_common(fire_ctx* ctx, long long n, double* pos, bool host, const fire_box* box,
                            const fire_potential* pot, double tol, long long max_steps, fire_result* out,
-                           double* trace_host, hipStream_t s) {
+                           double* trace_host, hipStream_t s, const fire_atoms* atoms = nullptr) {
   if (!(tol >= 0)) return set_err(ctx, FIRE_E_ARG, "tol must be >= 0");
   int rc = prepare_system(ctx, box, pot);
   if (rc) return rc;
   hipStream_t saved = ctx->stream;
   ctx->stream = s;
   rc = stage_in(ctx, n, pos, host, s);
+  if (!rc) rc = setup_props(ctx, atoms, host, s);
   if (!rc && trace_host) {
     hipFree(ctx->trace);
     ctx->trace = nullptr;
@@ -2751,6 +2889,7 @@ static int minimize_common(fire_ctx* ctx, long long n, double* pos, bool host, c
     ctx->trace_cap = 0;
     drop_graphs(ctx);
   }
+  ctx->with_mass = ctx->with_frozen = false;
   ctx->stream = saved;
   return rc;
 }
@@ -2775,6 +2914,23 @@ int fire_minimize_dev(fire_ctx* ctx, long long n, double* d_pos, const fire_box*
   int rc = check_ctx(ctx);
   if (rc) return rc;
   return minimize_common(ctx, n, d_pos, false, box, pot, tol, max_steps, out, nullptr, pick_stream(ctx, stream));
+}
+
+int fire_minimize_ex(fire_ctx* ctx, long long n, double* pos, const fire_box* box, const fire_potential* pot,
+                     const fire_atoms* atoms, double tol, long long max_steps, fire_result* out, double* trace) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (trace && !out) return set_err(ctx, FIRE_E_ARG, "a trace requires out");
+  return minimize_common(ctx, n, pos, true, box, pot, tol, max_steps, out, trace, ctx->stream, atoms);
+}
+
+int fire_minimize_ex_dev(fire_ctx* ctx, long long n, double* d_pos, const fire_box* box, const fire_potential* pot,
+                         const fire_atoms* d_atoms, double tol, long long max_steps, fire_result* out,
+                         void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  return minimize_common(ctx, n, d_pos, false, box, pot, tol, max_steps, out, nullptr, pick_stream(ctx, stream),
+                         d_atoms);
 }
 
 static int hvp_common(fire_ctx* ctx, long long n, const double* pos, const double* u, bool host, const fire_box* box,

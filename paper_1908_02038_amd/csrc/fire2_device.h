@@ -40,10 +40,11 @@ __device__ __forceinline__ float rsqrt_f(float x) {
 }
 
 // The scalar FIRE logic (one thread) on the reduced E, P, |F|^2, |v|^2,
-// max|F_i|^2, max|v_i|^2 of the force evaluation just finished: stop tests,
-// then the branch of Algorithm 2 (or 1) for the next iteration and the
-// coefficients of the next update.
-__device__ inline void fire_control(Ctrl* __restrict__ c, const double (&r)[6], double* __restrict__ trace) {
+// max|F_i|^2, max|v_i|^2, sum s_i v_i.F_i, sum s_i^2 |F_i|^2 of the force
+// evaluation just finished (the last two equal P and |F|^2 when every
+// s_i = 1/m_i is 1): stop tests, then the branch of Algorithm 2 (or 1) for
+// the next iteration and the coefficients of the next update.
+__device__ inline void fire_control(Ctrl* __restrict__ c, const double (&r)[kCtl], double* __restrict__ trace) {
   const double E = r[0], P = r[1], F2 = r[2], V2 = r[3], fm = sqrt(r[4]), vm = sqrt(r[5]);
   c->energy = E;
   c->P = P;
@@ -123,7 +124,7 @@ __device__ inline void fire_control(Ctrl* __restrict__ c, const double (&r)[6], 
   }
   const double dtf = dt * c->f2a;
   const double fn = sqrt(F2);
-  const double Pe = neg ? 0.0 : P, V2e = neg ? 0.0 : V2;
+  const double V2e = neg ? 0.0 : V2, SvFe = neg ? 0.0 : r[R_SVF], SFF = r[R_SFF];
   double k1, k2, k3, cv, cf;
   int mix_first = 0;
   if (c->integrator == FIRE_INT_EULER_EXPLICIT) {
@@ -140,8 +141,9 @@ __device__ inline void fire_control(Ctrl* __restrict__ c, const double (&r)[6], 
     k3 = 0.0;
   }
   if (c->variant == FIRE_VARIANT_FIRE2) {
-    // |v| of the velocity being mixed, from the reductions: |v + k1 F|^2
-    const double vn = sqrt(fmax(V2e + 2.0 * k1 * Pe + k1 * k1 * F2, 0.0));
+    // |v| of the velocity being mixed, from the reductions: the kick gives
+    // atom i v_i + k1 s_i F_i, so |v|^2 = V2 + 2 k1 sum s v.F + k1^2 sum s^2 F^2
+    const double vn = sqrt(fmax(V2e + 2.0 * k1 * SvFe + k1 * k1 * SFF, 0.0));
     cv = 1.0 - alpha;
     cf = fn > 0.0 ? alpha * vn / fn : 0.0;
   } else {

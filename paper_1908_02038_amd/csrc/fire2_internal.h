@@ -9,8 +9,11 @@ namespace fire {
 
 constexpr int kBlock = 256;   // threads per block of the per-atom kernels
 constexpr int kRed = 8;       // doubles per reduction record
-// reduction record layout (one per block of the force pass)
-enum RedField { R_E = 0, R_P = 1, R_F2 = 2, R_V2 = 3, R_FMAX2 = 4, R_VMAX2 = 5, R_EEMB = 6 };
+// reduction record layout (one per block of the force pass); the last two
+// are the mass-weighted sums sum_i s_i v_i.F_i and sum_i s_i^2 |F_i|^2
+// (s_i = 1 / m_i), kept only when the atoms carry masses
+enum RedField { R_E = 0, R_P = 1, R_F2 = 2, R_V2 = 3, R_FMAX2 = 4, R_VMAX2 = 5, R_SVF = 6, R_SFF = 7 };
+constexpr int kCtl = 8;       // reduced values the control reads (the record's fields)
 
 // ctrl->status: 0 running, 10 paused for the host, FIRE_STOP_* when stopped,
 // negative FIRE_E_* on a device-detected error.

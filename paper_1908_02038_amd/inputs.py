@@ -252,3 +252,26 @@ def random_directions(n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     u = rng.normal(size=(n, 3))
     return u / np.linalg.norm(u)
+
+
+def frozen_border(pos: np.ndarray, box: Box, width: float, top_bits: int = 3) -> np.ndarray:
+    """Per-atom freeze bits (bit d: component d fixed) for a boundary-clamped
+    test case: on every free axis the atoms within `width` of the lowest
+    coordinate are fixed completely (bits 7) and those within `width` of the
+    highest get `top_bits` (default 3: x and y fixed, free to move along the
+    surface normal of a z slab).  Periodic axes get no border."""
+    fz = np.zeros(len(pos), np.uint8)
+    for k in range(3):
+        if box.periodic[k]:
+            continue
+        lo, hi = pos[:, k].min(), pos[:, k].max()
+        fz[pos[:, k] < lo + width] = 7
+        fz[(pos[:, k] > hi - width) & (fz == 0)] |= np.uint8(top_bits)
+    return fz
+
+
+def random_masses(n: int, seed: int, lo: float = 0.5, hi: float = 4.0) -> np.ndarray:
+    """Seeded per-atom masses, log-uniform in [lo, hi] (a multi-species mix
+    relative to the reference mass)."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))

@@ -1,0 +1,189 @@
+"""GPU parity of per-atom masses and frozen degrees of freedom against the
+oracle: the mass in the kicks of Algorithms 3, 4 and 6 and the frozen borders
+of the boundary-clamped test cases (Sec. 5.3), through fire_minimize_ex and
+fire_minimize_ex_dev."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_02038_amd import inputs
+from systems import SMALL, min_image_diff
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {
+    "fire2": {},
+    "ee": {"integrator": "eulerexplicit"},
+    "vv": {"integrator": "verlet"},
+    "fire1": {"variant": "fire1"},
+}
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1908_02038_amd import api as a
+    return a
+
+
+def props(s, seed):
+    """Masses for every atom; on a slab its frozen borders, on a periodic box
+    a scatter of single frozen components (x of every 5th atom, y and z of
+    every 7th)."""
+    n = len(s.pos)
+    mass = inputs.random_masses(n, seed)
+    if all(s.box.periodic):
+        frozen = np.zeros(n, np.uint8)
+        frozen[::5] = 1
+        frozen[1::7] = 6
+    else:
+        frozen = inputs.frozen_border(s.pos, s.box, 2.0)
+    return frozen, mass
+
+
+def frozen_components_unchanged(out, s, frozen):
+    # the inputs are wrapped into boxes with lo = 0, where wrapping a
+    # coordinate that never changed returns the same bits
+    assert all(lo == 0.0 for lo, p in zip(s.box.lo, s.box.periodic) if p)
+    for d in range(3):
+        sel = (frozen & (1 << d)) > 0
+        assert sel.any()
+        np.testing.assert_array_equal(out[sel, d], s.pos[sel, d])
+
+
+@pytest.mark.parametrize("var", list(VARIANTS))
+@pytest.mark.parametrize("name", ["lj_small", "gupta_5", "gupta_slab"])
+def test_props_first_steps_match_oracle(api, var, name):
+    s = SMALL[name]()
+    fire = dict(s.fire, **VARIANTS[var])
+    frozen, mass = props(s, 61)
+    c = api.Context(0, fire)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 20, trace=True, frozen=frozen, mass=mass)
+    c.close()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 0.0, 20, trace=True, frozen=frozen, mass=mass)
+    assert r["iterations"] == ref["iterations"] == 20
+    assert np.abs(min_image_diff(r["pos"], ref["pos"], s.box)).max() <= 1e-12
+    np.testing.assert_array_equal(r["trace"][:, 7], ref["trace"][:, 7])  # branches
+    np.testing.assert_allclose(r["trace"][:, [5, 6]], ref["trace"][:, [5, 6]], rtol=1e-15)  # dt, alpha
+    np.testing.assert_allclose(r["trace"][:, 1], ref["trace"][:, 1], rtol=1e-12)  # E
+    np.testing.assert_allclose(r["trace"][:, [2, 3]], ref["trace"][:, [2, 3]], rtol=1e-9)  # masked norms
+    frozen_components_unchanged(r["pos"], s, frozen)
+
+
+@pytest.mark.parametrize("name", ["lj_small", "gupta_5", "gupta_slab"])
+def test_props_relaxation_matches_oracle(api, name):
+    s = SMALL[name]()
+    frozen, mass = props(s, 62)
+    c = api.Context(0, s.fire)
+    r = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000, trace=True, frozen=frozen, mass=mass)
+    c.close()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, s.tol, 50000, trace=True, frozen=frozen,
+                               mass=mass)
+    n = len(s.pos)
+    m = min(len(r["trace"]), len(ref["trace"]))
+    diff = np.nonzero(r["trace"][:m, 7] != ref["trace"][:m, 7])[0]
+    first = int(diff[0]) if len(diff) else None
+    print(f"{name}: gpu {r['stop']} {r['iterations']} it, oracle {ref['stop']} {ref['iterations']} it, "
+          f"first branch difference {first}")
+    assert r["stop"] == ref["stop"] == "converged"
+    if first is None and r["iterations"] == ref["iterations"]:
+        assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
+    else:
+        assert first is not None and first >= 50
+    frozen_components_unchanged(r["pos"], s, frozen)
+    # the oracle at the GPU's final positions: same energy, masked forces below tol
+    e_x, f_x = oracle.energy_forces(r["pos"], s.box, s.potential)
+    assert abs(e_x - r["energy"]) <= 1e-12 * abs(e_x)
+    f_x[(frozen[:, None] & (1 << np.arange(3))[None, :]) > 0] = 0.0
+    assert np.linalg.norm(f_x, axis=1).max() < s.tol * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("var", ["fire2", "vv"])
+@pytest.mark.parametrize("name", ["lj_6", "gupta_slab"])
+def test_unit_props_reproduce_the_plain_run_bitwise(api, var, name):
+    """Masses of 1 and no freeze bits take the property code paths (the extra
+    reductions, the per-atom scale) and give the plain run's bits."""
+    s = SMALL[name]()
+    fire = dict(s.fire, **VARIANTS[var])
+    n = len(s.pos)
+    c = api.Context(0, fire)
+    a = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000)
+    b = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000, frozen=np.zeros(n, np.uint8), mass=np.ones(n))
+    c.close()
+    assert a["iterations"] == b["iterations"] and a["rebuilds"] == b["rebuilds"]
+    np.testing.assert_array_equal(a["pos"], b["pos"])
+    assert a["energy"] == b["energy"] and a["fmax"] == b["fmax"]
+
+
+@pytest.mark.parametrize("name", ["lj_6", "gupta_slab"])
+def test_props_global_gather_path_is_bitwise_equal(api, name, monkeypatch):
+    """The passes with global gathers (separate update kernel) and the
+    LDS-staged passes with the update folded in give the same bits."""
+    s = SMALL[name]()
+    frozen, mass = props(s, 63)
+    c = api.Context(0, s.fire)
+    a = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 40, frozen=frozen, mass=mass)
+    c.close()
+    monkeypatch.setenv("FIRE_LDS", "0")
+    c = api.Context(0, s.fire)
+    b = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 40, frozen=frozen, mass=mass)
+    c.close()
+    np.testing.assert_array_equal(a["pos"], b["pos"])
+
+
+def test_props_device_entry_matches_host(api):
+    import torch
+    s = SMALL["gupta_slab"]()
+    frozen, mass = props(s, 64)
+    c = api.Context(0, s.fire)
+    h = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000, frozen=frozen, mass=mass)
+    x = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    r = c.fire_minimize_dev(x, s.box, s.potential, s.tol, 50000,
+                            frozen=torch.tensor(frozen, device="cuda"),
+                            mass=torch.tensor(mass, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    c.close()
+    assert r["iterations"] == h["iterations"] and r["energy"] == h["energy"]
+    np.testing.assert_array_equal(x.cpu().numpy(), h["pos"])
+
+
+def test_harmonic_well_with_masses(api):
+    """The list-free path (separate update kernel, harmonic force pass)."""
+    rng = np.random.default_rng(65)
+    n = 777
+    pos = rng.normal(size=(n, 3))
+    box = inputs.Box((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (0, 0, 0))
+    pot = inputs.harmonic_potential((1.0, 2.0, 0.5))
+    fire = inputs.fire_params(0.05)
+    mass = inputs.random_masses(n, 66)
+    frozen = np.zeros(n, np.uint8)
+    frozen[::3] = 2
+    c = api.Context(0, fire)
+    r = c.fire_minimize(pos, box, pot, 1e-8, 5000, frozen=frozen, mass=mass)
+    c.close()
+    ref = oracle.fire_minimize(pos, box, pot, fire, 1e-8, 5000, frozen=frozen, mass=mass)
+    assert r["stop"] == ref["stop"] == "converged" and r["iterations"] == ref["iterations"]
+    assert np.abs(r["pos"] - ref["pos"]).max() <= 1e-12
+    np.testing.assert_array_equal(r["pos"][::3, 1], pos[::3, 1])
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, np.nan, np.inf])
+def test_bad_mass_is_rejected_and_the_context_stays_usable(api, bad):
+    import torch
+    s = SMALL["lj_small"]()
+    n = len(s.pos)
+    mass = np.ones(n)
+    mass[n // 2] = bad
+    c = api.Context(0, s.fire)
+    with pytest.raises(api.FireError) as e:
+        c.fire_minimize(s.pos, s.box, s.potential, s.tol, 100, mass=mass)
+    assert e.value.name == "FIRE_E_ARG"
+    x = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    with pytest.raises(api.FireError) as e:
+        c.fire_minimize_dev(x, s.box, s.potential, s.tol, 100, mass=torch.tensor(mass, device="cuda"))
+    assert e.value.name == "FIRE_E_ARG"
+    a = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000)
+    c.close()
+    c = api.Context(0, s.fire)
+    b = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000)
+    c.close()
+    np.testing.assert_array_equal(a["pos"], b["pos"])
