@@ -5,8 +5,10 @@ this package.  It wraps ``oracle.c`` (plain C, brute-force pair sums, FP64)
 through ctypes and shares nothing with the HIP library.
 
 Functions (paper: Guenole et al., FIRE 2.0):
-  energy_forces   E and F = -grad E (Sec. 2.1) for LJ, Gupta (Sec. 5.2 EAM form)
-                  and a quadratic test well, brute force over all pairs.
+  energy_forces   E and F = -grad E (Sec. 2.1) for LJ, Gupta (Sec. 5.2 EAM form),
+                  Stillinger-Weber (the Si case of Sec. 5.3) and a quadratic
+                  test well, brute force over all pairs (and triplets).
+  sw_energy_direct  Stillinger-Weber E by a plain pair and triplet loop.
   sample_forces   the same for selected atoms, each computed on its own.
   hvp             analytic Hessian-vector product of the same energy.
   fire_minimize   FIRE 2.0 (Algorithm 2) with semi-implicit Euler and mixing
@@ -49,6 +51,8 @@ class _Pot(ctypes.Structure):
         ("A", ctypes.c_double), ("p", ctypes.c_double), ("q", ctypes.c_double), ("xi", ctypes.c_double),
         ("r0", ctypes.c_double), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
         ("k", ctypes.c_double * 3),
+        ("sw_B", ctypes.c_double), ("sw_a", ctypes.c_double), ("sw_lambda", ctypes.c_double),
+        ("sw_gamma", ctypes.c_double),
     ]
 
 
@@ -99,6 +103,7 @@ def _load():
                                              ctypes.c_long, P(_Result), dp, dp]
         lib.oracle_fire_minimize_ex.argtypes = [ctypes.c_long, dp, P(_Box), P(_Pot), P(_Fire), ctypes.c_void_p, dp,
                                                 ctypes.c_double, ctypes.c_long, P(_Result), dp, dp]
+        lib.oracle_sw_energy_direct.argtypes = [ctypes.c_long, dp, P(_Box), P(_Pot), dp]
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -141,6 +146,11 @@ def _pot(pot: dict) -> _Pot:
         p.kind = 3
         for d in range(3):
             p.k[d] = float(pot["k"][d])
+    elif kind == "sw":
+        p.kind = 4
+        for f in ("eps", "sigma", "A", "p", "q"):
+            setattr(p, f, float(pot[f]))
+        p.sw_B, p.sw_a, p.sw_lambda, p.sw_gamma = (float(pot[f]) for f in ("B", "a", "lambda", "gamma"))
     else:
         raise ValueError(kind)
     return p
@@ -195,6 +205,16 @@ def sample_forces(pos, box, pot, idx):
     _check(lib.oracle_sample_forces(pos.shape[0], _ptr(pos), ctypes.byref(b), ctypes.byref(p), m,
                                     idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _ptr(f), _ptr(ea)))
     return f, ea
+
+
+def sw_energy_direct(pos, box, pot):
+    """Stillinger-Weber E by a plain loop over every pair and triplet (small n)."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    e = ctypes.c_double()
+    b, p = _box(box), _pot(pot)
+    _check(lib.oracle_sw_energy_direct(pos.shape[0], _ptr(pos), ctypes.byref(b), ctypes.byref(p), ctypes.byref(e)))
+    return e.value
 
 
 def hvp(pos, u, box, pot):

@@ -13,6 +13,8 @@
  *     * energy-shifted 12-6 Lennard-Jones,
  *     * the second-moment (Gupta / RGL) EAM-form potential of Sec. 5.2
  *       (pair term plus embedding F(rho) = -xi sqrt(rho)), with a cubic taper,
+ *     * the Stillinger-Weber two- plus three-body potential of the Si test
+ *       case (Sec. 5.1, case 5 of Sec. 5.3; original parameterisation),
  *     * an anisotropic quadratic well (test potential),
  *     by brute force over every atom pair under the minimum image; each atom's
  *     sums run over all other atoms in index order (no cell list, no pruning),
@@ -43,6 +45,7 @@
 #define OR_POT_LJ 1
 #define OR_POT_GUPTA 2
 #define OR_POT_HARMONIC 3
+#define OR_POT_SW 4
 
 typedef struct {
   double lo[3];
@@ -56,6 +59,7 @@ typedef struct {
   double eps, sigma, rc;
   double A, p, q, xi, r0, r_in, r_out;
   double k[3];
+  double sw_B, sw_a, sw_lambda, sw_gamma; /* Stillinger-Weber (with eps, sigma, A, p, q) */
 } or_pot;
 
 int oracle_threads(void) {
@@ -88,6 +92,7 @@ static void min_image(const double *xi, const double *xj, const or_box *b, doubl
 static double pot_cutoff(const or_pot *p) {
   if (p->kind == OR_POT_LJ) return p->rc;
   if (p->kind == OR_POT_GUPTA) return p->r_out;
+  if (p->kind == OR_POT_SW) return p->sw_a * p->sigma;
   return 0.0;
 }
 
@@ -187,6 +192,176 @@ static int gupta_density_atom(long n, const double *pos, const or_box *b, const 
   return OR_OK;
 }
 
+/* ------------------------------------------------- Stillinger-Weber (Si)
+ *
+ * E = sum_{i<j} phi2(r_ij) + sum_i sum_{j<k; j,k != i} h(r_ij, r_ik, theta_jik)
+ *   phi2(r) = eps A [B (s/r)^p - (s/r)^q] exp(s / (r - a s))          r < a s
+ *   h       = lambda eps (cos theta_jik + 1/3)^2 g(r_ij) g(r_ik)
+ *   g(r)    = exp(gamma s / (r - a s))                                 r < a s
+ * (s = sigma; every term vanishes smoothly at the cutoff a s). */
+
+static void sw_phi2(const or_pot *p, double r, double *f0, double *f1) {
+  double s = p->sigma, rc = p->sw_a * s;
+  if (!(r < rc)) {
+    *f0 = *f1 = 0.0;
+    return;
+  }
+  double sr = s / r;
+  double bp = p->sw_B * pow(sr, p->p), bq = pow(sr, p->q);
+  double poly = bp - bq;
+  double dpoly = (-p->p * bp + p->q * bq) / r;
+  double ex = exp(s / (r - rc));
+  double dex = -s / ((r - rc) * (r - rc)) * ex;
+  *f0 = p->eps * p->A * poly * ex;
+  *f1 = p->eps * p->A * (dpoly * ex + poly * dex);
+}
+
+static void sw_g(const or_pot *p, double r, double *g0, double *g1) {
+  double s = p->sigma, rc = p->sw_a * s;
+  if (!(r < rc)) {
+    *g0 = *g1 = 0.0;
+    return;
+  }
+  *g0 = exp(p->sw_gamma * s / (r - rc));
+  *g1 = -p->sw_gamma * s / ((r - rc) * (r - rc)) * *g0;
+}
+
+/* Three-body term of the triplet centred at c with ends a and b, given
+ * u = x_a - x_c and w = x_b - x_c (both shorter than the cutoff); returns h
+ * and its gradients dh/du, dh/dw. */
+static double sw_h(const or_pot *p, const double u[3], const double w[3], double dhu[3], double dhw[3]) {
+  double ru = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  double rw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  double gu, gu1, gw, gw1;
+  sw_g(p, ru, &gu, &gu1);
+  sw_g(p, rw, &gw, &gw1);
+  double c = (u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) / (ru * rw);
+  double t = c + 1.0 / 3.0;
+  double le = p->sw_lambda * p->eps;
+  for (int a = 0; a < 3; ++a) {
+    double dcu = w[a] / (ru * rw) - c * u[a] / (ru * ru); /* d cos / du */
+    double dcw = u[a] / (ru * rw) - c * w[a] / (rw * rw);
+    dhu[a] = le * (2.0 * t * dcu * gu * gw + t * t * gu1 * (u[a] / ru) * gw);
+    dhw[a] = le * (2.0 * t * dcw * gu * gw + t * t * gu * gw1 * (w[a] / rw));
+  }
+  return le * t * t * gu * gw;
+}
+
+typedef struct {
+  long j;
+  double d[3]; /* x_j - x_i, minimum image */
+  double r;
+} sw_nb;
+
+/* Neighbours of atom i closer than the cutoff, in index order, into *out
+ * (malloc'd, caller frees); returns the count or a negative error code. */
+static long sw_neighbours(long n, const double *pos, const or_box *b, const or_pot *p, long i, sw_nb **out) {
+  double rc = pot_cutoff(p), rc2 = rc * rc;
+  long cap = 16, m = 0;
+  sw_nb *l = (sw_nb *)malloc(sizeof(sw_nb) * cap);
+  for (long j = 0; j < n; ++j) {
+    if (j == i) continue;
+    double d[3];
+    min_image(pos + 3 * j, pos + 3 * i, b, d);
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 == 0.0) {
+      free(l);
+      return OR_E_OVERLAP;
+    }
+    if (!(r2 < rc2)) continue;
+    if (m == cap) {
+      cap *= 2;
+      l = (sw_nb *)realloc(l, sizeof(sw_nb) * cap);
+    }
+    l[m].j = j;
+    l[m].d[0] = d[0];
+    l[m].d[1] = d[1];
+    l[m].d[2] = d[2];
+    l[m].r = sqrt(r2);
+    ++m;
+  }
+  *out = l;
+  return m;
+}
+
+/* F_i = -dE/dx_i collects every term that contains x_i: the pairs (i, j),
+ * the triplets centred at i, and the triplets centred at a neighbour m of i
+ * with i as one end.  e_i = 1/2 sum_j phi2 + the triplets centred at i. */
+static int sw_atom_force(long n, const double *pos, const or_box *b, const or_pot *p, long i, double f[3],
+                         double *e) {
+  sw_nb *ni = NULL;
+  long cnt = sw_neighbours(n, pos, b, p, i, &ni);
+  if (cnt < 0) return (int)cnt;
+  double fi[3] = {0.0, 0.0, 0.0}, ei = 0.0;
+  for (long a = 0; a < cnt; ++a) {
+    double f0, f1;
+    sw_phi2(p, ni[a].r, &f0, &f1);
+    ei += 0.5 * f0;
+    for (int k = 0; k < 3; ++k) fi[k] += f1 * ni[a].d[k] / ni[a].r;
+  }
+  for (long a = 0; a < cnt; ++a)
+    for (long c = a + 1; c < cnt; ++c) {
+      double dhu[3], dhw[3];
+      ei += sw_h(p, ni[a].d, ni[c].d, dhu, dhw);
+      for (int k = 0; k < 3; ++k) fi[k] += dhu[k] + dhw[k];
+    }
+  int err = OR_OK;
+  for (long a = 0; a < cnt && !err; ++a) {
+    long m = ni[a].j;
+    sw_nb *nm = NULL;
+    long cm = sw_neighbours(n, pos, b, p, m, &nm);
+    if (cm < 0) {
+      err = (int)cm;
+      break;
+    }
+    double u[3] = {-ni[a].d[0], -ni[a].d[1], -ni[a].d[2]}; /* x_i - x_m */
+    for (long c = 0; c < cm; ++c) {
+      if (nm[c].j == i) continue;
+      double dhu[3], dhw[3];
+      sw_h(p, u, nm[c].d, dhu, dhw);
+      for (int k = 0; k < 3; ++k) fi[k] -= dhu[k];
+    }
+    free(nm);
+  }
+  free(ni);
+  f[0] = fi[0]; f[1] = fi[1]; f[2] = fi[2];
+  *e = ei;
+  return err;
+}
+
+/* E straight from its definition for small systems: every pair i < j and
+ * every triplet (i; j < k) by a plain triple loop, no neighbour lists. */
+int oracle_sw_energy_direct(long n, const double *pos, const or_box *b, const or_pot *p, double *energy) {
+  int rc = check_inputs(n, pos, b, p);
+  if (rc) return rc;
+  if (p->kind != OR_POT_SW) return OR_E_ARG;
+  double cut = pot_cutoff(p);
+  double E = 0.0;
+  for (long i = 0; i < n; ++i)
+    for (long j = i + 1; j < n; ++j) {
+      double d[3], f0, f1;
+      min_image(pos + 3 * j, pos + 3 * i, b, d);
+      sw_phi2(p, sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]), &f0, &f1);
+      E += f0;
+    }
+  for (long i = 0; i < n; ++i)
+    for (long j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double u[3];
+      min_image(pos + 3 * j, pos + 3 * i, b, u);
+      if (!(sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) < cut)) continue;
+      for (long k = j + 1; k < n; ++k) {
+        if (k == i) continue;
+        double w[3], dhu[3], dhw[3];
+        min_image(pos + 3 * k, pos + 3 * i, b, w);
+        if (!(sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) < cut)) continue;
+        E += sw_h(p, u, w, dhu, dhw);
+      }
+    }
+  *energy = E;
+  return OR_OK;
+}
+
 /* Force and energy share of atom i.  For Gupta, rho[] must hold all
  * densities.  e_i: LJ 1/2 sum_j phi_s; Gupta c_e sum_j phi_t + F(rho_i). */
 static int atom_force(long n, const double *pos, const or_box *b, const or_pot *p, const double *rho,
@@ -200,6 +375,7 @@ static int atom_force(long n, const double *pos, const or_box *b, const or_pot *
     *e = 0.5 * (p->k[0] * x[0] * x[0] + p->k[1] * x[1] * x[1] + p->k[2] * x[2] * x[2]);
     return OR_OK;
   }
+  if (p->kind == OR_POT_SW) return sw_atom_force(n, pos, b, p, i, f, e);
   double rc = pot_cutoff(p), rc2 = rc * rc;
   double shift = 0.0;
   if (p->kind == OR_POT_LJ) {
@@ -356,6 +532,7 @@ static void pair_block(double g1, double g2, double r, const double dh[3], const
 int oracle_hvp(long n, const double *pos, const double *u, const or_box *b, const or_pot *p, double *hu) {
   int rc = check_inputs(n, pos, b, p);
   if (rc) return rc;
+  if (p->kind == OR_POT_SW) return OR_E_ARG; /* pair potentials and the well only */
   if (p->kind == OR_POT_HARMONIC) {
     for (long i = 0; i < n; ++i)
       for (int a = 0; a < 3; ++a) hu[3 * i + a] = p->k[a] * u[3 * i + a];

@@ -275,3 +275,62 @@ def random_masses(n: int, seed: int, lo: float = 0.5, hi: float = 4.0) -> np.nda
     relative to the reference mass)."""
     rng = np.random.default_rng(seed)
     return np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))
+
+
+# Stillinger-Weber silicon, the original parameterisation (Stillinger and
+# Weber 1985): eps in eV, sigma in Angstrom, the rest dimensionless.
+SW_SI = {"eps": 2.1683, "sigma": 2.0951, "A": 7.049556277, "B": 0.6022245584, "p": 4.0, "q": 0.0,
+         "a": 1.80, "lambda": 21.0, "gamma": 1.20}
+SI_MASS = 28.0855  # g/mol
+DIAMOND_BASIS = np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0],
+                          [0.25, 0.25, 0.25], [0.25, 0.75, 0.75], [0.75, 0.25, 0.75], [0.75, 0.75, 0.25]])
+
+
+def sw_potential() -> dict:
+    return dict(SW_SI, kind="sw")
+
+
+def sw_lattice_constant(pot: dict | None = None) -> float:
+    """Diamond lattice constant whose nearest-neighbour distance is
+    2^(1/6) sigma (where the SW pair term has its minimum)."""
+    s = (pot or SW_SI)["sigma"]
+    return 4.0 * 2.0 ** (1.0 / 6.0) * s / np.sqrt(3.0)
+
+
+def diamond_sites(nx: int, ny: int, nz: int, a: float) -> np.ndarray:
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    cells = np.stack([ix.ravel(order="F"), iy.ravel(order="F"), iz.ravel(order="F")], axis=1)
+    return ((cells[:, None, :].astype(np.float64) + DIAMOND_BASIS[None, :, :]) * a).reshape(-1, 3)
+
+
+def si_box(ncell, nvac=0, noise=0.05, seed=0, periodic=(1, 1, 1)) -> System:
+    """Diamond Si (SW equilibrium lattice constant), nvac vacancies drawn
+    without replacement, uniform +-noise Angstrom per component; on a free
+    axis the box spans the atoms with a margin."""
+    nc = (ncell,) * 3 if np.isscalar(ncell) else tuple(ncell)
+    pot = sw_potential()
+    a = sw_lattice_constant(pot)
+    rng = np.random.default_rng(seed)
+    sites = diamond_sites(*nc, a)
+    keep = np.ones(len(sites), bool)
+    if nvac:
+        keep[rng.choice(len(sites), nvac, replace=False)] = False
+    pos = sites[keep] + rng.uniform(-noise, noise, size=(int(keep.sum()), 3))
+    lo, length = [0.0] * 3, [0.0] * 3
+    for d in range(3):
+        if periodic[d]:
+            length[d] = nc[d] * a
+        else:
+            lo[d] = float(pos[:, d].min() - 4.0)
+            length[d] = float(np.ptp(pos[:, d]) + 8.0)
+    box = Box(tuple(lo), tuple(length), tuple(int(v) for v in periodic))
+    pos = _wrap(pos, box)
+    fire = workload_fire(0.001, EV_PER_A_AMU_IN_A_PER_PS2 / SI_MASS)
+    return System(f"si_{nc[0]}x{nc[1]}x{nc[2]}", pos, box, pot, fire, 1e-6, seed)
+
+
+def si_slab(seed: int = 5, ncell: int = 16, nvac: int = 5) -> System:
+    """Vacancies in a Si slab: 16^3 diamond cells (32,768 sites, 8.69 nm),
+    5 vacancies -> 32,763 atoms, periodic in x and y, free z."""
+    s = si_box(ncell, nvac=nvac, noise=0.05, seed=seed, periodic=(1, 1, 0))
+    return System("si_slab", s.pos, s.box, s.potential, s.fire, s.tol, seed)
