@@ -55,6 +55,7 @@ extern "C" {
 #define FIRE_POT_LJ 1         /* 4 eps [(s/r)^12 - (s/r)^6] - phi(rc) for r < rc */
 #define FIRE_POT_GUPTA 2      /* sum_j A e^{-p(r/r0-1)} S(r) - xi sqrt(sum_j e^{-2q(r/r0-1)} S(r)) */
 #define FIRE_POT_HARMONIC 3   /* 1/2 sum_i sum_d k_d x_id^2 (test well, no pairs) */
+#define FIRE_POT_SW 4         /* Stillinger-Weber: sum_{i<j} phi2(r_ij) + sum_i sum_{j<k} h(r_ij, r_ik, theta_jik) */
 
 #define FIRE_GUPTA_RGL 0      /* every ordered pair carries phi: E = sum_i [sum_j phi + F(rho_i)] */
 #define FIRE_GUPTA_HALF 1     /* EAM half sum: E = 1/2 sum_i sum_j phi + sum_i F(rho_i) */
@@ -91,13 +92,20 @@ typedef struct {
 /* Interatomic model.  LJ uses eps, sigma, rc.  Gupta uses A, p, q, xi, r0 and
  * the cubic taper S(r) = 1 (r <= r_in), (1-s)^2 (1+2s) with
  * s = (r - r_in)/(r_out - r_in), 0 (r >= r_out); r_out is the cutoff.
- * HARMONIC uses k[3]. */
+ * HARMONIC uses k[3].  SW (the Si test case of Sec. 5.3) uses eps, sigma, A,
+ * p, q and the sw_* fields, with s = sigma and cutoff a s:
+ *   phi2(r) = eps A [B (s/r)^p - (s/r)^q] exp(s / (r - a s)),
+ *   h       = lambda eps (cos theta_jik + 1/3)^2 g(r_ij) g(r_ik),
+ *   g(r)    = exp(gamma s / (r - a s)),  all zero for r >= a s.
+ * The SW path runs in FP64 whatever the precision setting, and has no
+ * Hessian product and no batched form. */
 typedef struct {
   int kind;        /* FIRE_POT_* */
   int convention;  /* FIRE_GUPTA_RGL or FIRE_GUPTA_HALF */
   double eps, sigma, rc;
   double A, p, q, xi, r0, r_in, r_out;
   double k[3];
+  double sw_B, sw_a, sw_lambda, sw_gamma;
 } fire_potential;
 
 /* FIRE parameters.  The first twelve fields are Table 1 of the paper

@@ -15,7 +15,7 @@ FIRE_OK = 0
 ERRORS = {-1: "FIRE_E_ARG", -2: "FIRE_E_BOX", -3: "FIRE_E_NONFINITE", -4: "FIRE_E_OVERLAP",
           -5: "FIRE_E_DEVICE", -6: "FIRE_E_OOM"}
 STOP = {1: "converged", 2: "max_steps", 3: "maxvdotf"}
-POT = {"lj": 1, "gupta": 2, "harmonic": 3}
+POT = {"lj": 1, "gupta": 2, "harmonic": 3, "sw": 4}
 CONVENTION = {"rgl": 0, "half": 1}
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
 INTEGRATOR = {"eulerimplicit": 0, "eulerexplicit": 1, "verlet": 2}
@@ -44,6 +44,8 @@ class fire_potential(ctypes.Structure):
         ("A", ctypes.c_double), ("p", ctypes.c_double), ("q", ctypes.c_double), ("xi", ctypes.c_double),
         ("r0", ctypes.c_double), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
         ("k", ctypes.c_double * 3),
+        ("sw_B", ctypes.c_double), ("sw_a", ctypes.c_double), ("sw_lambda", ctypes.c_double),
+        ("sw_gamma", ctypes.c_double),
     ]
 
 

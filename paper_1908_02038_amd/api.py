@@ -31,7 +31,7 @@ def make_box(box) -> L.fire_box:
 
 
 def make_potential(pot) -> L.fire_potential:
-    """fire_potential from a dict (kind lj / gupta / harmonic)."""
+    """fire_potential from a dict (kind lj / gupta / harmonic / sw)."""
     if isinstance(pot, L.fire_potential):
         return pot
     p = L.fire_potential()
@@ -42,6 +42,10 @@ def make_potential(pot) -> L.fire_potential:
         p.convention = L.CONVENTION[pot.get("convention", "rgl")]
         for f in ("A", "p", "q", "xi", "r0", "r_in", "r_out"):
             setattr(p, f, float(pot[f]))
+    elif pot["kind"] == "sw":
+        for f in ("eps", "sigma", "A", "p", "q"):
+            setattr(p, f, float(pot[f]))
+        p.sw_B, p.sw_a, p.sw_lambda, p.sw_gamma = (float(pot[f]) for f in ("B", "a", "lambda", "gamma"))
     else:
         for d in range(3):
             p.k[d] = float(pot["k"][d])

@@ -1430,8 +1430,6 @@ __global__ __launch_bounds__(kBlock) void k_harmonic_force(const double4* __rest
   force_epilogue(i, valid, fx, fy, fz, e, frc, vel, ncap, part, nullptr, b, ctrl, trace, pr);
 }
 
-// ------------------------------------------------------- Hessian * u (FP64)
-
 // Neighbour indices of atom i one at a time (dummy padding included; callers
 // reject it by the cutoff test before touching per-atom arrays).
 template <typename F>
@@ -1441,6 +1439,130 @@ __device__ __forceinline__ void for_neighbour_index(const int* __restrict__ nbr,
   const int kw = wcnt[w];
   for (int k = 0; k < kw; ++k) fn(nbr[lidx(w, k, lane, kcap)]);
 }
+
+// -------------------------------------------------- Stillinger-Weber (FP64)
+//
+// Two passes per evaluation.  k_sw_short compacts each real atom's in-range
+// neighbours (r < a sigma) from the skin list into a short list of 64-byte
+// records {x_j - x_i, 1/r ; g(r), g'(r), slot j} and sums the atom's pair
+// terms.  k_sw_force then gathers every three-body term that contains x_i:
+// the triplets centred at i, from i's own list, and the triplets centred at
+// each neighbour m with i as one end, from m's list (a periodic image reads
+// its source's list: relative vectors are the same).  No atomics: every
+// atom sums its own force in a fixed order.
+
+__device__ __forceinline__ void sw_record(double4* __restrict__ rec, double dx, double dy, double dz, double ir,
+                                          double g, double g1, int j) {
+  rec[0] = make_double4(dx, dy, dz, ir);
+  rec[1] = make_double4(g, g1, (double)j, 0.0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sw_short(const double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                     const int* __restrict__ wcnt, int n, int kcap, PotDev pot,
+                                                     double4* __restrict__ sw_nb, int* __restrict__ sw_cnt,
+                                                     double4* __restrict__ sw_fe, Ctrl* __restrict__ ctrl) {
+  if (!pass_gate(ctrl)) return;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 pi = pos[i];
+  double4* rec = sw_nb + 2 * (size_t)i * kcap;
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  int c = 0;
+  for_neighbour_index(nbr, wcnt, kcap, i, [&](int j) {
+    const double4 pj = pos[j];
+    const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < pot.rc2)) return;
+    const double r = sqrt(r2), ir = 1.0 / r, t = 1.0 / (r - pot.sw_as);
+    const double g = exp(pot.sw_gs * t), g1 = -pot.sw_gs * t * t * g;
+    // pair term and its derivative along r
+    const double sr = pot.sw_s * ir;
+    const double bp = pot.sw_B * pow(sr, pot.sw_p), bq = pow(sr, pot.sw_q);
+    const double poly = bp - bq, dpoly = (-pot.sw_p * bp + pot.sw_q * bq) * ir;
+    const double ex = exp(pot.sw_s * t), dex = -pot.sw_s * t * t * ex;
+    const double f1 = pot.sw_Aeps * (dpoly * ex + poly * dex);
+    e += 0.5 * pot.sw_Aeps * poly * ex;
+    fx += f1 * dx * ir;
+    fy += f1 * dy * ir;
+    fz += f1 * dz * ir;
+    sw_record(rec + 2 * c, dx, dy, dz, ir, g, g1, j);
+    ++c;
+  });
+  sw_cnt[i] = c;
+  sw_fe[i] = make_double4(fx, fy, fz, e);
+}
+
+// Gradient of the triplet term (centre c, ends a, b) with respect to the
+// end vector u = x_a - x_c, given w = x_b - x_c; returns h.  When both is
+// set, adds dh/du + dh/dw into acc, else subtracts dh/du.
+template <bool BOTH>
+__device__ __forceinline__ double sw_triplet(const PotDev& pot, const double (&u)[3], double iru, double gu,
+                                             double gu1, const double (&w)[3], double irw, double gw, double gw1,
+                                             double (&acc)[3]) {
+  const double c = (u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) * iru * irw;
+  const double t = c + 1.0 / 3.0;
+  const double a2 = 2.0 * pot.sw_leps * t * gu * gw;  // dh/dcos
+  const double bu = pot.sw_leps * t * t * gu1 * gw * iru;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double dcu = w[d] * iru * irw - c * u[d] * iru * iru;
+    const double dhu = a2 * dcu + bu * u[d];
+    if constexpr (BOTH) {
+      const double dcw = u[d] * iru * irw - c * w[d] * irw * irw;
+      const double dhw = a2 * dcw + pot.sw_leps * t * t * gu * gw1 * irw * w[d];
+      acc[d] += dhu + dhw;
+    } else {
+      acc[d] -= dhu;
+    }
+  }
+  return pot.sw_leps * t * t * gu * gw;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sw_force(const double4* __restrict__ sw_nb, const int* __restrict__ sw_cnt,
+                                                     const double4* __restrict__ sw_fe,
+                                                     const int* __restrict__ real_of, int n, int kcap, int ncap,
+                                                     PotDev pot, double* __restrict__ frc, double* __restrict__ vel,
+                                                     double* __restrict__ part, Ctrl* __restrict__ ctrl,
+                                                     double* __restrict__ trace, Props pr) {
+  if (!pass_gate(ctrl)) return;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  double f[3] = {0, 0, 0}, e = 0.0;
+  if (valid) {
+    const double4 fe = sw_fe[i];
+    f[0] = fe.x;
+    f[1] = fe.y;
+    f[2] = fe.z;
+    e = fe.w;
+    const int ci = sw_cnt[i];
+    const double4* li = sw_nb + 2 * (size_t)i * kcap;
+    for (int a = 0; a < ci; ++a) {
+      const double4 ra = li[2 * a], sa = li[2 * a + 1];
+      const double u[3] = {ra.x, ra.y, ra.z};
+      // triplets centred at i: (a, c) with c > a
+      for (int c = a + 1; c < ci; ++c) {
+        const double4 rc = li[2 * c], sc = li[2 * c + 1];
+        const double w[3] = {rc.x, rc.y, rc.z};
+        e += sw_triplet<true>(pot, u, ra.w, sa.x, sa.y, w, rc.w, sc.x, sc.y, f);
+      }
+      // triplets centred at m = neighbour a, with i as one end
+      const int m = real_of[(int)sa.z];
+      const int cm = sw_cnt[m];
+      const double4* lm = sw_nb + 2 * (size_t)m * kcap;
+      const double v[3] = {-ra.x, -ra.y, -ra.z};  // x_i - x_m
+      for (int k = 0; k < cm; ++k) {
+        const double4 rk = lm[2 * k], sk = lm[2 * k + 1];
+        if (real_of[(int)sk.z] == i) continue;
+        const double w[3] = {rk.x, rk.y, rk.z};
+        sw_triplet<false>(pot, v, ra.w, sa.x, sa.y, w, rk.w, sk.x, sk.y, f);
+      }
+    }
+  }
+  force_epilogue(i, valid, f[0], f[1], f[2], e, frc, vel, ncap, part, nullptr, b, ctrl, trace, pr);
+}
+
+// ------------------------------------------------------- Hessian * u (FP64)
 
 // Gupta HVP prologue: rho_i, F'_i, F''_i and s_i = sum_j rho'(r) dh.(u_i - u_j).
 // Per-atom vectors are indexed by real slot (real_of maps ghosts to sources).
@@ -1655,6 +1777,11 @@ struct fire_ctx {
   double *minv_atom = nullptr, *sinv = nullptr;
   unsigned char *fmask_atom = nullptr, *fmask = nullptr;
   bool with_mass = false, with_frozen = false;
+  // Stillinger-Weber short lists: kcap records of 2 double4 per real slot,
+  // their counts, and each atom's pair force and energy
+  double4 *sw_nb = nullptr, *sw_fe = nullptr;
+  int* sw_cnt = nullptr;
+  size_t sw_cap = 0;
   double* aux = nullptr;  // HVP / Lanczos planes
   int aux_planes = 0;
   Ctrl* ctrl = nullptr;
@@ -1725,6 +1852,10 @@ void free_single(fire_ctx* c) {
   hipFree(c->xref); hipFree(c->wcnt); hipFree(c->tile_h); hipFree(c->hslot); hipFree(c->hsrc); hipFree(c->nbr16);
   hipFree(c->gcount); hipFree(c->goff); hipFree(c->gcnt); hipFree(c->glist); hipFree(c->new_of_old);
   hipFree(c->minv_atom); hipFree(c->sinv); hipFree(c->fmask_atom); hipFree(c->fmask);
+  hipFree(c->sw_nb); hipFree(c->sw_fe); hipFree(c->sw_cnt);
+  c->sw_nb = c->sw_fe = nullptr;
+  c->sw_cnt = nullptr;
+  c->sw_cap = 0;
   c->minv_atom = c->sinv = nullptr;
   c->fmask_atom = c->fmask = nullptr;
   c->with_mass = c->with_frozen = false;
@@ -1831,7 +1962,7 @@ int ensure_aux(fire_ctx* ctx, int planes) {
 
 int prepare_pot(fire_ctx* ctx, const fire_potential* p, PotDev& d) {
   if (!p) return set_err(ctx, FIRE_E_ARG, "potential is required");
-  if (p->kind != FIRE_POT_LJ && p->kind != FIRE_POT_GUPTA && p->kind != FIRE_POT_HARMONIC)
+  if (p->kind != FIRE_POT_LJ && p->kind != FIRE_POT_GUPTA && p->kind != FIRE_POT_HARMONIC && p->kind != FIRE_POT_SW)
     return set_err(ctx, FIRE_E_ARG, "unknown potential kind");
   d = PotDev{};
   d.kind = p->kind;
@@ -1858,6 +1989,18 @@ int prepare_pot(fire_ctx* ctx, const fire_potential* p, PotDev& d) {
     d.inv_w = 1.0 / (p->r_out - p->r_in);
     d.cpair = p->convention == FIRE_GUPTA_RGL ? 2.0 : 1.0;
     d.epair = p->convention == FIRE_GUPTA_RGL ? 1.0 : 0.5;
+  } else if (p->kind == FIRE_POT_SW) {
+    if (!(p->sigma > 0) || !(p->sw_a > 0) || !std::isfinite(p->sigma * p->sw_a))
+      return set_err(ctx, FIRE_E_ARG, "SW needs sigma > 0 and a > 0");
+    d.rc = p->sw_a * p->sigma;
+    d.sw_s = p->sigma;
+    d.sw_as = p->sw_a * p->sigma;
+    d.sw_Aeps = p->A * p->eps;
+    d.sw_B = p->sw_B;
+    d.sw_p = p->p;
+    d.sw_q = p->q;
+    d.sw_leps = p->sw_lambda * p->eps;
+    d.sw_gs = p->sw_gamma * p->sigma;
   } else {
     for (int k = 0; k < 3; ++k) d.k[k] = p->k[k];
   }
@@ -2034,7 +2177,10 @@ int build_lists(fire_ctx* ctx) {
   const int n = ctx->n, nb = nblocks(n), dummy = ctx->tcap - 1;
   const double rcs2 = ctx->rcs * ctx->rcs;
   const bool was = ctx->use_lds;
-  const int hcap = (int)std::min<size_t>(ctx->lds_limit / halo_bytes_per_atom(ctx), 65535);
+  // no LDS tiles for the three-body potential (its force pass reads the
+  // neighbours' short lists, not their positions)
+  const int hcap = ctx->pot.kind == FIRE_POT_SW ? 0
+                                                : (int)std::min<size_t>(ctx->lds_limit / halo_bytes_per_atom(ctx), 65535);
   for (int attempt = 0; attempt < 6; ++attempt) {
     if (!ctx->nbr16) HIPCHK(dalloc(&ctx->nbr16, (size_t)ctx->kcap * ctx->ncap));
     if (hcap >= 64 && (!ctx->hslot || ctx->hcap != hcap)) {
@@ -2166,6 +2312,22 @@ int rebuild(fire_ctx* ctx) {
   }
   rc = build_lists(ctx);
   if (rc) return rc;
+  if (ctx->pot.kind == FIRE_POT_SW) {
+    const size_t need = (size_t)ctx->kcap * ctx->ncap;
+    if (need > ctx->sw_cap) {
+      hipFree(ctx->sw_nb);
+      hipFree(ctx->sw_fe);
+      hipFree(ctx->sw_cnt);
+      ctx->sw_nb = ctx->sw_fe = nullptr;
+      ctx->sw_cnt = nullptr;
+      ctx->sw_cap = 0;
+      HIPCHK(dalloc(&ctx->sw_nb, 2 * need));
+      HIPCHK(dalloc(&ctx->sw_fe, (size_t)ctx->ncap));
+      HIPCHK(dalloc(&ctx->sw_cnt, (size_t)ctx->ncap));
+      ctx->sw_cap = need;
+      ctx->layout_version++;
+    }
+  }
   ctx->have_list = true;
   gather_props(ctx, s);
   return FIRE_OK;
@@ -2230,8 +2392,21 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
   }
 }
 
+void launch_sw(fire_ctx* ctx, hipStream_t s) {
+  const int n = ctx->n, nb = nblocks(n);
+  hipLaunchKernelGGL(k_sw_short, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, ctx->kcap, ctx->pot,
+                     ctx->sw_nb, ctx->sw_cnt, ctx->sw_fe, ctx->ctrl);
+  hipLaunchKernelGGL(k_sw_force, dim3(nb), dim3(kBlock), 0, s, ctx->sw_nb, ctx->sw_cnt, ctx->sw_fe, ctx->real_of, n,
+                     ctx->kcap, ctx->ncap, ctx->pot, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace,
+                     props_of(ctx));
+}
+
 template <bool WE>
 void launch_pairs(fire_ctx* ctx, hipStream_t s, int prec, int parity) {
+  if (ctx->pot.kind == FIRE_POT_SW) {  // FP64, global gathers, energy always summed
+    launch_sw(ctx, s);
+    return;
+  }
   if (ctx->use_lds) {
     if (prec) launch_pair_passes<float, true, WE>(ctx, s, parity);
     else launch_pair_passes<double, true, WE>(ctx, s, parity);
@@ -2426,7 +2601,8 @@ void ctrl_defaults(fire_ctx* ctx, Ctrl& c, double tol, long long max_steps, int 
   const fire_params& p = ctx->params;
   memset(&c, 0, sizeof(c));
   c.status = ST_RUNNING;
-  c.precision = p.precision == FIRE_FP64 ? 0 : 1;
+  // the three-body path has FP64 terms only
+  c.precision = (p.precision == FIRE_FP64 || ctx->pot.kind == FIRE_POT_SW) ? 0 : 1;
   c.dt_start = p.dt_start;
   c.dtmax = p.tmax * p.dt_start;
   c.dtmin = p.tmin * p.dt_start;
@@ -2447,7 +2623,7 @@ void ctrl_defaults(fire_ctx* ctx, Ctrl& c, double tol, long long max_steps, int 
   c.integrator = p.integrator;
   c.criterion = p.criterion;
   c.variant = p.variant;
-  c.mode = p.precision;
+  c.mode = ctx->pot.kind == FIRE_POT_SW ? FIRE_FP64 : p.precision;
   c.natoms = ctx->n;
   c.dt = p.dt_start;
   c.alpha = p.alpha0;
@@ -2560,7 +2736,7 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
   if (out) {
     memset(out, 0, sizeof(*out));
     out->stop_reason = h.status;
-    out->precision_switched = (ctx->params.precision == FIRE_MIXED && h.precision == 0) ? 1 : 0;
+    out->precision_switched = (h.mode == FIRE_MIXED && h.precision == 0) ? 1 : 0;
     out->iterations = h.iter;
     out->force_evals = h.evals;
     out->iterations_low = h.iter_low;
@@ -2938,6 +3114,7 @@ static int hvp_common(fire_ctx* ctx, long long n, const double* pos, const doubl
   if (!u || !hu) return set_err(ctx, FIRE_E_ARG, "u and hu are required");
   int rc = prepare_system(ctx, box, pot);
   if (rc) return rc;
+  if (ctx->pot.kind == FIRE_POT_SW) return set_err(ctx, FIRE_E_ARG, "no Hessian product for the SW potential");
   hipStream_t saved = ctx->stream;
   ctx->stream = s;
   rc = stage_in(ctx, n, pos, host, s);
@@ -2991,6 +3168,7 @@ int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const f
   if (!lambda_min || k < 1 || k > 500) return set_err(ctx, FIRE_E_ARG, "need lambda_min and 1 <= k <= 500");
   rc = prepare_system(ctx, box, pot);
   if (rc) return rc;
+  if (ctx->pot.kind == FIRE_POT_SW) return set_err(ctx, FIRE_E_ARG, "no Hessian product for the SW potential");
   hipStream_t s = ctx->stream;
   rc = stage_in(ctx, n, pos, true, s);
   if (rc) return rc;

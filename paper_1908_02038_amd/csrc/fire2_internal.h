@@ -41,6 +41,9 @@ struct PotDev {
   double A, pr0, qr0, xi, r0, r_in, inv_w;  // Gupta: pr0 = p / r0, qr0 = 2 q / r0
   double cpair, epair;  // Gupta force / energy weights of the pair term (RGL 2, 1; half 1, 1/2)
   double k[3];          // harmonic well
+  // Stillinger-Weber: phi2 = Aeps [B (s/r)^p - (s/r)^q] exp(s / (r - as)),
+  // h = leps (cos + 1/3)^2 g g, g = exp(gs / (r - as)); rc = as
+  double sw_s, sw_as, sw_Aeps, sw_B, sw_p, sw_q, sw_leps, sw_gs;
 };
 
 // FIRE control record of one system, resident in device memory.  The first
