@@ -36,11 +36,16 @@ PEAK_FP64_TFLOPS = 78.6
 # updates 6, plus the cutoff test); Gupta r_out = 5 A -> 42 neighbours = 21
 # pairs of ~125 flop (FP64, two exponentials and a square root).  Bytes: positions read once, velocities
 # read for P = F.v, forces written (3 x 8 B each); the EAM form adds F'(rho)
-# written and read (2 x 8 B).
+# written and read (2 x 8 B).  Stillinger-Weber on diamond Si: 4 neighbours
+# -> 2 pairs of ~70 flop (two exponentials, a power) and 6 triplets of ~90 flop
+# (cosine, both end gradients, the radial factors), each term counted once;
+# bytes as for LJ (the short lists are the implementation's, not the method's).
 ALG = {
     "lj": {"bytes": 72.0, "flops": 27.0 * 25.0, "kernel": "k_lj_force", "tag": "k_lj_force_global"},
     "gupta": {"bytes": 120.0, "flops": 21.0 * 165.0, "kernel": "k_gupta_density + k_gupta_force",
               "tag": "k_gupta_global"},
+    "sw": {"bytes": 72.0, "flops": 2.0 * 70.0 + 6.0 * 90.0, "kernel": "k_sw_short + k_sw_force",
+           "tag": "k_sw_global"},
 }
 # The LDS-staged loop folds the update into the first pass of each iteration
 # (the kernel that dominates a relaxation): per atom it also reads the
@@ -237,7 +242,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lj_bulk", choices=["lj_small", "lj_bulk", "gupta_bulk", "gupta_slab"])
+    ap.add_argument("--workload", default="lj_bulk",
+                    choices=["lj_small", "lj_bulk", "gupta_bulk", "gupta_slab", "si_slab"])
     ap.add_argument("--max-steps", type=int, default=100000)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -277,7 +283,9 @@ def main():
     log(f"[bench] fp64: {args.steps} relaxations in {dt:.3f} s, {r['iterations']} iterations each, "
         f"stop {r['stop']}, E/N {r['energy_per_atom']:.12f}, fmax {r['fmax']:.3e}, rebuilds {r['rebuilds']}")
     kt = kernel_time_ms(ctx, args.kernel_reps)
-    staged = os.environ.get("FIRE_LDS", "1") != "0"  # LDS-staged tiles (and the folded update) unless switched off
+    # LDS-staged tiles (and the folded update) unless switched off; the
+    # three-body path always gathers from global memory
+    staged = os.environ.get("FIRE_LDS", "1") != "0" and kind != "sw"
     alg = FUSED[kind] if staged else ALG[kind]
     bytes_launch = alg["bytes"] * n
     flops_launch = alg["flops"] * n
@@ -293,7 +301,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": hbm_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": hbm_ach / PEAK_HBM_GBS}
-    roof.update({"traffic": traffic, "kernel": kname if staged else kname + "<double, false, false>",
+    roof.update({"traffic": traffic,
+                 "kernel": kname if (staged or kind == "sw") else kname + "<double, false, false>",
                  "ms_per_launch": kt,
                  "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops_launch,
                  "hbm_achieved_GBs": hbm_ach, "hbm_frac": hbm_ach / PEAK_HBM_GBS,
@@ -327,7 +336,7 @@ def main():
     }
 
     # ---- mixed precision on the same input
-    if not args.no_mixed:
+    if not args.no_mixed and kind != "sw":  # the three-body path has no FP32 terms
         ctxm = api.Context(0, s.fire, precision="mixed")
         dtm, resm, _ = time_relaxations(ctxm, pos0, s, args.steps, args.warmup, args.max_steps)
         rm = resm[-1]

@@ -63,7 +63,7 @@ class _Fire(ctypes.Structure):
         ("alphashrink", ctypes.c_double), ("f2a", ctypes.c_double),
         ("delaystep", ctypes.c_int), ("vdfmax", ctypes.c_int), ("halfstepback", ctypes.c_int),
         ("initialdelay", ctypes.c_int), ("integrator", ctypes.c_int), ("criterion", ctypes.c_int),
-        ("variant", ctypes.c_int),
+        ("variant", ctypes.c_int), ("pad", ctypes.c_int), ("dmax", ctypes.c_double),
     ]
 
 
@@ -165,6 +165,7 @@ def _fire(fp: dict) -> _Fire:
     f.integrator = {"eulerimplicit": 0, "eulerexplicit": 1, "verlet": 2}[fp.get("integrator", "eulerimplicit")]
     f.criterion = {"fmax": 0, "f2norm": 1}[fp.get("criterion", "fmax")]
     f.variant = {"fire2": 0, "fire1": 1}[fp.get("variant", "fire2")]
+    f.dmax = float(fp.get("dmax", 0.0))
     return f
 
 

@@ -628,6 +628,8 @@ typedef struct {
   int integrator; /* 0 semi-implicit Euler, 1 explicit Euler, 2 velocity Verlet */
   int criterion;  /* 0 max per-atom |F_i|, 1 Euclidean norm of the 3N force vector */
   int variant;    /* 0 FIRE 2.0 (Algorithm 2), 1 original FIRE (Algorithm 1) */
+  int pad;
+  double dmax;    /* > 0: largest displacement of any atom in one drift (see drift()) */
 } or_fire;
 
 typedef struct {
@@ -673,6 +675,26 @@ static void apply_frozen(long n, double *f, const unsigned char *frozen) {
   for (long i = 0; i < n; ++i)
     for (int d = 0; d < 3; ++d)
       if (frozen[i] & (1 << d)) f[3 * i + d] = 0.0;
+}
+
+/* The drift x += dt_x v of one step.  Without dmax, dt_x = dt.  With dmax
+ * (the maximum atomic displacement per step the paper's melt case needed,
+ * Sec. 5.3; the paper names the setting but not its mechanism), the step is
+ * shortened so that the fastest atom moves exactly dmax:
+ * dt_x = min(dt, dmax / max_i |v_i|), with v the velocity the drift uses.
+ * dt itself (the FIRE state, the kicks, the half step back) is unchanged. */
+static void drift(long n, double *pos, const double *v, double dt, double dmax) {
+  double dtx = dt;
+  if (dmax > 0.0) {
+    double vmax2 = 0.0;
+    for (long i = 0; i < n; ++i) {
+      double s = v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2];
+      if (s > vmax2) vmax2 = s;
+    }
+    double vmax = sqrt(vmax2);
+    if (vmax * dt > dmax) dtx = dmax / vmax;
+  }
+  for (long k = 0; k < 3 * n; ++k) pos[k] += dtx * v[k];
 }
 
 /* The kick of one component: v += (c s_i) F with c the step's kick factor
@@ -782,13 +804,13 @@ int oracle_fire_minimize_ex(long n, double *pos, const or_box *b, const or_pot *
       /* Algorithm 4: kick, mix, drift */
       kick(n, v, f, dtf, inv_mass);
       if (mixing) mix(n, v, f, alpha);
-      for (long k = 0; k < 3 * n; ++k) pos[k] += dt * v[k];
+      drift(n, pos, v, dt, fp->dmax);
       rc = oracle_energy_forces(n, pos, b, p, &E, f, NULL, NULL);
       apply_frozen(n, f, frozen);
     } else if (fp->integrator == 1) {
       /* Algorithm 3: mix, drift with the old v, kick with the old force */
       if (mixing) mix(n, v, f, alpha);
-      for (long k = 0; k < 3 * n; ++k) pos[k] += dt * v[k];
+      drift(n, pos, v, dt, fp->dmax);
       kick(n, v, f, dtf, inv_mass);
       rc = oracle_energy_forces(n, pos, b, p, &E, f, NULL, NULL);
       apply_frozen(n, f, frozen);
@@ -796,7 +818,7 @@ int oracle_fire_minimize_ex(long n, double *pos, const or_box *b, const or_pot *
       /* Algorithm 6: half kick, mix, drift, force, half kick */
       kick(n, v, f, 0.5 * dtf, inv_mass);
       if (mixing) mix(n, v, f, alpha);
-      for (long k = 0; k < 3 * n; ++k) pos[k] += dt * v[k];
+      drift(n, pos, v, dt, fp->dmax);
       rc = oracle_energy_forces(n, pos, b, p, &E, fnew, NULL, NULL);
       memcpy(f, fnew, sizeof(double) * 3 * n);
       apply_frozen(n, f, frozen);

@@ -243,6 +243,7 @@ WORKLOADS = {
     "lj_bulk": lj_bulk,
     "gupta_bulk": gupta_bulk,
     "gupta_slab": gupta_slab,
+    "si_slab": lambda: si_slab(),
 }
 
 

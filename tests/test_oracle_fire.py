@@ -248,3 +248,52 @@ def test_frozen_components_never_move_and_the_rest_relaxes():
     _, f = oracle.energy_forces(r["pos"], s.box, s.potential)
     f[(frozen[:, None] & (1 << np.arange(3))[None, :]) > 0] = 0.0
     assert np.linalg.norm(f, axis=1).max() < 1e-7
+
+
+# ---- dmax: the largest displacement of any atom in one step (the melt case
+# of Sec. 5.3); the drift is shortened to dt_x = min(dt, dmax / max_i |v_i|)
+
+def test_dmax_above_every_step_changes_nothing():
+    s = inputs.lj_box(3, nvac=1, noise=0.08, seed=64, rc=2.0)
+    a = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 0.0, 60, trace=True)
+    b = oracle.fire_minimize(s.pos, s.box, s.potential, dict(s.fire, dmax=1e6), 0.0, 60, trace=True)
+    assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["trace"], b["trace"])
+
+
+def test_dmax_caps_the_first_step_in_a_well():
+    # 1-D well: the first step's drift would move x0 -> x0 (1 - k dt^2); with
+    # dmax below k dt^2 x0 the atom moves by exactly dmax toward the minimum
+    k, dt, x0 = 2.0, 0.1, 1.5
+    assert k * dt * dt * x0 > 0.01
+    r = run([x0, 0, 0], (k, 0, 0), 1, dt_start=dt, dmax=0.01)
+    assert r["pos"][0, 0] == pytest.approx(x0 - 0.01, rel=1e-15)
+    r = run([x0, 0, 0], (k, 0, 0), 1, dt_start=dt, dmax=0.5)  # not binding
+    assert r["pos"][0, 0] == pytest.approx(x0 * (1 - k * dt * dt), rel=1e-15)
+    # dt itself is unchanged by the cap: the second step's kick still uses dt
+    r = run([x0, 0, 0], (k, 0, 0), 1, dt_start=dt, dmax=0.01)
+    assert r["trace"][1, 5] == dt
+
+
+@pytest.mark.parametrize("integrator", ["eulerimplicit", "eulerexplicit", "verlet"])
+def test_dmax_bounds_every_drift_and_binds(integrator):
+    """A strongly disordered LJ start (large forces): without the half step
+    back only the drift moves atoms, so between consecutive iterations no
+    atom moves more than dmax, and the cap is reached."""
+    s = inputs.lj_box(3, nvac=2, noise=0.2, seed=65, rc=2.0)
+    dmax = 0.01
+    fire = dict(s.fire, dmax=dmax, halfstepback=0, integrator=integrator, dt_start=0.01)
+    prev = s.pos
+    hit = 0
+    for k in range(1, 16):
+        r = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 0.0, k)
+        d = r["pos"] - prev
+        for a in range(3):
+            d[:, a] -= s.box.length[a] * np.rint(d[:, a] / s.box.length[a])
+        step = np.linalg.norm(d, axis=1).max()
+        assert step <= dmax * (1 + 1e-12)
+        hit += step > dmax * (1 - 1e-12)
+        prev = r["pos"]
+    assert hit >= 3
+    # and the capped run still relaxes
+    r = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 1e-6, 50000)
+    assert r["stop"] == "converged"
