@@ -133,6 +133,13 @@ typedef struct {
                           <= 0 selects 100 * tol */
   double skin;         /* neighbour-list skin in length units; <= 0 selects 0.12 * cutoff,
                           clamped to fit the box */
+  double dmax;         /* > 0: displacement cap (the maximum atomic displacement per step of
+                          the melt case, Sec. 5.3).  The drift uses the step
+                          min(dt, dmax / max_i |v_i|), v the velocity it moves the atoms
+                          with, so no atom drifts more than dmax; the half step back undoes
+                          half of such a step of the velocity being zeroed (at most dmax/2).
+                          dt itself and the kicks are unchanged.  0 (default): no cap.  Not
+                          available in the batched form. */
 } fire_params;
 
 /* Outcome of a minimisation.  iterations counts integration steps

@@ -677,23 +677,26 @@ static void apply_frozen(long n, double *f, const unsigned char *frozen) {
       if (frozen[i] & (1 << d)) f[3 * i + d] = 0.0;
 }
 
-/* The drift x += dt_x v of one step.  Without dmax, dt_x = dt.  With dmax
- * (the maximum atomic displacement per step the paper's melt case needed,
- * Sec. 5.3; the paper names the setting but not its mechanism), the step is
- * shortened so that the fastest atom moves exactly dmax:
- * dt_x = min(dt, dmax / max_i |v_i|), with v the velocity the drift uses.
- * dt itself (the FIRE state, the kicks, the half step back) is unchanged. */
-static void drift(long n, double *pos, const double *v, double dt, double dmax) {
-  double dtx = dt;
-  if (dmax > 0.0) {
-    double vmax2 = 0.0;
-    for (long i = 0; i < n; ++i) {
-      double s = v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2];
-      if (s > vmax2) vmax2 = s;
-    }
-    double vmax = sqrt(vmax2);
-    if (vmax * dt > dmax) dtx = dmax / vmax;
+/* The step length a move x += c dt v may use.  Without dmax it is dt.  With
+ * dmax (the maximum atomic displacement per step the paper's melt case
+ * needed, Sec. 5.3; the paper names the setting but not its mechanism) it is
+ * shortened so that the fastest atom moves at most dmax per full step:
+ * min(dt, dmax / max_i |v_i|), with v the velocity of that move.  It applies
+ * to the drift and to the half step back (half of such a step); dt itself,
+ * the FIRE state and the kicks are unchanged. */
+static double capped_step(long n, const double *v, double dt, double dmax) {
+  if (!(dmax > 0.0)) return dt;
+  double vmax2 = 0.0;
+  for (long i = 0; i < n; ++i) {
+    double s = v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2];
+    if (s > vmax2) vmax2 = s;
   }
+  double vmax = sqrt(vmax2);
+  return vmax * dt > dmax ? dmax / vmax : dt;
+}
+
+static void drift(long n, double *pos, const double *v, double dt, double dmax) {
+  double dtx = capped_step(n, v, dt, dmax);
   for (long k = 0; k < 3 * n; ++k) pos[k] += dtx * v[k];
 }
 
@@ -776,8 +779,10 @@ int oracle_fire_minimize_ex(long n, double *pos, const or_box *b, const or_pot *
           if (dt * fp->dtshrink >= dtmin) dt *= fp->dtshrink;
           alpha = fp->alpha0;
         }
-        if (fp->halfstepback)
-          for (long k = 0; k < 3 * n; ++k) pos[k] -= 0.5 * dt * v[k];
+        if (fp->halfstepback) {
+          double dth = capped_step(n, v, dt, fp->dmax);
+          for (long k = 0; k < 3 * n; ++k) pos[k] -= 0.5 * dth * v[k];
+        }
         memset(v, 0, sizeof(double) * 3 * n);
       }
     } else {

@@ -57,7 +57,7 @@ class fire_params(ctypes.Structure):
         ("delaystep", ctypes.c_int), ("vdfmax", ctypes.c_int), ("halfstepback", ctypes.c_int),
         ("initialdelay", ctypes.c_int), ("integrator", ctypes.c_int), ("criterion", ctypes.c_int),
         ("variant", ctypes.c_int), ("precision", ctypes.c_int),
-        ("mixed_switch", ctypes.c_double), ("skin", ctypes.c_double),
+        ("mixed_switch", ctypes.c_double), ("skin", ctypes.c_double), ("dmax", ctypes.c_double),
     ]
 
 

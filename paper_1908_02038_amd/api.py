@@ -64,7 +64,7 @@ def make_params(fire: dict | None = None, **over) -> L.fire_params:
     d = dict(fire or {})
     d.update(over)
     for k in ("dt_start", "tmax", "tmin", "dtgrow", "dtshrink", "alpha0", "alphashrink", "f2a",
-              "mixed_switch", "skin"):
+              "mixed_switch", "skin", "dmax"):
         if k in d:
             setattr(p, k, float(d[k]))
     for k in ("delaystep", "vdfmax", "halfstepback", "initialdelay"):

@@ -803,9 +803,12 @@ __device__ __forceinline__ UpdCoef load_coef(const Ctrl* __restrict__ c) {
 // update kernel, and the passes that apply the update while staging their
 // halo -- runs this same arithmetic, so an atom gets the same bits wherever it
 // is updated.
-__device__ __forceinline__ void fire_step(const UpdCoef& u, double (&x)[3], double (&v)[3], const double (&f)[3],
-                                          double s) {
-  const double k1 = u.k1 * s, k2 = u.k2 * s;
+// fire_vel: everything before the drift (half step back and zeroing on
+// P <= 0, kick, mixing); fire_drift: the drift with step dtx and the explicit
+// Euler kick after it.  fire_step = both with dtx = dt.
+__device__ __forceinline__ void fire_vel(const UpdCoef& u, double (&x)[3], double (&v)[3], const double (&f)[3],
+                                         double s) {
+  const double k1 = u.k1 * s;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double vd = v[d], xd = x[d];
@@ -816,11 +819,23 @@ __device__ __forceinline__ void fire_step(const UpdCoef& u, double (&x)[3], doub
     if (u.mix_first) vd = u.cv * vd + u.cf * f[d];
     vd = vd + k1 * f[d];
     if (!u.mix_first) vd = u.cv * vd + u.cf * f[d];
-    xd = xd + u.dtx * vd;
-    vd = vd + k2 * f[d];
     v[d] = vd;
     x[d] = xd;
   }
+}
+__device__ __forceinline__ void fire_drift(const UpdCoef& u, double dtx, double (&x)[3], double (&v)[3],
+                                           const double (&f)[3], double s) {
+  const double k2 = u.k2 * s;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    x[d] = x[d] + dtx * v[d];
+    v[d] = v[d] + k2 * f[d];
+  }
+}
+__device__ __forceinline__ void fire_step(const UpdCoef& u, double (&x)[3], double (&v)[3], const double (&f)[3],
+                                          double s) {
+  fire_vel(u, x, v, f, s);
+  fire_drift(u, u.dtx, x, v, f, s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, double* __restrict__ vel,
@@ -850,6 +865,83 @@ __global__ __launch_bounds__(kBlock) void k_update(double4* __restrict__ pos, do
   vel[ncap + i] = v[1];
   vel[2 * ncap + i] = v[2];
   for (int k = 0; k < gc; ++k) {  // periodic images move along
+    const int g = glist[8 * i + k], code = gcode[g - n];
+    pos[g] = make_double4(x[0] + ghost_shift(code, 0, box), x[1] + ghost_shift(code, 1, box),
+                          x[2] + ghost_shift(code, 2, box), p.w);
+  }
+  const double ex = x[0] - r.x, ey = x[1] - r.y, ez = x[2] - r.z;
+  if (ex * ex + ey * ey + ez * ez > ctrl->skin_half2) atomicOr(&ctrl->viol, 1);
+}
+
+// The update with a displacement cap (dmax > 0) in two launches: k_update_vel
+// applies everything before the drift and reduces max_i |v_i|^2; its last
+// block sets the drift step dtx = min(dt, dmax / max|v|).  k_update_drift then
+// moves the atoms (and their periodic images) by dtx v and tests the skin.
+__global__ __launch_bounds__(kBlock) void k_update_vel(double4* __restrict__ pos, double* __restrict__ vel,
+                                                       const double* __restrict__ frc, int n, int ncap,
+                                                       double* __restrict__ part, Ctrl* __restrict__ ctrl,
+                                                       Props pr) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * blockDim.x + threadIdx.x;
+  if (!ctrl_running(ctrl)) return;  // uniform: the status does not change during this kernel
+  const UpdCoef u = load_coef(ctrl);
+  double r[1] = {0.0};
+  if (i < n) {
+    const double4 p = pos[i];
+    double x[3] = {p.x, p.y, p.z};
+    double v[3] = {vel[i], vel[ncap + i], vel[2 * ncap + i]};
+    const double f[3] = {frc[i], frc[ncap + i], frc[2 * ncap + i]};
+    fire_vel(u, x, v, f, pr.sinv ? pr.sinv[i] : 1.0);
+    pos[i] = make_double4(x[0], x[1], x[2], p.w);
+    vel[i] = v[0];
+    vel[ncap + i] = v[1];
+    vel[2 * ncap + i] = v[2];
+    r[0] = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  }
+  block_reduce<0, 1>(r);
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(part + (size_t)kRed * b, r[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    const unsigned int t = __hip_atomic_fetch_add(&ctrl->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  double q[1] = {0.0};
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x)
+    q[0] = fmax(q[0], __hip_atomic_load(part + (size_t)kRed * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  block_reduce<0, 1>(q);
+  if (threadIdx.x == 0) {
+    ctrl->ticket = 0;
+    const double vmax = sqrt(q[0]), dt = u.dtx;
+    ctrl->dtx = vmax * dt > ctrl->dmax ? ctrl->dmax / vmax : dt;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_drift(double4* __restrict__ pos, double* __restrict__ vel,
+                                                         const double* __restrict__ frc,
+                                                         const double4* __restrict__ xref,
+                                                         const int* __restrict__ gcnt, const int* __restrict__ glist,
+                                                         const int* __restrict__ gcode, BoxDev box, int n, int ncap,
+                                                         Ctrl* __restrict__ ctrl, Props pr) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = pos[i];
+  double v[3] = {vel[i], vel[ncap + i], vel[2 * ncap + i]};
+  const double f[3] = {frc[i], frc[ncap + i], frc[2 * ncap + i]};
+  const double4 r = xref[i];
+  const int gc = gcnt[i];
+  const double sc = pr.sinv ? pr.sinv[i] : 1.0;
+  if (!ctrl_running(ctrl)) return;
+  const UpdCoef u = load_coef(ctrl);
+  double x[3] = {p.x, p.y, p.z};
+  fire_drift(u, u.dtx, x, v, f, sc);
+  pos[i] = make_double4(x[0], x[1], x[2], p.w);
+  vel[i] = v[0];
+  vel[ncap + i] = v[1];
+  vel[2 * ncap + i] = v[2];
+  for (int k = 0; k < gc; ++k) {
     const int g = glist[8 * i + k], code = gcode[g - n];
     pos[g] = make_double4(x[0] + ghost_shift(code, 0, box), x[1] + ghost_shift(code, 1, box),
                           x[2] + ghost_shift(code, 2, box), p.w);
@@ -2433,7 +2525,8 @@ void launch_forces(fire_ctx* ctx, hipStream_t s, int prec, bool with_e = true) {
 // pair potentials, and no velocity-Verlet half kick in the force epilogue
 // (that kick would have to be undone when a rebuild discards the pass).
 bool fold_update(const fire_ctx* ctx) {
-  return ctx->use_lds && ctx->pot.kind != FIRE_POT_HARMONIC && ctx->params.integrator != FIRE_INT_VERLET;
+  return ctx->use_lds && ctx->pot.kind != FIRE_POT_HARMONIC && ctx->params.integrator != FIRE_INT_VERLET &&
+         !(ctx->params.dmax > 0);
 }
 
 // Primary state set current and its periodic images consistent (see
@@ -2447,6 +2540,14 @@ void materialize(fire_ctx* ctx, hipStream_t s) {
 }
 
 void launch_update(fire_ctx* ctx, hipStream_t s) {
+  if (ctx->params.dmax > 0) {  // the drift step depends on every atom's new velocity
+    hipLaunchKernelGGL(k_update_vel, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->vel, ctx->frc,
+                       ctx->n, ctx->ncap, ctx->part, ctx->ctrl, props_of(ctx));
+    hipLaunchKernelGGL(k_update_drift, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->vel, ctx->frc,
+                       ctx->xref, ctx->gcnt, ctx->glist, ctx->gcode, ctx->box, ctx->n, ctx->ncap, ctx->ctrl,
+                       props_of(ctx));
+    return;
+  }
   hipLaunchKernelGGL(k_update, dim3(nblocks(ctx->n)), dim3(kBlock), 0, s, ctx->pos, ctx->vel, ctx->frc, ctx->xref,
                      ctx->gcnt, ctx->glist, ctx->gcode, ctx->box, ctx->n, ctx->ncap, ctx->ctrl, props_of(ctx));
 }
@@ -2614,6 +2715,7 @@ void ctrl_defaults(fire_ctx* ctx, Ctrl& c, double tol, long long max_steps, int 
   c.tol = tol;
   c.switch_tol = p.mixed_switch > 0 ? p.mixed_switch : 100.0 * tol;
   c.skin_half2 = ctx->pot.kind == FIRE_POT_HARMONIC ? 1e300 : 0.25 * ctx->skin * ctx->skin;
+  c.dmax = p.dmax;
   c.eval_only = eval_only;
   c.max_steps = max_steps;
   c.delaystep = p.delaystep;
@@ -2773,6 +2875,7 @@ int validate_params(const fire_params* p) {
   if (p->integrator < 0 || p->integrator > 2 || p->criterion < 0 || p->criterion > 1 || p->variant < 0 ||
       p->variant > 1 || p->precision < 0 || p->precision > 2)
     return FIRE_E_ARG;
+  if (!(p->dmax >= 0) || !std::isfinite(p->dmax)) return FIRE_E_ARG;
   return FIRE_OK;
 }
 
@@ -2875,6 +2978,7 @@ void fire_params_default(fire_params* p) {
   p->precision = FIRE_FP64;
   p->mixed_switch = 0.0;
   p->skin = 0.0;
+  p->dmax = 0.0;
 }
 
 const char* fire_stop_name(int r) {
@@ -3265,10 +3369,19 @@ int fire_repeat_forces_dev(fire_ctx* ctx, int reps, void* stream) {
   return FIRE_OK;
 }
 
+// The batched form has no displacement cap.
+static int batched_no_dmax(fire_ctx* ctx, int nsys, const fire_params* per_sys) {
+  bool any = ctx->params.dmax > 0;
+  for (int s = 0; per_sys && s < nsys && !any; ++s) any = per_sys[s].dmax > 0;
+  return any ? set_err(ctx, FIRE_E_ARG, "batched: dmax is not available") : FIRE_OK;
+}
+
 int fire_minimize_batched(fire_ctx* ctx, int nsys, const long long* offsets, double* pos, const fire_box* boxes,
                           const fire_potential* pot, const fire_params* per_sys, double tol, long long max_steps,
                           fire_result* out) {
   int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = batched_no_dmax(ctx, nsys, per_sys);
   if (rc) return rc;
   return fire_batched_run(ctx, nsys, offsets, pos, true, boxes, pot, per_sys, tol, max_steps, out, ctx->stream);
 }
@@ -3277,6 +3390,8 @@ int fire_minimize_batched_dev(fire_ctx* ctx, int nsys, const long long* offsets,
                               const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
                               double tol, long long max_steps, fire_result* out, void* stream) {
   int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = batched_no_dmax(ctx, nsys, per_sys);
   if (rc) return rc;
   return fire_batched_run(ctx, nsys, offsets, d_pos, false, boxes, pot, per_sys, tol, max_steps, out,
                           pick_stream(ctx, stream));

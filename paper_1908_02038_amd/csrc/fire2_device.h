@@ -157,7 +157,10 @@ __device__ inline void fire_control(Ctrl* __restrict__ c, const double (&r)[kCtl
   c->P_used = P;
   c->neg = neg;
   c->mix_first = mix_first;
-  c->hsb = (neg && c->variant == FIRE_VARIANT_FIRE2 && c->halfstepback) ? 0.5 * dt : 0.0;
+  // the half step back undoes half of a step; with a displacement cap that
+  // step is min(dt, dmax / max_i |v_i|) of the velocity being undone
+  const double dth = (c->dmax > 0.0 && vm * dt > c->dmax) ? c->dmax / vm : dt;
+  c->hsb = (neg && c->variant == FIRE_VARIANT_FIRE2 && c->halfstepback) ? 0.5 * dth : 0.0;
   c->kick1 = k1;
   c->kick2 = k2;
   c->kick3 = k3;

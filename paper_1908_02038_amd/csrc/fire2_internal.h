@@ -57,7 +57,7 @@ struct Ctrl {
   int pad0;
   // parameters
   double dt_start, dtmax, dtmin, dtgrow, dtshrink, alpha0, alphashrink, f2a;
-  double tol, switch_tol, skin_half2;
+  double tol, switch_tol, skin_half2, dmax;
   long long max_steps, trace_cap, iter_low;
   int delaystep, vdfmax, halfstepback, initialdelay;
   int integrator, criterion, variant, mode;

@@ -1,0 +1,151 @@
+"""GPU parity of the displacement cap dmax (the melt case of Sec. 5.3) against
+the oracle: first steps and relaxations with the cap binding, every drift
+bounded, a cap above every step giving the uncapped run's bits, and the
+batched form refusing it."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_02038_amd import inputs
+from systems import min_image_diff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1908_02038_amd import api as a
+    return a
+
+
+def hot_lj():
+    """A strongly disordered LJ start (noise 0.2 sigma): large first forces."""
+    return inputs.lj_box(5, nvac=5, noise=0.2, seed=71, rc=2.0)  # 495 atoms
+
+
+def hot_gupta():
+    return inputs.gupta_box(4, nvac=3, noise=0.3, seed=72)
+
+
+SYSTEMS = {"lj": (hot_lj, 0.01, 0.01), "gupta": (hot_gupta, 0.002, 0.002)}  # system, dt_start, dmax
+
+
+@pytest.mark.parametrize("integrator", ["eulerimplicit", "eulerexplicit", "verlet"])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_dmax_first_steps_match_oracle(api, name, integrator):
+    make, dt, dmax = SYSTEMS[name]
+    s = make()
+    fire = dict(s.fire, dt_start=dt, dmax=dmax, integrator=integrator)
+    c = api.Context(0, fire)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 20, trace=True)
+    c.close()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 0.0, 20, trace=True)
+    assert np.abs(min_image_diff(r["pos"], ref["pos"], s.box)).max() <= 1e-12
+    np.testing.assert_array_equal(r["trace"][:, 7], ref["trace"][:, 7])
+    np.testing.assert_allclose(r["trace"][:, 1], ref["trace"][:, 1], rtol=1e-12)
+    # the cap binds from the start (uncapped, these hot starts soon blow up)
+    free = oracle.fire_minimize(s.pos, s.box, s.potential, dict(fire, dmax=0.0), 0.0, 2)
+    capped = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 0.0, 2)
+    assert np.abs(min_image_diff(free["pos"], capped["pos"], s.box)).max() > 1e-6
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_dmax_relaxation_matches_oracle(api, name):
+    make, dt, dmax = SYSTEMS[name]
+    s = make()
+    fire = dict(s.fire, dt_start=dt, dmax=dmax)
+    c = api.Context(0, fire)
+    r = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000, trace=True)
+    c.close()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, fire, s.tol, 50000, trace=True)
+    m = min(len(r["trace"]), len(ref["trace"]))
+    diff = np.nonzero(r["trace"][:m, 7] != ref["trace"][:m, 7])[0]
+    first = int(diff[0]) if len(diff) else None
+    print(f"{name}: gpu {r['stop']} {r['iterations']} it, oracle {ref['stop']} {ref['iterations']} it, "
+          f"first branch difference {first}")
+    assert r["stop"] == ref["stop"] == "converged"
+    n = len(s.pos)
+    if first is None and r["iterations"] == ref["iterations"]:
+        assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
+    else:
+        assert first is not None and first >= 50
+    e_x, f_x = oracle.energy_forces(r["pos"], s.box, s.potential)
+    assert abs(e_x - r["energy"]) <= 1e-12 * abs(e_x)
+    assert np.linalg.norm(f_x, axis=1).max() < s.tol * (1 + 1e-6)
+
+
+def test_every_drift_is_bounded(api):
+    """Without the half step back only the drift moves atoms: between
+    consecutive iterations no atom moves more than dmax, and it binds."""
+    s = hot_lj()
+    dmax = 0.01
+    fire = dict(s.fire, dt_start=0.01, dmax=dmax, halfstepback=0)
+    c = api.Context(0, fire)
+    prev, hit = s.pos, 0
+    for k in range(1, 13):
+        r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, k)
+        step = np.linalg.norm(min_image_diff(r["pos"], prev, s.box), axis=1).max()
+        assert step <= dmax * (1 + 1e-12)
+        hit += step > dmax * (1 - 1e-12)
+        prev = r["pos"]
+    c.close()
+    assert hit >= 3
+
+
+@pytest.mark.parametrize("name", ["lj_6", "gupta_5"])
+def test_a_cap_above_every_step_gives_the_uncapped_bits(api, name):
+    """dmax far above any step: the two-launch capped update (then the plain
+    force passes) gives the same bits as the loop with the update folded into
+    the first pass."""
+    from systems import SMALL
+    s = SMALL[name]()
+    c = api.Context(0, s.fire)
+    a = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000)
+    c.close()
+    c = api.Context(0, dict(s.fire, dmax=1e6))
+    b = c.fire_minimize(s.pos, s.box, s.potential, s.tol, 50000)
+    c.close()
+    assert a["iterations"] == b["iterations"]
+    np.testing.assert_array_equal(a["pos"], b["pos"])
+
+
+def test_dmax_with_masses_and_frozen_atoms(api):
+    s = hot_lj()
+    fire = dict(s.fire, dt_start=0.01, dmax=0.01)
+    frozen = np.zeros(len(s.pos), np.uint8)
+    frozen[::4] = 7
+    mass = inputs.random_masses(len(s.pos), 73)
+    c = api.Context(0, fire)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 20, frozen=frozen, mass=mass)
+    c.close()
+    ref = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 0.0, 20, frozen=frozen, mass=mass)
+    assert np.abs(min_image_diff(r["pos"], ref["pos"], s.box)).max() <= 1e-12
+    np.testing.assert_array_equal(r["pos"][::4], s.pos[::4])
+
+
+def test_batched_refuses_dmax(api):
+    s = inputs.gupta_box(3, nvac=1, noise=0.05, seed=74)
+    c = api.Context(0, dict(s.fire, dmax=0.01))
+    with pytest.raises(api.FireError) as e:
+        c.fire_minimize_batched([(s.pos, s.box)] * 2, s.potential, 1e-6, 100)
+    assert e.value.name == "FIRE_E_ARG"
+    c.close()
+    c = api.Context(0, s.fire)
+    with pytest.raises(api.FireError):
+        c.fire_minimize_batched([(s.pos, s.box)] * 2, s.potential, 1e-6, 100,
+                                per_sys=[s.fire, dict(s.fire, dmax=0.01)])
+    c.close()
+
+
+def test_capped_half_step_back_closed_form(api):
+    """1-D well k = 1, x0 = 1, dt = 1.2, dmax = 1.3: the first drift is capped
+    (x1 = -0.3); at i = 2 (P < 0) the half step back undoes half of a capped
+    step (+0.65), then the kick with F(x1) and an uncapped drift: x2 = 0.782."""
+    box = inputs.Box((-1e3,) * 3, (2e3,) * 3, (0, 0, 0))
+    fire = inputs.fire_params(1.2, 1.0, tmax=10.0, alpha0=0.1, delaystep=5, dtgrow=1.1, dtshrink=0.5, dmax=1.3)
+    c = api.Context(0, fire)
+    r = c.fire_minimize(np.array([[1.0, 0.0, 0.0]]), box, inputs.harmonic_potential((1.0, 0.0, 0.0)), 0.0, 2,
+                        trace=True)
+    c.close()
+    assert r["trace"][2, 7] == -1
+    assert r["pos"][0, 0] == pytest.approx(-0.3 + 0.65 + 1.2 * 1.2 * 0.3, rel=1e-14)

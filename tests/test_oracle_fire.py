@@ -251,7 +251,8 @@ def test_frozen_components_never_move_and_the_rest_relaxes():
 
 
 # ---- dmax: the largest displacement of any atom in one step (the melt case
-# of Sec. 5.3); the drift is shortened to dt_x = min(dt, dmax / max_i |v_i|)
+# of Sec. 5.3); the drift, and the half step back, use the step
+# min(dt, dmax / max_i |v_i|) of the velocity they move the atoms with
 
 def test_dmax_above_every_step_changes_nothing():
     s = inputs.lj_box(3, nvac=1, noise=0.08, seed=64, rc=2.0)
@@ -297,3 +298,27 @@ def test_dmax_bounds_every_drift_and_binds(integrator):
     # and the capped run still relaxes
     r = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 1e-6, 50000)
     assert r["stop"] == "converged"
+
+
+def test_dmax_caps_the_half_step_back():
+    """1-D well k = 1, x0 = 1, dt = 1.2, dmax = 1.3 (f2a = 1, no dt change
+    inside the delay).  i = 1: v = -1.2 and the drift is capped to dmax:
+    x1 = -0.3.  i = 2: P = F v < 0, so the half step back undoes half of a
+    capped step, dt_h = dmax / |v| = 1.3 / 1.2, moving the atom by +0.65
+    (uncapped: +0.72); then v = 0, the kick with F(x1) = 0.3 gives v = 0.36,
+    and the drift (not binding) adds 0.432: x2 = 0.782."""
+    r1 = run([1.0, 0, 0], (1.0, 0, 0), 1, dt_start=1.2, dmax=1.3)
+    assert r1["pos"][0, 0] == pytest.approx(-0.3, rel=1e-14)
+    r2 = run([1.0, 0, 0], (1.0, 0, 0), 2, dt_start=1.2, dmax=1.3)
+    assert r2["trace"][2, 7] == -1
+    assert r2["pos"][0, 0] == pytest.approx(-0.3 + 0.65 + 1.2 * 1.2 * 0.3, rel=1e-14)
+
+
+def test_dmax_keeps_a_hot_start_finite():
+    """A strongly disordered LJ start with restarts (P <= 0 steps, each with
+    its half step back) stays finite and lowers E under the cap."""
+    s = inputs.lj_box(3, nvac=2, noise=0.2, seed=66, rc=2.0)
+    fire = dict(s.fire, dmax=0.01, dt_start=0.01)
+    r = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 0.0, 400, trace=True)
+    assert (r["trace"][1:, 7] == -1).sum() > 1
+    assert np.isfinite(r["pos"]).all() and r["energy"] < oracle.energy_forces(s.pos, s.box, s.potential)[0]
