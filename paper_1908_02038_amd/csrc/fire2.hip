@@ -1536,12 +1536,27 @@ __device__ __forceinline__ void for_neighbour_index(const int* __restrict__ nbr,
 //
 // Two passes per evaluation.  k_sw_short compacts each real atom's in-range
 // neighbours (r < a sigma) from the skin list into a short list of 64-byte
-// records {x_j - x_i, 1/r ; g(r), g'(r), slot j} and sums the atom's pair
-// terms.  k_sw_force then gathers every three-body term that contains x_i:
+// records {x_j - x_i, 1/r ; g(r), g'(r), real atom of j} and sums the atom's
+// pair terms.  k_sw_force then gathers every three-body term that contains x_i:
 // the triplets centred at i, from i's own list, and the triplets centred at
 // each neighbour m with i as one end, from m's list (a periodic image reads
 // its source's list: relative vectors are the same).  No atomics: every
 // atom sums its own force in a fixed order.
+
+// (s/r)^p: integer exponents up to 16 by repeated squaring (the published Si
+// set has p = 4, q = 0), others through pow.
+__device__ __forceinline__ double sw_pow(double x, double p) {
+  const int k = (int)p;
+  if ((double)k == p && k >= 0 && k <= 16) {
+    double r = 1.0, b = x;
+    for (int m = k; m; m >>= 1) {
+      if (m & 1) r *= b;
+      b *= b;
+    }
+    return r;
+  }
+  return pow(x, p);
+}
 
 __device__ __forceinline__ void sw_record(double4* __restrict__ rec, double dx, double dy, double dz, double ir,
                                           double g, double g1, int j) {
@@ -1549,39 +1564,75 @@ __device__ __forceinline__ void sw_record(double4* __restrict__ rec, double dx, 
   rec[1] = make_double4(g, g1, (double)j, 0.0);
 }
 
+// G lanes per atom: lane g takes candidates g, g + G, ...; a wave ballot
+// gives each in-range candidate its record slot in list order of the rounds
+// (a wave's groups are atoms of one list wave, so every lane runs the same
+// number of rounds).  The group's partial pair sums are combined by a fixed
+// butterfly.
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_sw_short(const double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                     const int* __restrict__ wcnt, int n, int kcap, PotDev pot,
+                                                     const int* __restrict__ wcnt, const int* __restrict__ real_of,
+                                                     int n, int kcap, PotDev pot,
                                                      double4* __restrict__ sw_nb, int* __restrict__ sw_cnt,
                                                      double4* __restrict__ sw_fe, Ctrl* __restrict__ ctrl) {
+  static_assert(G > 0 && 64 % G == 0, "a group must divide the wave");
   if (!pass_gate(ctrl)) return;
-  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double4 pi = pos[i];
+  constexpr int kAtoms = kBlock / G;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * kAtoms + (int)threadIdx.x / G, g = threadIdx.x % G;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long group = ((1ull << G) - 1) << (lane & ~(G - 1));
+  const bool valid = i < n;
+  const int w = i >> 6, l = i & 63;
+  const int kw = wcnt[w];
+  const double4 pi = pos[valid ? i : 0];
   double4* rec = sw_nb + 2 * (size_t)i * kcap;
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
   int c = 0;
-  for_neighbour_index(nbr, wcnt, kcap, i, [&](int j) {
-    const double4 pj = pos[j];
-    const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < pot.rc2)) return;
-    const double r = sqrt(r2), ir = 1.0 / r, t = 1.0 / (r - pot.sw_as);
-    const double g = exp(pot.sw_gs * t), g1 = -pot.sw_gs * t * t * g;
-    // pair term and its derivative along r
-    const double sr = pot.sw_s * ir;
-    const double bp = pot.sw_B * pow(sr, pot.sw_p), bq = pow(sr, pot.sw_q);
-    const double poly = bp - bq, dpoly = (-pot.sw_p * bp + pot.sw_q * bq) * ir;
-    const double ex = exp(pot.sw_s * t), dex = -pot.sw_s * t * t * ex;
-    const double f1 = pot.sw_Aeps * (dpoly * ex + poly * dex);
-    e += 0.5 * pot.sw_Aeps * poly * ex;
-    fx += f1 * dx * ir;
-    fy += f1 * dy * ir;
-    fz += f1 * dz * ir;
-    sw_record(rec + 2 * c, dx, dy, dz, ir, g, g1, j);
-    ++c;
-  });
-  sw_cnt[i] = c;
-  sw_fe[i] = make_double4(fx, fy, fz, e);
+  for (int k0 = 0; k0 < kw; k0 += G) {
+    const int k = k0 + g;
+    bool in = false;
+    int j = 0, rj = 0;
+    double dx = 0.0, dy = 0.0, dz = 0.0, r2 = 0.0;
+    if (valid && k < kw) {
+      j = nbr[lidx(w, k, l, kcap)];
+      const double4 pj = pos[j];
+      rj = real_of[j];  // gathered beside the position; the force pass needs the real atom only
+      dx = pj.x - pi.x;
+      dy = pj.y - pi.y;
+      dz = pj.z - pi.z;
+      r2 = dx * dx + dy * dy + dz * dz;
+      in = r2 < pot.rc2;
+    }
+    const unsigned long long mine = __ballot(in) & group;
+    if (in) {
+      const double r = sqrt(r2), ir = 1.0 / r, t = 1.0 / (r - pot.sw_as);
+      const double gg = exp(pot.sw_gs * t), g1 = -pot.sw_gs * t * t * gg;
+      // pair term and its derivative along r
+      const double sr = pot.sw_s * ir;
+      const double bp = pot.sw_B * sw_pow(sr, pot.sw_p), bq = sw_pow(sr, pot.sw_q);
+      const double poly = bp - bq, dpoly = (-pot.sw_p * bp + pot.sw_q * bq) * ir;
+      const double ex = exp(pot.sw_s * t), dex = -pot.sw_s * t * t * ex;
+      const double f1 = pot.sw_Aeps * (dpoly * ex + poly * dex);
+      e += 0.5 * pot.sw_Aeps * poly * ex;
+      fx += f1 * dx * ir;
+      fy += f1 * dy * ir;
+      fz += f1 * dz * ir;
+      sw_record(rec + 2 * (c + __popcll(mine & ((1ull << lane) - 1))), dx, dy, dz, ir, gg, g1, rj);
+    }
+    c += __popcll(mine);
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    fx += __shfl_xor(fx, o, 64);
+    fy += __shfl_xor(fy, o, 64);
+    fz += __shfl_xor(fz, o, 64);
+    e += __shfl_xor(e, o, 64);
+  }
+  if (valid && g == 0) {
+    sw_cnt[i] = c;
+    sw_fe[i] = make_double4(fx, fy, fz, e);
+  }
 }
 
 // Gradient of the triplet term (centre c, ends a, b) with respect to the
@@ -1610,48 +1661,96 @@ __device__ __forceinline__ double sw_triplet(const PotDev& pot, const double (&u
   return pot.sw_leps * t * t * gu * gw;
 }
 
+// G lanes per atom: lane g takes the atom's short-list entries a = g, g + G, ...
+// (the triplets centred at i with a as the first end, and those centred at
+// neighbour a with i as an end); the group's sums are combined by a fixed
+// butterfly and the first lane runs the epilogue.
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_sw_force(const double4* __restrict__ sw_nb, const int* __restrict__ sw_cnt,
-                                                     const double4* __restrict__ sw_fe,
-                                                     const int* __restrict__ real_of, int n, int kcap, int ncap,
+                                                     const double4* __restrict__ sw_fe, int n, int kcap, int ncap,
                                                      PotDev pot, double* __restrict__ frc, double* __restrict__ vel,
                                                      double* __restrict__ part, Ctrl* __restrict__ ctrl,
                                                      double* __restrict__ trace, Props pr) {
+  static_assert(G > 0 && 64 % G == 0, "a group must divide the wave");
   if (!pass_gate(ctrl)) return;
+  constexpr int kAtoms = kBlock / G;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * blockDim.x + threadIdx.x;
+  const int i = b * kAtoms + (int)threadIdx.x / G, g = threadIdx.x % G;
   const bool valid = i < n;
   double f[3] = {0, 0, 0}, e = 0.0;
   if (valid) {
-    const double4 fe = sw_fe[i];
-    f[0] = fe.x;
-    f[1] = fe.y;
-    f[2] = fe.z;
-    e = fe.w;
+    // Records are read in batches of kB, issued together: a batch of a
+    // neighbour's list is loaded beside its count (bounded by the list
+    // capacity, not the count), so each lane waits for two round trips, not
+    // one per record.  Only the arithmetic is limited to the live entries.
+    constexpr int kB = 4;
     const int ci = sw_cnt[i];
     const double4* li = sw_nb + 2 * (size_t)i * kcap;
-    for (int a = 0; a < ci; ++a) {
+    for (int a = g; a < ci; a += G) {
       const double4 ra = li[2 * a], sa = li[2 * a + 1];
       const double u[3] = {ra.x, ra.y, ra.z};
-      // triplets centred at i: (a, c) with c > a
-      for (int c = a + 1; c < ci; ++c) {
-        const double4 rc = li[2 * c], sc = li[2 * c + 1];
-        const double w[3] = {rc.x, rc.y, rc.z};
-        e += sw_triplet<true>(pot, u, ra.w, sa.x, sa.y, w, rc.w, sc.x, sc.y, f);
-      }
-      // triplets centred at m = neighbour a, with i as one end
-      const int m = real_of[(int)sa.z];
-      const int cm = sw_cnt[m];
+      const int m = (int)sa.z;  // neighbour a's real atom (a periodic image reads its source's list)
       const double4* lm = sw_nb + 2 * (size_t)m * kcap;
       const double v[3] = {-ra.x, -ra.y, -ra.z};  // x_i - x_m
-      for (int k = 0; k < cm; ++k) {
-        const double4 rk = lm[2 * k], sk = lm[2 * k + 1];
-        if (real_of[(int)sk.z] == i) continue;
-        const double w[3] = {rk.x, rk.y, rk.z};
-        sw_triplet<false>(pot, v, ra.w, sa.x, sa.y, w, rk.w, sk.x, sk.y, f);
+      double4 rk[kB], sk[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q)
+        if (q < kcap) {
+          rk[q] = lm[2 * q];
+          sk[q] = lm[2 * q + 1];
+        }
+      const int cm = sw_cnt[m];
+      // triplets centred at i: (a, c) with c > a
+      for (int c0 = a + 1; c0 < ci; c0 += kB) {
+        double4 rc[kB], sc[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+          if (c0 + q < ci) {
+            rc[q] = li[2 * (c0 + q)];
+            sc[q] = li[2 * (c0 + q) + 1];
+          }
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+          if (c0 + q < ci) {
+            const double w[3] = {rc[q].x, rc[q].y, rc[q].z};
+            e += sw_triplet<true>(pot, u, ra.w, sa.x, sa.y, w, rc[q].w, sc[q].x, sc[q].y, f);
+          }
+      }
+      // triplets centred at m with i as one end
+      for (int k0 = 0; k0 < cm; k0 += kB) {
+        if (k0 > 0) {
+#pragma unroll
+          for (int q = 0; q < kB; ++q)
+            if (k0 + q < cm) {
+              rk[q] = lm[2 * (k0 + q)];
+              sk[q] = lm[2 * (k0 + q) + 1];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+          if (k0 + q < cm && (int)sk[q].z != i) {
+            const double w[3] = {rk[q].x, rk[q].y, rk[q].z};
+            sw_triplet<false>(pot, v, ra.w, sa.x, sa.y, w, rk[q].w, sk[q].x, sk[q].y, f);
+          }
       }
     }
   }
-  force_epilogue(i, valid, f[0], f[1], f[2], e, frc, vel, ncap, part, nullptr, b, ctrl, trace, pr);
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    f[0] += __shfl_xor(f[0], o, 64);
+    f[1] += __shfl_xor(f[1], o, 64);
+    f[2] += __shfl_xor(f[2], o, 64);
+    e += __shfl_xor(e, o, 64);
+  }
+  const bool lead = valid && g == 0;
+  if (lead) {
+    const double4 fe = sw_fe[i];
+    f[0] += fe.x;
+    f[1] += fe.y;
+    f[2] += fe.z;
+    e += fe.w;
+  }
+  force_epilogue(i, lead, f[0], f[1], f[2], e, frc, vel, ncap, part, nullptr, b, ctrl, trace, pr);
 }
 
 // ------------------------------------------------------- Hessian * u (FP64)
@@ -2023,7 +2122,7 @@ int ensure_atoms(fire_ctx* ctx, int n) {
   HIPCHK(dalloc(&ctx->wcnt, cap / 64));
   HIPCHK(dalloc(&ctx->tile_h, nb));
   HIPCHK(dalloc(&ctx->stage, 3 * (size_t)cap));
-  HIPCHK(dalloc(&ctx->part, (size_t)kRed * nb));
+  HIPCHK(dalloc(&ctx->part, (size_t)kRed * (cap / kPartAtoms)));
   HIPCHK(dalloc(&ctx->part_emb, nb));
   HIPCHK(dalloc(&ctx->bbox_part, 6 * (size_t)nb));
   HIPCHK(hipMemset(ctx->wcnt, 0, sizeof(int) * (cap / 64)));
@@ -2484,13 +2583,19 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
   }
 }
 
+// Lanes per atom of the two Stillinger-Weber passes (the force pass's grid,
+// n / (kBlock / kSwForceLanes) blocks, must fit the partial records).
+constexpr int kSwShortLanes = 8, kSwForceLanes = 4;
+static_assert(kBlock / kSwForceLanes >= kPartAtoms, "partial records are sized for this grid");
+
 void launch_sw(fire_ctx* ctx, hipStream_t s) {
-  const int n = ctx->n, nb = nblocks(n);
-  hipLaunchKernelGGL(k_sw_short, dim3(nb), dim3(kBlock), 0, s, ctx->pos, ctx->nbr, ctx->wcnt, n, ctx->kcap, ctx->pot,
-                     ctx->sw_nb, ctx->sw_cnt, ctx->sw_fe, ctx->ctrl);
-  hipLaunchKernelGGL(k_sw_force, dim3(nb), dim3(kBlock), 0, s, ctx->sw_nb, ctx->sw_cnt, ctx->sw_fe, ctx->real_of, n,
-                     ctx->kcap, ctx->ncap, ctx->pot, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace,
-                     props_of(ctx));
+  const int n = ctx->n;
+  hipLaunchKernelGGL(k_sw_short<kSwShortLanes>, dim3(nblocks(n, kBlock / kSwShortLanes)), dim3(kBlock), 0, s,
+                     ctx->pos, ctx->nbr, ctx->wcnt, ctx->real_of, n, ctx->kcap, ctx->pot, ctx->sw_nb, ctx->sw_cnt,
+                     ctx->sw_fe, ctx->ctrl);
+  hipLaunchKernelGGL(k_sw_force<kSwForceLanes>, dim3(nblocks(n, kBlock / kSwForceLanes)), dim3(kBlock), 0, s,
+                     ctx->sw_nb, ctx->sw_cnt, ctx->sw_fe, n, ctx->kcap, ctx->ncap, ctx->pot, ctx->frc,
+                     ctx->vel, ctx->part, ctx->ctrl, ctx->trace, props_of(ctx));
 }
 
 template <bool WE>

@@ -9,6 +9,7 @@ namespace fire {
 
 constexpr int kBlock = 256;   // threads per block of the per-atom kernels
 constexpr int kRed = 8;       // doubles per reduction record
+constexpr int kPartAtoms = 64; // reduction records exist for grids of up to ncap / kPartAtoms blocks
 // reduction record layout (one per block of the force pass); the last two
 // are the mass-weighted sums sum_i s_i v_i.F_i and sum_i s_i^2 |F_i|^2
 // (s_i = 1 / m_i), kept only when the atoms carry masses
