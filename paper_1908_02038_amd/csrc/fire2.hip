@@ -2406,9 +2406,10 @@ int build_lists(fire_ctx* ctx) {
   }
   ctx->use_lds = false;
   if (hcap >= 64 && !(ctx->h_flags[3] & 4)) {
-    // round up so small changes of the largest halo do not force a new graph
-    const size_t atoms = (size_t)ctx->h_flags[2] + 1;
-    const size_t rounded = std::min((size_t)hcap, (atoms + 127) & ~(size_t)127);
+    // every tile block reserves the full halo capacity: the captured graphs
+    // then survive rebuilds (a reservation sized to the largest halo changed
+    // with it and forced a new capture), and three blocks still fit a CU
+    const size_t rounded = (size_t)hcap;
     if (getenv("FIRE_DEBUG"))
       fprintf(stderr, "[fire] rebuild: n %d, kcap %d, max halo %d atoms, LDS for %zu atoms per tile block\n", n,
               ctx->kcap, ctx->h_flags[2], rounded);
@@ -2862,8 +2863,9 @@ int resume(fire_ctx* ctx, hipStream_t s) {
   up[1] = 0;
   *ctx->h_zero = 0.0;
   HIPCHK(hipMemcpyAsync(ctx->ctrl, up, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+  // stream order puts the next launches after these copies; the pinned
+  // sources hold the same constants on every call, so no wait is needed
   HIPCHK(hipMemcpyAsync(&ctx->ctrl->viol, ctx->h_zero, sizeof(int), hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
   return FIRE_OK;
 }
 
@@ -2874,8 +2876,8 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
   long long rebuilds = 1;
   ctrl_defaults(ctx, *ctx->h_ctrl, tol, max_steps, 0);
   int prec = ctx->h_ctrl->precision;
+  // the pinned record is not written again before the copy back at the end
   HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
   launch_forces(ctx, s, prec);  // evaluation 0 and the set-up of iteration 1
   // graph length: short for small systems (launch-bound), longer for large ones
   ctx->graph_k = ctx->n < 20000 ? 32 : 16;
@@ -2899,9 +2901,12 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
       cur ^= 1;
     }
     materialize(ctx, s);
-    HIPCHK(hipStreamSynchronize(s));
-    const int status = st[8 * (cur ^ 1)];
-    const int pause = st[8 * (cur ^ 1) + 1];
+    // the older replay ended stopped or paused, so every kernel of the newer
+    // one exited at its gate: its status equals the older one's, which the
+    // host already holds (no wait here; the next host read of device data
+    // synchronises)
+    const int status = st[8 * cur];
+    const int pause = st[8 * cur + 1];
     if (status != ST_PAUSED) break;
     if (pause & PAUSE_PRECISION) {  // before the next update: switch pair precision
       prec = 0;
