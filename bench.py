@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "atom-force-evals/s + FIRE2 steps/s to fmax 1e-6; mixed/batched vs FP64 plain"
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 
 # Algorithmic cost of one force evaluation per atom (each in-range pair counted
 # once, FCC neighbour shells): LJ rc = 2.5 sigma -> 54 neighbours = 27 pairs of
@@ -190,6 +191,58 @@ def bench_batched(args):
     }
 
 
+def measure_config(name: str, precision: str, steps: int, warmup: int, max_steps: int, kernel_reps: int = 20):
+    """One workload at one precision: timed relaxations (inputs resident in
+    HBM), iterations, and the force evaluation's HIP-event time against the
+    algorithmic bytes and flops of the pass that dominates the loop."""
+    import torch
+    from paper_1908_02038_amd import api
+    s = make_system(name)
+    n = len(s.pos)
+    kind = s.potential["kind"]
+    pos0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    ctx = api.Context(0, s.fire, precision=precision)
+    dt, res, _ = time_relaxations(ctx, pos0, s, steps, warmup, max_steps)
+    kt = kernel_time_ms(ctx, kernel_reps)
+    ctx.close()
+    r = res[-1]
+    staged = os.environ.get("FIRE_LDS", "1") != "0" and kind != "sw"
+    alg = FUSED[kind] if staged else ALG[kind]
+    hbm = alg["bytes"] * n / (kt * 1e-3) / 1e9
+    alu = alg["flops"] * n / (kt * 1e-3) / 1e12
+    peak_alu = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
+    return {
+        "atoms": n, "potential": kind, "precision": precision, "fmax_tol": s.tol,
+        "value": n * sum(x["force_evals"] for x in res) / dt, "unit": "atom-force-evals/s",
+        "ms_per_relaxation": dt / steps * 1e3, "steps_per_s": sum(x["iterations"] for x in res) / dt,
+        "iterations": r["iterations"], "iterations_fp32": r["iterations_low"], "rebuilds": r["rebuilds"],
+        "stop": r["stop"], "energy_per_atom": r["energy_per_atom"], "fmax": r["fmax"],
+        "force_pass_us": kt * 1e3, "force_pass_kernel": alg["kernel"],
+        "force_pass_hbm_frac_alg": hbm / PEAK_HBM_GBS, "force_pass_hbm_GBs_alg": hbm,
+        "force_pass_alu_frac_alg": alu / peak_alu, "force_pass_TFLOPs_alg": alu,
+        "note": "force pass timed at the start positions with the run's first pair precision"
+                if precision != "fp64" else "",
+    }
+
+
+def other_configs(args):
+    """The other single-system configurations, one line each (the headline's
+    LJ bulk is the top-level record): the 255-atom LJ crystal to 1e-8, the
+    253,440-atom EAM-form bulk in FP64 and mixed, the 2,037,760-atom EAM-form
+    slab in mixed precision (its passes have enough atoms per CU to press on
+    HBM), and the 32,763-atom Stillinger-Weber Si slab."""
+    out = {}
+    plan = [("lj_small", "fp64", 3, 1), ("gupta_bulk", "fp64", 3, 1), ("gupta_bulk", "mixed", 3, 1),
+            ("gupta_slab", "mixed", 1, 1), ("si_slab", "fp64", 3, 1)]
+    for name, prec, steps, warm in plan:
+        r = measure_config(name, prec, steps, warm, args.max_steps)
+        out[f"{name}_{prec}"] = r
+        log(f"[bench] {name} {prec}: {r['ms_per_relaxation']:.1f} ms/relaxation, {r['iterations']} iterations, "
+            f"stop {r['stop']}, force pass {r['force_pass_us']:.1f} us ({r['force_pass_hbm_frac_alg']:.3f} of HBM alg, "
+            f"{r['force_pass_alu_frac_alg']:.3f} of {prec} VALU alg)")
+    return out
+
+
 COPY_BYTES = 256 << 20
 
 
@@ -248,6 +301,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other configurations")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--kernel-only", action="store_true",
@@ -363,6 +417,9 @@ def main():
 
     if not args.no_batched:
         out["batched"] = bench_batched(args)
+
+    if not args.no_configs and args.workload == "lj_bulk":
+        out["other_configs"] = other_configs(args)
 
     if not args.no_cpu:
         log("[bench] cpu oracle baseline ...")
