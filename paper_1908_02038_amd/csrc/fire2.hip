@@ -170,7 +170,7 @@ __global__ void k_stage_out_pos(const double4* __restrict__ pos, int n, const in
 // periodic face gets ghost copies (shifted by the box length) in an extra
 // layer of cells outside the box, so pair loops never take a minimum image.
 // All atoms (real and ghost) are counting-sorted by cell; cells inside the box
-// are numbered first (in Morton order), so real atoms occupy slots [0, n) and
+// are numbered first (along a Hilbert curve), so real atoms occupy slots [0, n) and
 // ghosts follow.  The update and density kernels refresh each atom's ghosts.
 
 struct Grid {
@@ -1951,7 +1951,7 @@ struct fire_ctx {
   double4* xref = nullptr;                // positions at the last list build
   int* bucket = nullptr;                  // cell-bucketed slots before ranking
   int* srank = nullptr;                   // cell rank of each slot
-  int *cell_rank = nullptr, *rank_cell = nullptr;  // linear cell <-> Morton rank
+  int *cell_rank = nullptr, *rank_cell = nullptr;  // linear cell <-> rank along the Hilbert curve
   int rank_dims[3] = {0, 0, 0}, rank_per = -1;
   // LDS-staged tiles
   int* tile_h = nullptr;
@@ -2228,7 +2228,7 @@ int prepare_system(fire_ctx* ctx, const fire_box* b, const fire_potential* p) {
 
 // Cell grid: edge >= rcs; on periodic axes the box plus one ghost layer on
 // each side, on free axes the bounding box of the atoms.  Cells inside the
-// box get the first ranks (Morton order), the ghost layers the rest, so a
+// box get the first ranks (Hilbert order), the ghost layers the rest, so a
 // sort by rank puts real atoms before ghosts.
 // start[0..m] = exclusive prefix sum of count[0..m), start[m] = total.
 int launch_scan(fire_ctx* ctx, hipStream_t s, const int* count, int m, int* start) {
@@ -2318,21 +2318,46 @@ int make_grid(fire_ctx* ctx, int n) {
   const int per_code = ctx->box.per[0] | (ctx->box.per[1] << 1) | (ctx->box.per[2] << 2);
   if (ctx->rank_dims[0] != g.n[0] || ctx->rank_dims[1] != g.n[1] || ctx->rank_dims[2] != g.n[2] ||
       ctx->rank_per != per_code) {
-    auto spread = [](unsigned v) {
-      unsigned long long x = v & 0x3ff;
-      x = (x | (x << 16)) & 0x30000ffULL;
-      x = (x | (x << 8)) & 0x300f00fULL;
-      x = (x | (x << 4)) & 0x30c30c3ULL;
-      x = (x | (x << 2)) & 0x9249249ULL;
-      return x;
+    // Cells are ranked along a 3-D Hilbert curve (inside the box first, then
+    // the periodic-image layers): consecutive ranks are face neighbours, so
+    // every run of 256 slots -- a tile of the LDS-staged passes -- stays
+    // compact in space and its halo small.  A Morton order jumps across the
+    // box at power-of-two boundaries, and a tile straddling a jump needs a
+    // halo for two separate pieces.  Index by Skilling's transpose method
+    // (Programming the Hilbert curve, AIP Conf. Proc. 707, 2004).
+    int bits = 1;
+    while ((1 << bits) < std::max(g.n[0], std::max(g.n[1], g.n[2]))) ++bits;
+    auto hilbert = [bits](const int (&cc)[3]) {
+      unsigned x[3] = {(unsigned)cc[0], (unsigned)cc[1], (unsigned)cc[2]};
+      const unsigned top = 1u << (bits - 1);
+      for (unsigned q = top; q > 1; q >>= 1) {  // undo the excess work of the reflections
+        const unsigned p = q - 1;
+        for (int i = 0; i < 3; ++i) {
+          if (x[i] & q) {
+            x[0] ^= p;
+          } else {
+            const unsigned t = (x[0] ^ x[i]) & p;
+            x[0] ^= t;
+            x[i] ^= t;
+          }
+        }
+      }
+      for (int i = 1; i < 3; ++i) x[i] ^= x[i - 1];  // Gray code
+      unsigned t = 0;
+      for (unsigned q = top; q > 1; q >>= 1)
+        if (x[2] & q) t ^= q - 1;
+      for (int i = 0; i < 3; ++i) x[i] ^= t;
+      unsigned long long h = 0;  // interleave, most significant level first
+      for (int b = bits - 1; b >= 0; --b)
+        for (int i = 0; i < 3; ++i) h = (h << 1) | ((x[i] >> b) & 1u);
+      return h;
     };
     std::vector<std::pair<unsigned long long, int>> key(g.ncell);
     for (int c = 0; c < g.ncell; ++c) {
       const int cc[3] = {c % g.n[0], (c / g.n[0]) % g.n[1], c / (g.n[0] * g.n[1])};
       bool inside = true;
       for (int k = 0; k < 3; ++k) inside = inside && cc[k] >= in_lo[k] && cc[k] <= in_hi[k];
-      const unsigned long long m = spread(cc[0]) | (spread(cc[1]) << 1) | (spread(cc[2]) << 2);
-      key[c] = {(inside ? 0ULL : (1ULL << 40)) | m, c};
+      key[c] = {(inside ? 0ULL : (1ULL << 40)) | hilbert(cc), c};
     }
     std::sort(key.begin(), key.end());
     std::vector<int> rank(g.ncell), cell(g.ncell);
