@@ -2323,8 +2323,10 @@ int make_grid(fire_ctx* ctx, int n) {
     // every run of 256 slots -- a tile of the LDS-staged passes -- stays
     // compact in space and its halo small.  A Morton order jumps across the
     // box at power-of-two boundaries, and a tile straddling a jump needs a
-    // halo for two separate pieces.  Index by Skilling's transpose method
-    // (Programming the Hilbert curve, AIP Conf. Proc. 707, 2004).
+    // halo for two separate pieces.  The inside cells are indexed from 0, so
+    // the largest power-of-two cube of the curve lies wholly inside the box
+    // and the curve leaves it less often.  Index by Skilling's transpose
+    // method (Programming the Hilbert curve, AIP Conf. Proc. 707, 2004).
     int bits = 1;
     while ((1 << bits) < std::max(g.n[0], std::max(g.n[1], g.n[2]))) ++bits;
     auto hilbert = [bits](const int (&cc)[3]) {
@@ -2357,7 +2359,10 @@ int make_grid(fire_ctx* ctx, int n) {
       const int cc[3] = {c % g.n[0], (c / g.n[0]) % g.n[1], c / (g.n[0] * g.n[1])};
       bool inside = true;
       for (int k = 0; k < 3; ++k) inside = inside && cc[k] >= in_lo[k] && cc[k] <= in_hi[k];
-      key[c] = {(inside ? 0ULL : (1ULL << 40)) | hilbert(cc), c};
+      int ci[3] = {cc[0], cc[1], cc[2]};
+      if (inside)
+        for (int k = 0; k < 3; ++k) ci[k] -= in_lo[k];
+      key[c] = {(inside ? 0ULL : (1ULL << 40)) | hilbert(ci), c};
     }
     std::sort(key.begin(), key.end());
     std::vector<int> rank(g.ncell), cell(g.ncell);
@@ -3148,9 +3153,6 @@ int fire_init(fire_ctx** out, int device, const fire_params* params) {
     HIPCHK(hipMalloc((void**)&ctx->ctrl, sizeof(Ctrl)));
     HIPCHK(hipMalloc((void**)&ctx->flags, 8 * sizeof(int)));
     HIPCHK(hipHostMalloc((void**)&ctx->h_flags, 8 * sizeof(int), hipHostMallocDefault));
-    // LDS-staged neighbour passes are opt-in: with halos of ~2-3k atoms per
-    // 256-atom tile they fit one block per CU and measure slower than the
-    // global-gather passes on the bulk workloads
     // LDS-staged pair passes with at most 52 KB per block (three blocks per
     // CU); FIRE_LDS=0: global gathers only; FIRE_LDS=<bytes>: another limit
     {
