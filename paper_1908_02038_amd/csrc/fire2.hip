@@ -513,28 +513,40 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
     const double4 pi = pos[i];
     const int c[3] = {real_cell_coord(pi.x, g, 0), real_cell_coord(pi.y, g, 1), real_cell_coord(pi.z, g, 2)};
     // stencil cells in ascending rank, so each list comes out sorted by slot:
-    // lanes of a wave then read nearby (or identical) neighbours at each step
-    int cells[27];
+    // lanes of a wave then read nearby (or identical) neighbours at each step.
+    // Sorted by a bitonic network over 32 entries (cells outside the grid
+    // and the padding hold INT_MAX and sort last): every register index is
+    // static.  An insertion sort indexes the array by a per-lane position,
+    // which compiles to a compare-and-select over all entries per access and
+    // cost several times the candidate tests themselves.
+    int cells[32];
     int nc = 0;
-    for (int oz = -1; oz <= 1; ++oz) {
-      const int cz = c[2] + oz;
-      if (cz < 0 || cz >= g.n[2]) continue;
-      for (int oy = -1; oy <= 1; ++oy) {
-        const int cy = c[1] + oy;
-        if (cy < 0 || cy >= g.n[1]) continue;
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int cx = c[0] + ox;
-          if (cx < 0 || cx >= g.n[0]) continue;
-          const int r = cell_rank[cx + g.n[0] * (cy + g.n[1] * cz)];
-          int k = nc++;
-          while (k > 0 && cells[k - 1] > r) {
-            cells[k] = cells[k - 1];
-            --k;
-          }
-          cells[k] = r;
+#pragma unroll
+    for (int o = 0; o < 32; ++o) {
+      int r = INT_MAX;
+      if (o < 27) {
+        const int cx = c[0] + o % 3 - 1, cy = c[1] + (o / 3) % 3 - 1, cz = c[2] + o / 9 - 1;
+        if (cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1] && cz >= 0 && cz < g.n[2]) {
+          r = cell_rank[cx + g.n[0] * (cy + g.n[1] * cz)];
+          ++nc;
         }
       }
+      cells[o] = r;
     }
+#pragma unroll
+    for (int k = 2; k <= 32; k <<= 1)
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+        for (int a = 0; a < 32; ++a) {
+          const int b = a ^ j;
+          if (b > a) {
+            const int lo = min(cells[a], cells[b]), hi = max(cells[a], cells[b]);
+            const bool up = (a & k) == 0;
+            cells[a] = up ? lo : hi;
+            cells[b] = up ? hi : lo;
+          }
+        }
     for (int q = 0; q < nc; ++q) {
       const int cell = cells[q];
       // candidates in groups of 8: all loads issued before the tests, so
