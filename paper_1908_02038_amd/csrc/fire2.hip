@@ -704,33 +704,48 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
   for (int q = t; q < nwords; q += blockDim.x) used[q] = 0u;
   for (int h = t; h < nu; h += blockDim.x) cslot[h] = start[cand[h]];
   __syncthreads();
-  auto run_of_slot = [&](int j) {  // last run h with cslot[h] <= j
-    int lo = 0, hi = nu - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (cslot[mid] <= j) lo = mid;
-      else hi = mid - 1;
-    }
-    return lo;
+  // Searches by binary lifting: a trip count that is the same for every lane
+  // (log2 of the block-uniform run count), so the four searches of a list
+  // group interleave their LDS reads instead of waiting on each other.
+  int top = 1;
+  while (2 * top <= nu) top *= 2;
+  auto run_of_slot = [&](int j) {  // last run h with cslot[h] <= j (h = 0 if none)
+    int h = 0;
+    for (int step = top; step > 0; step >>= 1)
+      if (h + step < nu && cslot[h + step] <= j) h += step;
+    return h;
   };
   // pass 1: candidate index of every list entry, marked in the bitmap and
-  // kept in nbr16 until the halo numbering is known (padding: 0xFFFF)
+  // kept in nbr16 until the halo numbering is known (padding: 0xFFFF).
+  // Lists are read a group of four at a time (one 16-byte load per lane,
+  // the next group in flight while this one is searched).
   const int i = b * kBlock + t;
   const int w = i >> 6, lane = t & 63;
-  const int kw = wcnt[w];
-  for (int k = 0; k < kw; ++k) {
-    const int j = nbr[lidx(w, k, lane, kcap)];
-    int q = 0xFFFF;
-    if (j != dummy) {
-      const int h = run_of_slot(j);
-      q = hoff[h] + (j - cslot[h]);
-      if (j < cslot[h] || q >= hoff[h + 1]) {  // not among the candidates: cannot happen for valid lists
-        atomicOr(&flags[3], 4);
-        q = 0;
+  const int kw = wcnt[w];  // a multiple of 4
+  auto group = [&](int k) { return *reinterpret_cast<const int4*>(nbr + lidx(w, k, lane, kcap)); };
+  int4 next = kw > 0 ? group(0) : make_int4(0, 0, 0, 0);
+  for (int k = 0; k < kw; k += 4) {
+    const int4 g4 = next;
+    if (k + 4 < kw) next = group(k + 4);
+    const int jv[4] = {g4.x, g4.y, g4.z, g4.w};
+    int qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = jv[u];
+      int q = 0xFFFF;
+      if (j != dummy) {
+        const int h = run_of_slot(j);
+        q = hoff[h] + (j - cslot[h]);
+        if (j < cslot[h] || q >= hoff[h + 1]) {  // not among the candidates: cannot happen for valid lists
+          atomicOr(&flags[3], 4);
+          q = 0;
+        }
+        atomicOr(&used[q >> 5], 1u << (q & 31));
       }
-      atomicOr(&used[q >> 5], 1u << (q & 31));
+      qv[u] = q;
     }
-    nbr16[lidx(w, k, lane, kcap)] = (unsigned short)q;
+    *reinterpret_cast<ushort4*>(nbr16 + lidx(w, k, lane, kcap)) =
+        make_ushort4((unsigned short)qv[0], (unsigned short)qv[1], (unsigned short)qv[2], (unsigned short)qv[3]);
   }
   __syncthreads();
   // halo index of the first marked candidate of each bitmap word
@@ -758,21 +773,22 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
   int* hr = hsrc + (size_t)b * hcap;
   for (int q = t; q < Hc; q += blockDim.x) {
     if (!(used[q >> 5] & (1u << (q & 31)))) continue;
-    int lo = 0, hi = nu - 1;  // last run h with hoff[h] <= q
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (hoff[mid] <= q) lo = mid;
-      else hi = mid - 1;
-    }
-    const int j = cslot[lo] + (q - hoff[lo]);
+    int h = 0;  // last run h with hoff[h] <= q
+    for (int step = top; step > 0; step >>= 1)
+      if (h + step < nu && hoff[h + step] <= q) h += step;
+    const int j = cslot[h] + (q - hoff[h]);
     hs[halo_index(q)] = j;
     hr[halo_index(q)] = real_of[j];
   }
-  // pass 2: candidate index -> halo index
-  for (int k = 0; k < kw; ++k) {
-    const size_t e = lidx(w, k, lane, kcap);
-    const int q = nbr16[e];
-    nbr16[e] = (unsigned short)(q == 0xFFFF ? H : halo_index(q));
+  // pass 2: candidate index -> halo index, a group of four per load and store
+  auto group16 = [&](int k) { return *reinterpret_cast<const ushort4*>(nbr16 + lidx(w, k, lane, kcap)); };
+  ushort4 next16 = kw > 0 ? group16(0) : make_ushort4(0, 0, 0, 0);
+  for (int k = 0; k < kw; k += 4) {
+    const ushort4 g4 = next16;
+    if (k + 4 < kw) next16 = group16(k + 4);
+    auto remap = [&](int q) { return (unsigned short)(q == 0xFFFF ? H : halo_index(q)); };
+    *reinterpret_cast<ushort4*>(nbr16 + lidx(w, k, lane, kcap)) =
+        make_ushort4(remap(g4.x), remap(g4.y), remap(g4.z), remap(g4.w));
   }
   if (t == 0) {
     tile_h[b] = H;
