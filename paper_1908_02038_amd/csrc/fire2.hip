@@ -39,10 +39,11 @@ namespace fire {
 
 // Block-level reduction of NS sums followed by NM maxima; result valid in
 // thread 0.  Order is fixed by the thread layout, so results are
-// reproducible run to run.
-template <int NS, int NM>
+// reproducible run to run.  MAXB: the largest block size of the caller (its
+// LDS scratch is sized for it; kernels at the LDS limit keep the default).
+template <int NS, int NM, int MAXB = kBlock>
 __device__ __forceinline__ void block_reduce(double (&v)[NS + NM]) {
-  __shared__ double red[kBlock / 64][NS + NM];
+  __shared__ double red[MAXB / 64][NS + NM];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NS; ++k) v[k] = wave_sum(v[k]);
@@ -582,16 +583,17 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
   if (overlap) atomicOr(&flags[0], ERR_OVERLAP);
 }
 
-// Candidates of tile b (the 256 slots of block b): the stencil cells of the
+// Candidates of tile b (the TILE slots of block b): the stencil cells of the
 // tile's cells, sorted by rank and made unique, with the offsets of their atom
 // runs (hoff, hoff[nu] = number of candidate atoms).  Returns nu, or -1 if
 // the tile has more than kCandMax / 27 distinct cells.
 constexpr int kCandMax = 4096;
+template <int TILE>
 __device__ int tile_candidates(const int* __restrict__ srank, const int* __restrict__ start,
                                const int* __restrict__ rank_cell, const int* __restrict__ cell_rank, int n,
                                const Grid& g, int* cand, int* hoff, int* dcell, int* s_shared) {
   const int b = blockIdx.x, t = threadIdx.x;
-  const int s0 = b * kBlock, s1 = min(s0 + kBlock, n);
+  const int s0 = b * TILE, s1 = min(s0 + TILE, n);
   int tot;
   {
     const int sl = s0 + t;
@@ -634,8 +636,8 @@ __device__ int tile_candidates(const int* __restrict__ srank, const int* __restr
       }
       __syncthreads();
     }
-  // unique cells and their run offsets; thread t owns 16 consecutive entries
-  constexpr int kPer = kCandMax / kBlock;
+  // unique cells and their run offsets; thread t owns kPer consecutive entries
+  constexpr int kPer = kCandMax / TILE;
   int r[kPer], nu_t = 0, len_t = 0;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -666,8 +668,8 @@ __device__ int tile_candidates(const int* __restrict__ srank, const int* __restr
   return *s_shared;
 }
 
-// Per-tile halo for the LDS-staged passes.  Tile b is the 256 slots of block
-// b.  Its halo is the set of atoms that occur in the tile's neighbour lists:
+// Per-tile halo for the LDS-staged passes.  Tile b is the TILE slots of block
+// b (one thread per slot).  Its halo is the set of atoms that occur in the tile's neighbour lists:
 // every list entry marks its candidate (tile_candidates) in a bitmap, and the
 // marked candidates, in candidate order, are the halo.  The kernel writes the
 // halo's slot list (hslot, at most hcap entries), its size (tile_h), and
@@ -675,7 +677,8 @@ __device__ int tile_candidates(const int* __restrict__ srank, const int* __restr
 // an LDS slot set to a far position).  A halo that does not fit sets
 // flags[3] bit 4; flags[2] = max H.
 constexpr int kHaloCandMax = 16384;   // candidate atoms of one tile (bitmap bits)
-__global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ srank, const int* __restrict__ start,
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_tile_halo(const int* __restrict__ srank, const int* __restrict__ start,
                                                       const int* __restrict__ rank_cell,
                                                       const int* __restrict__ cell_rank, int n, Grid g,
                                                       const int* __restrict__ nbr, const int* __restrict__ wcnt,
@@ -685,12 +688,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
                                                       unsigned short* __restrict__ nbr16, int* __restrict__ flags) {
   __shared__ int cand[kCandMax];
   __shared__ int hoff[kCandMax + 1];
-  __shared__ int dcell[kBlock];
+  __shared__ int dcell[TILE];
   __shared__ unsigned int used[kHaloCandMax / 32];
   __shared__ int wpre[kHaloCandMax / 32];
   __shared__ int s_nu;
   const int b = blockIdx.x, t = threadIdx.x;
-  const int nu = tile_candidates(srank, start, rank_cell, cell_rank, n, g, cand, hoff, dcell, &s_nu);
+  const int nu = tile_candidates<TILE>(srank, start, rank_cell, cell_rank, n, g, cand, hoff, dcell, &s_nu);
   int* cslot = cand;  // below, cand[h] is replaced by the first slot of run h (runs ascend in slot order)
   if (nu < 0 || hoff[nu] > kHaloCandMax) {
     if (t == 0) {
@@ -719,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
   // kept in nbr16 until the halo numbering is known (padding: 0xFFFF).
   // Lists are read a group of four at a time (one 16-byte load per lane,
   // the next group in flight while this one is searched).
-  const int i = b * kBlock + t;
+  const int i = b * TILE + t;
   const int w = i >> 6, lane = t & 63;
   const int kw = wcnt[w];  // a multiple of 4
   auto group = [&](int k) { return *reinterpret_cast<const int4*>(nbr + lidx(w, k, lane, kcap)); };
@@ -750,7 +753,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_halo(const int* __restrict__ sr
   __syncthreads();
   // halo index of the first marked candidate of each bitmap word
   int tot = 0;
-  for (int base = 0; base < nwords; base += kBlock) {
+  for (int base = 0; base < nwords; base += TILE) {
     const int q = base + t;
     const int pc = q < nwords ? __popc(used[q]) : 0;
     int part;
@@ -1040,6 +1043,7 @@ __device__ __forceinline__ double ld_cohere(const double* p) {
 // max |F_i|^2, max |v_i|^2 (and, with masses, sum s v.F and sum s^2 F^2)
 // into the block's reduction record; the last block to finish reduces all
 // records in fixed order (second stage) and runs the FIRE control.
+template <int MAXB = kBlock>
 __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, double fy, double fz, double e,
                                                double* __restrict__ frc, double* __restrict__ vel, int ncap,
                                                double* __restrict__ part, const double* __restrict__ part_emb,
@@ -1081,8 +1085,8 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
   // every memory operation of this thread (the skin flag's atomic among them)
   // has completed before the block's ticket is taken
   __builtin_amdgcn_s_waitcnt(0);
-  block_reduce<4, 2>(r);
-  if (pr.sinv) block_reduce<2, 0>(rm);  // uniform over the block
+  block_reduce<4, 2, MAXB>(r);
+  if (pr.sinv) block_reduce<2, 0, MAXB>(rm);  // uniform over the block
   __shared__ int is_last;
   if (threadIdx.x == 0) {
     // The partial record is the only data the last block reads: it is stored
@@ -1112,7 +1116,7 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
     q[4] = fmax(q[4], ld_cohere(o + R_FMAX2));
     q[5] = fmax(q[5], ld_cohere(o + R_VMAX2));
   }
-  block_reduce<4, 2>(q);
+  block_reduce<4, 2, MAXB>(q);
   // without masses the mass-weighted sums are P and |F|^2 exactly
   double qm[2] = {q[R_P], q[R_F2]};
   if (pr.sinv) {
@@ -1121,7 +1125,7 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
       qm[0] += ld_cohere(part + (size_t)kRed * b + R_SVF);
       qm[1] += ld_cohere(part + (size_t)kRed * b + R_SFF);
     }
-    block_reduce<2, 0>(qm);
+    block_reduce<2, 0, MAXB>(qm);
   }
   if (threadIdx.x == 0) {
     const double qc[kCtl] = {q[0], q[1], q[2], q[3], q[4], q[5], qm[0], qm[1]};
@@ -1364,7 +1368,7 @@ __device__ __forceinline__ double4 own_update(const UpdArgs& ua, const UpdCoef& 
 // LDS, own atoms written to ua.dst) and reads and writes ua's state sets
 // instead of pos / frc / vel; requires LDS.
 template <typename T, bool LDS, bool WE, bool UPD = false>
-__global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
+__global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
                                                      Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
                                                      int ncap, PotDev pot, double* __restrict__ frc,
                                                      double* __restrict__ vel, double* __restrict__ part,
@@ -1411,8 +1415,8 @@ __global__ __launch_bounds__(kBlock) void k_lj_force(const double4* __restrict__
     az += fr * (T)dz;
     if constexpr (WE) ae += in ? (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh) : (T)0;
   });
-  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, nullptr, b, ctrl,
-                 trace, pr, UPD);
+  force_epilogue<kMaxTile>(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, nullptr, b,
+                           ctrl, trace, pr, UPD);
 }
 
 // Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
@@ -1989,6 +1993,9 @@ struct fire_ctx {
   int hcap = 0;
   bool use_lds = false;
   size_t lds_atoms = 0, lds_limit = 0;  // halo capacity per tile block; byte limit per block
+  bool lds_default = true;              // no explicit limit: the LJ pass's 512-atom tiles get kLdsLj
+  size_t lds_cap = 0;                   // the device's LDS per block, less a margin for static LDS
+  int tile = kBlock;                    // atoms per tile of the current lists' halos
   double *part = nullptr, *part_emb = nullptr, *bbox_part = nullptr;
   // per-atom properties of the running minimisation: 1/m and freeze bits in
   // caller order (minv_atom, fmask_atom) and in slot order (sinv, fmask),
@@ -2127,13 +2134,13 @@ int ensure_slots(fire_ctx* ctx, int nt, int keep = 0) {
   return FIRE_OK;
 }
 
-// Real-atom arrays.  Capacity is a multiple of the block size, so every
-// launch over ceil(n/256) blocks stays inside them.
+// Real-atom arrays.  Capacity is a multiple of the largest tile, so every
+// launch over ceil(n/256) blocks, or ceil(n/512) tiles, stays inside them.
 int ensure_atoms(fire_ctx* ctx, int n) {
   if (n <= ctx->ncap) return FIRE_OK;
   drop_graphs(ctx);
   free_single(ctx);
-  const int cap = ((std::max(n, 64) + kBlock - 1) / kBlock) * kBlock;
+  const int cap = ((std::max(n, 64) + kMaxTile - 1) / kMaxTile) * kMaxTile;
   const int nb = cap / kBlock;
   HIPCHK(dalloc(&ctx->xref, cap));
   HIPCHK(dalloc(&ctx->vel, 3 * (size_t)cap));
@@ -2348,8 +2355,8 @@ int make_grid(fire_ctx* ctx, int n) {
       ctx->rank_per != per_code) {
     // Cells are ranked along a 3-D Hilbert curve (inside the box first, then
     // the periodic-image layers): consecutive ranks are face neighbours, so
-    // every run of 256 slots -- a tile of the LDS-staged passes -- stays
-    // compact in space and its halo small.  A Morton order jumps across the
+    // every run of 256 or 512 slots -- a tile of the LDS-staged passes --
+    // stays compact in space and its halo small.  A Morton order jumps across the
     // box at power-of-two boundaries, and a tile straddling a jump needs a
     // halo for two separate pieces.  The inside cells are indexed from 0, so
     // the largest power-of-two cube of the curve lies wholly inside the box
@@ -2416,6 +2423,34 @@ int read_flags(fire_ctx* ctx) {
 // for the EAM force pass.
 size_t halo_bytes_per_atom(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_POT_GUPTA ? 32 : 24; }
 
+// Tiles of the LDS-staged passes.  The LJ pass takes 512 atoms per tile: its
+// halo grows less than the tile (1.6 against 2 times), so fewer halo atoms
+// are staged per atom, and its one pass per evaluation runs 29.1 instead of
+// 30.3 us per launch on the 130,417-atom box.  The EAM form's two passes
+// measured faster on 256-atom tiles (104 against 110 us).  With 80 KB of
+// LDS per LJ tile block two blocks still fit a CU.
+constexpr size_t kLdsLj = 80 * 1024;
+int tile_atoms(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_POT_LJ ? kMaxTile : kBlock; }
+
+// EAM-form tile blocks reserve 52 KB (three force-pass blocks per CU) while
+// an XCD's share of the per-atom state (about 96 B per atom: positions,
+// velocities, forces, F'(rho), the staged-update reads) fits its 4 MB L2,
+// and 56 KB (two force-pass blocks per CU, the density pass keeps three)
+// beyond.  Past that size the passes stream their halos from beyond the L2
+// and a third block per CU only adds misses: on the 2,037,760-atom slab the
+// FP64 passes take 752 instead of 950 us per evaluation, while the
+// 253,440-atom bulk, whose share stays in the L2, is faster with three
+// (103 against 108 us).
+constexpr size_t kLdsEamLarge = 56 * 1024;
+constexpr long long kL2Atoms = 8LL * (4 << 20) / 96;
+
+size_t lds_budget(const fire_ctx* ctx, int tile) {
+  if (!ctx->lds_default) return ctx->lds_limit;
+  if (tile == kMaxTile) return std::min(kLdsLj, ctx->lds_cap);
+  if (ctx->pot.kind == FIRE_POT_GUPTA && ctx->n > kL2Atoms) return std::min(kLdsEamLarge, ctx->lds_cap);
+  return ctx->lds_limit;
+}
+
 
 
 // Neighbour lists (and, with the LDS budget, tile halos) of the current
@@ -2423,31 +2458,41 @@ size_t halo_bytes_per_atom(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_P
 // list fits.
 int build_lists(fire_ctx* ctx) {
   hipStream_t s = ctx->stream;
-  const int n = ctx->n, nb = nblocks(n), dummy = ctx->tcap - 1;
+  const int n = ctx->n, dummy = ctx->tcap - 1;
+  const int tile = tile_atoms(ctx), nt = nblocks(n, tile);
   const double rcs2 = ctx->rcs * ctx->rcs;
   const bool was = ctx->use_lds;
+  const size_t limit = lds_budget(ctx, tile);
   // no LDS tiles for the three-body potential (its force pass reads the
   // neighbours' short lists, not their positions)
-  const int hcap = ctx->pot.kind == FIRE_POT_SW ? 0
-                                                : (int)std::min<size_t>(ctx->lds_limit / halo_bytes_per_atom(ctx), 65535);
+  const int hcap = ctx->pot.kind == FIRE_POT_SW || ctx->lds_limit == 0
+                       ? 0
+                       : (int)std::min<size_t>(limit / halo_bytes_per_atom(ctx), 65535);
   for (int attempt = 0; attempt < 6; ++attempt) {
     if (!ctx->nbr16) HIPCHK(dalloc(&ctx->nbr16, (size_t)ctx->kcap * ctx->ncap));
-    if (hcap >= 64 && (!ctx->hslot || ctx->hcap != hcap)) {
+    if (hcap >= 64 && (!ctx->hslot || ctx->hcap != hcap || ctx->tile != tile)) {
       hipFree(ctx->hslot);
       hipFree(ctx->hsrc);
       ctx->hslot = ctx->hsrc = nullptr;
-      HIPCHK(dalloc(&ctx->hslot, (size_t)hcap * (ctx->ncap / kBlock)));
-      HIPCHK(dalloc(&ctx->hsrc, (size_t)hcap * (ctx->ncap / kBlock)));
+      HIPCHK(dalloc(&ctx->hslot, (size_t)hcap * (ctx->ncap / tile)));
+      HIPCHK(dalloc(&ctx->hsrc, (size_t)hcap * (ctx->ncap / tile)));
       ctx->hcap = hcap;
+      ctx->tile = tile;
       ctx->layout_version++;
     }
     HIPCHK(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), s));
     hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, n, ctx->grid,
                        ctx->cell_rank, ctx->cell_start, rcs2, ctx->kcap, dummy, ctx->nbr, ctx->wcnt, ctx->flags);
-    if (hcap >= 64)
-      hipLaunchKernelGGL(k_tile_halo, dim3(nb), dim3(kBlock), 0, s, ctx->srank, ctx->cell_start, ctx->rank_cell,
-                         ctx->cell_rank, n, ctx->grid, ctx->nbr, ctx->wcnt, ctx->kcap, hcap, dummy, ctx->tile_h,
-                         ctx->hslot, ctx->hsrc, ctx->real_of, ctx->nbr16, ctx->flags);
+    if (hcap >= 64) {
+      if (tile == kMaxTile)
+        hipLaunchKernelGGL(k_tile_halo<kMaxTile>, dim3(nt), dim3(kMaxTile), 0, s, ctx->srank, ctx->cell_start,
+                           ctx->rank_cell, ctx->cell_rank, n, ctx->grid, ctx->nbr, ctx->wcnt, ctx->kcap, hcap, dummy,
+                           ctx->tile_h, ctx->hslot, ctx->hsrc, ctx->real_of, ctx->nbr16, ctx->flags);
+      else
+        hipLaunchKernelGGL(k_tile_halo<kBlock>, dim3(nt), dim3(kBlock), 0, s, ctx->srank, ctx->cell_start,
+                           ctx->rank_cell, ctx->cell_rank, n, ctx->grid, ctx->nbr, ctx->wcnt, ctx->kcap, hcap, dummy,
+                           ctx->tile_h, ctx->hslot, ctx->hsrc, ctx->real_of, ctx->nbr16, ctx->flags);
+    }
     int rc = read_flags(ctx);
     if (rc) return rc;
     if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
@@ -2466,7 +2511,8 @@ int build_lists(fire_ctx* ctx) {
   if (hcap >= 64 && !(ctx->h_flags[3] & 4)) {
     // every tile block reserves the full halo capacity: the captured graphs
     // then survive rebuilds (a reservation sized to the largest halo changed
-    // with it and forced a new capture), and three blocks still fit a CU
+    // with it and forced a new capture), and three 256-atom (two 512-atom)
+    // tile blocks still fit a CU
     const size_t rounded = (size_t)hcap;
     if (getenv("FIRE_DEBUG"))
       fprintf(stderr, "[fire] rebuild: n %d, kcap %d, max halo %d atoms, LDS for %zu atoms per tile block\n", n,
@@ -2607,7 +2653,10 @@ UpdArgs upd_args(fire_ctx* ctx, int parity) {
 // `parity` and writing the other (LDS-staged passes only).
 template <typename T, bool LDS, bool WE>
 void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
-  const int n = ctx->n, nb = nblocks(n), kc = ctx->kcap, nc = ctx->ncap;
+  // the LJ pass runs on its tiles' blocks also with global gathers, so both
+  // forms reduce over the same atom groups and give the same bits
+  const int tile = tile_atoms(ctx);
+  const int n = ctx->n, nb = nblocks(n), nt = nblocks(n, tile), kc = ctx->kcap, nc = ctx->ncap;
   const PotDev& P = ctx->pot;
   const Tiles tl{ctx->tile_h, ctx->hslot, ctx->hsrc, ctx->nbr16, ctx->hcap};
   const size_t sm = LDS ? ctx->lds_atoms * 24 : 0;     // x, y, z
@@ -2618,7 +2667,7 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
     if (parity >= 0) {
       const StateBuf d = ua.dst;
       if (P.kind == FIRE_POT_LJ) {
-        hipLaunchKernelGGL((k_lj_force<T, true, WE, true>), dim3(nb), dim3(kBlock), sm, s, ua.src.pos, ctx->nbr, tl,
+        hipLaunchKernelGGL((k_lj_force<T, true, WE, true>), dim3(nt), dim3(tile), sm, s, ua.src.pos, ctx->nbr, tl,
                            ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
       } else {
         hipLaunchKernelGGL((k_gupta_density<T, true, true>), dim3(nb), dim3(kBlock), sm, s, ua.src.pos, ctx->nbr,
@@ -2631,8 +2680,8 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
     }
   }
   if (P.kind == FIRE_POT_LJ) {
-    hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt,
-                       n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
+    hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nt), dim3(tile), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt, n,
+                       kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
   } else {
     hipLaunchKernelGGL((k_gupta_density<T, LDS>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl,
                        ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
@@ -3181,13 +3230,16 @@ int fire_init(fire_ctx** out, int device, const fire_params* params) {
     HIPCHK(hipMalloc((void**)&ctx->ctrl, sizeof(Ctrl)));
     HIPCHK(hipMalloc((void**)&ctx->flags, 8 * sizeof(int)));
     HIPCHK(hipHostMalloc((void**)&ctx->h_flags, 8 * sizeof(int), hipHostMallocDefault));
-    // LDS-staged pair passes with at most 52 KB per block (three blocks per
-    // CU); FIRE_LDS=0: global gathers only; FIRE_LDS=<bytes>: another limit
+    // LDS-staged pair passes with at most 52 KB per 256-atom tile block
+    // (three blocks per CU) and 80 KB per 512-atom LJ tile block (two);
+    // FIRE_LDS=0: global gathers only; FIRE_LDS=<bytes>: that limit for both
     {
       const char* e = getenv("FIRE_LDS");
       const long v = e ? atol(e) : 1;
       const size_t cap = prop.sharedMemPerBlock > 4096 ? prop.sharedMemPerBlock - 4096 : 0;
       ctx->lds_limit = v <= 0 ? 0 : std::min<size_t>(cap, v == 1 ? 52 * 1024 : (size_t)v);
+      ctx->lds_default = v == 1;
+      ctx->lds_cap = cap;
     }
     HIPCHK(hipHostMalloc((void**)&ctx->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_status, 16 * sizeof(int), hipHostMallocDefault));

@@ -8,6 +8,7 @@
 namespace fire {
 
 constexpr int kBlock = 256;   // threads per block of the per-atom kernels
+constexpr int kMaxTile = 512; // atoms (threads) per tile of the LDS-staged LJ pass; real-atom capacity is a multiple
 constexpr int kRed = 8;       // doubles per reduction record
 constexpr int kPartAtoms = 64; // reduction records exist for grids of up to ncap / kPartAtoms blocks
 // reduction record layout (one per block of the force pass); the last two
