@@ -1038,6 +1038,32 @@ __device__ __forceinline__ double ld_cohere(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// What the epilogue needs of atom i besides its force: the velocity, 1/m
+// (1 without masses) and the freeze mask.  Loaded when the pass starts (or
+// carried from the update the pass applies), so the epilogue at the end of a
+// block's life waits on no memory round trip.
+struct EpiIn {
+  double v[3];
+  double sc;
+  int mask;
+};
+__device__ __forceinline__ EpiIn epi_props(int i, bool valid, const Props& pr) {
+  EpiIn a{{0.0, 0.0, 0.0}, 1.0, 0};
+  if (valid) {
+    if (pr.sinv) a.sc = pr.sinv[i];
+    if (pr.fmask) a.mask = pr.fmask[i];
+  }
+  return a;
+}
+__device__ __forceinline__ EpiIn epi_load(int i, bool valid, const double* __restrict__ vel, int ncap,
+                                          const Props& pr) {
+  EpiIn a = epi_props(i, valid, pr);
+  if (valid)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.v[d] = vel[d * ncap + i];
+  return a;
+}
+
 // Force-pass epilogue of one atom: zero the frozen components, store F,
 // apply the velocity-Verlet second half kick, fold E, P, |F|^2, |v|^2,
 // max |F_i|^2, max |v_i|^2 (and, with masses, sum s v.F and sum s^2 F^2)
@@ -1045,24 +1071,22 @@ __device__ __forceinline__ double ld_cohere(const double* p) {
 // records in fixed order (second stage) and runs the FIRE control.
 template <int MAXB = kBlock>
 __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, double fy, double fz, double e,
-                                               double* __restrict__ frc, double* __restrict__ vel, int ncap,
-                                               double* __restrict__ part, const double* __restrict__ part_emb,
+                                               const EpiIn& in, double* __restrict__ frc, double* __restrict__ vel,
+                                               int ncap,
+                                               double* __restrict__ part, double emb,
                                                int rec, Ctrl* __restrict__ ctrl, double* __restrict__ trace,
                                                const Props& pr, bool check_viol = false) {
   double r[6] = {0, 0, 0, 0, 0, 0};
   double rm[2] = {0, 0};
   if (valid) {
-    if (pr.fmask) {
-      const int m = pr.fmask[i];
-      if (m & 1) fx = 0.0;
-      if (m & 2) fy = 0.0;
-      if (m & 4) fz = 0.0;
-    }
+    if (in.mask & 1) fx = 0.0;
+    if (in.mask & 2) fy = 0.0;
+    if (in.mask & 4) fz = 0.0;
     frc[i] = fx;
     frc[ncap + i] = fy;
     frc[2 * ncap + i] = fz;
-    double vx = vel[i], vy = vel[ncap + i], vz = vel[2 * ncap + i];
-    const double sc = pr.sinv ? pr.sinv[i] : 1.0;
+    double vx = in.v[0], vy = in.v[1], vz = in.v[2];
+    const double sc = in.sc;
     const double kick3 = ctrl->kick3 * sc;
     if (kick3 != 0.0) {
       vx += kick3 * fx;
@@ -1097,7 +1121,7 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
     // under every other block still running there.  Later kernels see the
     // rest of this pass's output through the kernel boundary.
     double* o = part + (size_t)kRed * rec;
-    const double vals[kCtl] = {r[0] + (part_emb ? part_emb[rec] : 0.0), r[1], r[2], r[3], r[4], r[5], rm[0], rm[1]};
+    const double vals[kCtl] = {r[0] + emb, r[1], r[2], r[3], r[4], r[5], rm[0], rm[1]};
     const int nv = pr.sinv ? kCtl : 6;
     for (int k = 0; k < nv; ++k) __hip_atomic_store(o + k, vals[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_s_waitcnt(0);
@@ -1344,17 +1368,21 @@ __device__ __forceinline__ Halo stage_halo_updated(const UpdArgs& ua, const UpdC
 }
 
 // The pending update of a pass's own atom i (< n): new position (returned,
-// w as in src) and velocity written to dst, skin test against the build
+// w as in src) and velocity written to dst (and kept in ep for the
+// epilogue; ep.sc must hold the atom's 1/m), skin test against the build
 // positions.
-__device__ __forceinline__ double4 own_update(const UpdArgs& ua, const UpdCoef& u, int i, int ncap, Ctrl* ctrl) {
+__device__ __forceinline__ double4 own_update(const UpdArgs& ua, const UpdCoef& u, int i, int ncap, Ctrl* ctrl,
+                                              EpiIn& ep) {
   const double4 p = ua.src.pos[i];
   double x[3] = {p.x, p.y, p.z};
   double v[3] = {ua.src.vel[i], ua.src.vel[ncap + i], ua.src.vel[2 * ncap + i]};
   const double f[3] = {ua.src.frc[i], ua.src.frc[ncap + i], ua.src.frc[2 * ncap + i]};
-  fire_step(u, x, v, f, ua.sinv ? ua.sinv[i] : 1.0);
+  fire_step(u, x, v, f, ep.sc);
   ua.dst.vel[i] = v[0];
   ua.dst.vel[ncap + i] = v[1];
   ua.dst.vel[2 * ncap + i] = v[2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ep.v[d] = v[d];
   const double4 xr = ua.xref[i];
   const double ex = x[0] - xr.x, ey = x[1] - xr.y, ez = x[2] - xr.z;
   if (ex * ex + ey * ey + ez * ez > ctrl->skin_half2) atomicOr(&ctrl->viol, 1);
@@ -1382,10 +1410,12 @@ __global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict
   T ax = 0, ay = 0, az = 0, ae = 0;
   Halo halo{nullptr, 0};
   double4 pi;
+  EpiIn ep;
   if constexpr (UPD) {
     const UpdCoef u = load_coef(ctrl);
+    ep = epi_props(i, valid, pr);
     if (valid) {
-      pi = own_update(ua, u, i, ncap, ctrl);
+      pi = own_update(ua, u, i, ncap, ctrl, ep);
       ua.dst.pos[i] = pi;
     } else {
       pi = ua.src.pos[i];
@@ -1395,6 +1425,7 @@ __global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict
     frc = ua.dst.frc;
     vel = ua.dst.vel;
   } else {
+    ep = epi_load(i, valid, vel, ncap, pr);
     if constexpr (LDS) halo = stage_halo<false>(pos, tl, b);
     pi = pos[i];
   }
@@ -1415,8 +1446,8 @@ __global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict
     az += fr * (T)dz;
     if constexpr (WE) ae += in ? (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh) : (T)0;
   });
-  force_epilogue<kMaxTile>(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, nullptr, b,
-                           ctrl, trace, pr, UPD);
+  force_epilogue<kMaxTile>(i, valid, (double)ax, (double)ay, (double)az, (double)ae, ep, frc, vel, ncap, part, 0.0,
+                           b, ctrl, trace, pr, UPD);
 }
 
 // Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
@@ -1440,7 +1471,8 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
   double4 pi;
   if constexpr (UPD) {
     const UpdCoef u = load_coef(ctrl);
-    pi = i < n ? own_update(ua, u, i, ncap, ctrl) : ua.src.pos[i];
+    EpiIn ep{{0.0, 0.0, 0.0}, (ua.sinv && i < n) ? ua.sinv[i] : 1.0, 0};
+    pi = i < n ? own_update(ua, u, i, ncap, ctrl, ep) : ua.src.pos[i];
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->cur = ua.dst_index;
     halo = stage_halo_updated(ua, u, tl, b, n, ncap);
     pos = ua.dst.pos;
@@ -1498,9 +1530,11 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
                                                         Props pr) {
   if (!pass_gate(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const Halo halo = LDS ? stage_halo<true>(pos, tl, b) : Halo{nullptr, 0};
   const int i = b * blockDim.x + threadIdx.x;
   const bool valid = i < n;
+  const EpiIn ep = epi_load(i, valid, vel, ncap, pr);
+  const double emb = threadIdx.x == 0 ? part_emb[b] : 0.0;  // the block's sum of F(rho), from the density pass
+  const Halo halo = LDS ? stage_halo<true>(pos, tl, b) : Halo{nullptr, 0};
   T ax = 0, ay = 0, az = 0, ae = 0;
   const double4 pi = pos[i];
   const T A = (T)pot.A, pr0 = (T)pot.pr0, qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in,
@@ -1529,8 +1563,8 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
     az += fr * (T)dz;
     if constexpr (WE) ae += in ? epair * ph * S : (T)0;
   });
-  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, frc, vel, ncap, part, part_emb, b, ctrl,
-                 trace, pr);
+  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, ep, frc, vel, ncap, part, emb, b,
+                 ctrl, trace, pr);
 }
 
 // Quadratic test well E = 1/2 sum k_d x_d^2 (no pairs).
@@ -1551,7 +1585,8 @@ __global__ __launch_bounds__(kBlock) void k_harmonic_force(const double4* __rest
     fz = -pot.k[2] * p.z;
     e = 0.5 * (pot.k[0] * p.x * p.x + pot.k[1] * p.y * p.y + pot.k[2] * p.z * p.z);
   }
-  force_epilogue(i, valid, fx, fy, fz, e, frc, vel, ncap, part, nullptr, b, ctrl, trace, pr);
+  force_epilogue(i, valid, fx, fy, fz, e, epi_load(i, valid, vel, ncap, pr), frc, vel, ncap, part, 0.0, b, ctrl,
+                 trace, pr);
 }
 
 // Neighbour indices of atom i one at a time (dummy padding included; callers
@@ -1709,6 +1744,10 @@ __global__ __launch_bounds__(kBlock) void k_sw_force(const double4* __restrict__
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int i = b * kAtoms + (int)threadIdx.x / G, g = threadIdx.x % G;
   const bool valid = i < n;
+  const bool lead = valid && g == 0;
+  // the lead lane's epilogue inputs and pair-term sums, loaded up front
+  const EpiIn ep = epi_load(i, lead, vel, ncap, pr);
+  const double4 fe = lead ? sw_fe[i] : make_double4(0.0, 0.0, 0.0, 0.0);
   double f[3] = {0, 0, 0}, e = 0.0;
   if (valid) {
     // Records are read in batches of kB, issued together: a batch of a
@@ -1774,15 +1813,13 @@ __global__ __launch_bounds__(kBlock) void k_sw_force(const double4* __restrict__
     f[2] += __shfl_xor(f[2], o, 64);
     e += __shfl_xor(e, o, 64);
   }
-  const bool lead = valid && g == 0;
   if (lead) {
-    const double4 fe = sw_fe[i];
     f[0] += fe.x;
     f[1] += fe.y;
     f[2] += fe.z;
     e += fe.w;
   }
-  force_epilogue(i, lead, f[0], f[1], f[2], e, frc, vel, ncap, part, nullptr, b, ctrl, trace, pr);
+  force_epilogue(i, lead, f[0], f[1], f[2], e, ep, frc, vel, ncap, part, 0.0, b, ctrl, trace, pr);
 }
 
 // ------------------------------------------------------- Hessian * u (FP64)
