@@ -2464,9 +2464,10 @@ size_t halo_bytes_per_atom(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_P
 // halo grows less than the tile (1.6 against 2 times), so fewer halo atoms
 // are staged per atom, and its one pass per evaluation runs 29.1 instead of
 // 30.3 us per launch on the 130,417-atom box.  The EAM form's two passes
-// measured faster on 256-atom tiles (104 against 110 us).  With 80 KB of
-// LDS per LJ tile block two blocks still fit a CU.
-constexpr size_t kLdsLj = 80 * 1024;
+// measured faster on 256-atom tiles (104 against 110 us).  78 KB of LDS per
+// LJ tile block (halos up to 3,328 atoms; the 130,417-atom box's largest is
+// 2,670) keeps two blocks, with their static LDS, within a CU's 160 KB.
+constexpr size_t kLdsLj = 78 * 1024;
 int tile_atoms(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_POT_LJ ? kMaxTile : kBlock; }
 
 // EAM-form tile blocks reserve 52 KB (three force-pass blocks per CU) while

@@ -194,6 +194,23 @@ def test_hvp_matches_oracle(ctx, name):
     assert np.abs(hu - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("name", ["lj_6", "gupta_5"])
+def test_halo_budget_too_small_falls_back_to_gathers(api, name, monkeypatch):
+    """An LDS budget below the tiles' halos (16 KB) makes the list build
+    report the overflow and the passes gather from global memory: the same
+    bits as the LDS-staged default."""
+    s = SMALL[name]()
+    c = api.Context(0, s.fire)
+    a = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 30)
+    c.close()
+    monkeypatch.setenv("FIRE_LDS", "16384")
+    c = api.Context(0, s.fire)
+    b = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 30)
+    c.close()
+    np.testing.assert_array_equal(a["pos"], b["pos"])
+    assert a["energy"] == b["energy"]
+
+
 @pytest.mark.parametrize("name", ["lj_6", "gupta_5", "gupta_slab", "gupta_cluster"])
 def test_global_gather_path_matches_oracle(api, name, monkeypatch):
     """The passes that gather neighbour positions from global memory (used
