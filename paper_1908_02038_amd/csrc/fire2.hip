@@ -494,16 +494,33 @@ __device__ __forceinline__ size_t lidx(int w, int k, int lane, int kcap) {
   return (((size_t)w * (kcap >> 2) + (k >> 2)) * 64 + lane) * 4 + (k & 3);
 }
 
+// FP32 copy of the slot positions relative to the grid origin, for the
+// neighbour search's distance tests.
+__global__ __launch_bounds__(kBlock) void k_pos_f32(const double4* __restrict__ pos, int nt, Grid g,
+                                                    float4* __restrict__ posf) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nt) {
+    const double4 p = pos[j];
+    posf[j] = make_float4((float)(p.x - g.lo[0]), (float)(p.y - g.lo[1]), (float)(p.z - g.lo[2]), 0.0f);
+  }
+}
+
 // Full neighbour list of every real atom: all slots (real or ghost) within
 // rcs, in ascending slot order, stored per wave of 64 atoms at
 // lidx(w, k, lane).  Each wave's lists are padded to a common length (a
 // multiple of 4, kept in wcnt[w]) with a dummy slot far outside the system,
 // so the force loops run a wave-uniform trip count and the padding fails
 // every cutoff test.  The grid covers every wave of the allocation.
-// flags[0] |= overlap, flags[1] = max count.
-__global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict__ pos, int n, Grid g,
+// The distance tests run in FP32 on posf against rcs2f, the square of rcs
+// widened by the FP32 rounding bound of the coordinates (set by the host):
+// every slot within rcs is in the list, and a few just beyond it may be,
+// which the passes treat like any entry beyond the cutoff (zero terms).
+// Half the bytes per candidate of FP64 positions, and half the loads.
+// flags[0] |= overlap (positions equal in FP64), flags[1] = max count.
+__global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict__ pos,
+                                                      const float4* __restrict__ posf, int n, Grid g,
                                                       const int* __restrict__ cell_rank,
-                                                      const int* __restrict__ start, double rcs2, int kcap,
+                                                      const int* __restrict__ start, float rcs2f, int kcap,
                                                       int dummy, int* __restrict__ nbr, int* __restrict__ wcnt,
                                                       int* __restrict__ flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -512,6 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
   bool overlap = false;
   if (i < n) {
     const double4 pi = pos[i];
+    const float4 pf = posf[i];
     const int c[3] = {real_cell_coord(pi.x, g, 0), real_cell_coord(pi.y, g, 1), real_cell_coord(pi.z, g, 2)};
     // stencil cells in ascending rank, so each list comes out sorted by slot:
     // lanes of a wave then read nearby (or identical) neighbours at each step.
@@ -554,18 +572,21 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
       // their latencies overlap; entries are appended in slot order
       constexpr int kG = 8;
       for (int j0 = start[cell], e = start[cell + 1]; j0 < e; j0 += kG) {
-        double4 pj[kG];
+        float4 pj[kG];
 #pragma unroll
-        for (int u = 0; u < kG; ++u) pj[u] = pos[min(j0 + u, e - 1)];
+        for (int u = 0; u < kG; ++u) pj[u] = posf[min(j0 + u, e - 1)];
 #pragma unroll
         for (int u = 0; u < kG; ++u) {
           const int j = j0 + u;
           if (j >= e) break;
           if (j == i) continue;
-          const double dx = pi.x - pj[u].x, dy = pi.y - pj[u].y, dz = pi.z - pj[u].z;
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == 0.0) overlap = true;
-          if (r2 < rcs2) {
+          const float dx = pf.x - pj[u].x, dy = pf.y - pj[u].y, dz = pf.z - pj[u].z;
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0f) {  // equal in FP32: compare the FP64 positions
+            const double4 q = pos[j];
+            if (q.x == pi.x && q.y == pi.y && q.z == pi.z) overlap = true;
+          }
+          if (r2 < rcs2f) {
             if (cnt < kcap) nbr[lidx(w, cnt, lane, kcap)] = j;
             ++cnt;
           }
@@ -2005,6 +2026,7 @@ struct fire_ctx {
   // between rebuilds, the second state set of the loop that folds the update
   // into the next pass (ctrl->cur says which set is current)
   double4 *pos = nullptr, *pos2 = nullptr;
+  float4* posf = nullptr;  // FP32 copy of the slot positions for the neighbour search
   double *vel = nullptr, *vel2 = nullptr, *frc = nullptr, *frc2 = nullptr;
   int *id = nullptr, *id2 = nullptr, *cell_of = nullptr, *order = nullptr;
   long long* key = nullptr;                  // in-cell ordering key per slot
@@ -2099,8 +2121,9 @@ int set_err(fire_ctx* c, int code, const std::string& msg) {
 void free_slots(fire_ctx* c) {
   hipFree(c->pos); hipFree(c->pos2); hipFree(c->cell_of); hipFree(c->order); hipFree(c->bucket);
   hipFree(c->srank); hipFree(c->key); hipFree(c->real_of); hipFree(c->gsrc); hipFree(c->gcode);
-  hipFree(c->gsrc2); hipFree(c->gcode2);
+  hipFree(c->gsrc2); hipFree(c->gcode2); hipFree(c->posf);
   c->pos = c->pos2 = nullptr;
+  c->posf = nullptr;
   c->cell_of = c->order = c->bucket = c->srank = c->real_of = nullptr;
   c->gsrc = c->gcode = c->gsrc2 = c->gcode2 = nullptr;
   c->key = nullptr;
@@ -2166,6 +2189,7 @@ int ensure_slots(fire_ctx* ctx, int nt, int keep = 0) {
   HIPCHK(dalloc(&ctx->gcode, cap));
   HIPCHK(dalloc(&ctx->gsrc2, cap));
   HIPCHK(dalloc(&ctx->gcode2, cap));
+  HIPCHK(dalloc(&ctx->posf, cap));
   ctx->tcap = cap;
   ctx->layout_version++;
   return FIRE_OK;
@@ -2498,7 +2522,17 @@ int build_lists(fire_ctx* ctx) {
   hipStream_t s = ctx->stream;
   const int n = ctx->n, dummy = ctx->tcap - 1;
   const int tile = tile_atoms(ctx), nt = nblocks(n, tile);
-  const double rcs2 = ctx->rcs * ctx->rcs;
+  // FP32 distance tests: coordinates relative to the grid origin lie within
+  // the grid's extent E, so each is off by at most E 2^-24 and a separation
+  // by twice that per axis; widen rcs by the resulting bound (and r^2 by the
+  // rounding of its own evaluation) so that no pair within rcs is missed
+  double ext = 0.0;
+  for (int k = 0; k < 3; ++k)
+    if (ctx->grid.inv[k] > 0) ext = std::max(ext, ctx->grid.n[k] / ctx->grid.inv[k]);
+  const double widen = 4.0 * std::sqrt(3.0) * ext * std::ldexp(1.0, -24);
+  const float rcs2f = (float)((ctx->rcs + widen) * (ctx->rcs + widen) * (1.0 + std::ldexp(1.0, -20)));
+  hipLaunchKernelGGL(k_pos_f32, dim3(nblocks(n + ctx->ng)), dim3(kBlock), 0, s, ctx->pos, n + ctx->ng, ctx->grid,
+                     ctx->posf);
   const bool was = ctx->use_lds;
   const size_t limit = lds_budget(ctx, tile);
   // no LDS tiles for the three-body potential (its force pass reads the
@@ -2519,8 +2553,8 @@ int build_lists(fire_ctx* ctx) {
       ctx->layout_version++;
     }
     HIPCHK(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), s));
-    hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, n, ctx->grid,
-                       ctx->cell_rank, ctx->cell_start, rcs2, ctx->kcap, dummy, ctx->nbr, ctx->wcnt, ctx->flags);
+    hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, ctx->posf, n, ctx->grid,
+                       ctx->cell_rank, ctx->cell_start, rcs2f, ctx->kcap, dummy, ctx->nbr, ctx->wcnt, ctx->flags);
     if (hcap >= 64) {
       if (tile == kMaxTile)
         hipLaunchKernelGGL(k_tile_halo<kMaxTile>, dim3(nt), dim3(kMaxTile), 0, s, ctx->srank, ctx->cell_start,
