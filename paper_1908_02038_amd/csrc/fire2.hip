@@ -2075,7 +2075,8 @@ struct fire_ctx {
   int scan_cap = 0;
   int* h_flags = nullptr;     // pinned
   Ctrl* h_ctrl = nullptr;     // pinned
-  int* h_status = nullptr;    // pinned, 2 slots x 8 ints
+  unsigned long long* h_poll = nullptr;  // pinned, coherent: status | pause << 32, written by k_poll
+  unsigned long long* d_poll = nullptr;  // its device address
   double* h_zero = nullptr;   // pinned scalar for small uploads
   double* trace = nullptr;
   long long trace_cap = 0;
@@ -2839,6 +2840,18 @@ void launch_update(fire_ctx* ctx, hipStream_t s) {
 
 // One FIRE iteration; energies only when a trace is recorded.
 // parity: the state set the iteration starts from (iterations alternate).
+// Status and pause bits of the loop, written to coherent host memory at the
+// end of every graph replay: the host polls the word after the replay's event
+// instead of enqueueing a device-to-host copy between replays.
+__global__ void k_poll(const Ctrl* __restrict__ ctrl, unsigned long long* __restrict__ poll) {
+  if (threadIdx.x == 0) {
+    const unsigned st = (unsigned)__hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned pa = (unsigned)__hip_atomic_load(&ctrl->pause, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(poll, (unsigned long long)st | ((unsigned long long)pa << 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 void launch_iteration(fire_ctx* ctx, hipStream_t s, int prec, int parity) {
   if (fold_update(ctx)) {
     if (ctx->trace) launch_pairs<true>(ctx, s, prec, parity);
@@ -2861,6 +2874,7 @@ int graph_for(fire_ctx* ctx, int prec, hipGraphExec_t* out) {
   hipGraph_t g;
   HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
   for (int k = 0; k < ctx->graph_k; ++k) launch_iteration(ctx, ctx->cap_stream, prec, k & 1);  // graph_k is even
+  hipLaunchKernelGGL(k_poll, dim3(1), dim3(64), 0, ctx->cap_stream, ctx->ctrl, ctx->d_poll);
   HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
   if (getenv("FIRE_DEBUG")) {  // dynamic LDS of the captured kernel nodes
     size_t nn = 0;
@@ -3060,32 +3074,32 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
   launch_forces(ctx, s, prec);  // evaluation 0 and the set-up of iteration 1
   // graph length: short for small systems (launch-bound), longer for large ones
   ctx->graph_k = ctx->n < 20000 ? 32 : 16;
-  int* st = ctx->h_status;
-  const int poll_bytes = 32;
   for (;;) {
-    // two replays in flight; poll the older one
+    // two replays in flight; after the older one's event, read the status
+    // word that the last node of a replay writes to host memory (the older
+    // replay's, or the newer one's if that has finished too: either way the
+    // state the stream is in once the host's next work runs)
     hipGraphExec_t g;
     rc = graph_for(ctx, prec, &g);
     if (rc) return rc;
     HIPCHK(hipGraphLaunch(g, s));
-    HIPCHK(hipMemcpyAsync(st, ctx->ctrl, poll_bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(ctx->ev[0], s));
     int cur = 0;
+    unsigned long long word = 0;
     for (;;) {
       HIPCHK(hipGraphLaunch(g, s));
-      HIPCHK(hipMemcpyAsync(st + 8 * (cur ^ 1), ctx->ctrl, poll_bytes, hipMemcpyDeviceToHost, s));
       HIPCHK(hipEventRecord(ctx->ev[cur ^ 1], s));
       HIPCHK(hipEventSynchronize(ctx->ev[cur]));
-      if (st[8 * cur] != ST_RUNNING) break;
+      word = __atomic_load_n(ctx->h_poll, __ATOMIC_ACQUIRE);
+      if ((int)(unsigned)word != ST_RUNNING) break;
       cur ^= 1;
     }
     materialize(ctx, s);
-    // the older replay ended stopped or paused, so every kernel of the newer
-    // one exited at its gate: its status equals the older one's, which the
-    // host already holds (no wait here; the next host read of device data
-    // synchronises)
-    const int status = st[8 * cur];
-    const int pause = st[8 * cur + 1];
+    // the replay seen ended stopped or paused, so every later kernel exits at
+    // its gate and the status stays as read (no wait here; the next host read
+    // of device data synchronises)
+    const int status = (int)(unsigned)word;
+    const int pause = (int)(unsigned)(word >> 32);
     if (status != ST_PAUSED) break;
     if (pause & PAUSE_PRECISION) {  // before the next update: switch pair precision
       prec = 0;
@@ -3314,7 +3328,8 @@ int fire_init(fire_ctx** out, int device, const fire_params* params) {
       ctx->lds_cap = cap;
     }
     HIPCHK(hipHostMalloc((void**)&ctx->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&ctx->h_status, 16 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_poll, sizeof(unsigned long long), hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void**)&ctx->d_poll, ctx->h_poll, 0));
     HIPCHK(hipHostMalloc((void**)&ctx->h_zero, sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming));
@@ -3349,7 +3364,7 @@ void fire_finalize(fire_ctx* ctx) {
   hipFree(ctx->trace);
   if (ctx->h_flags) hipHostFree(ctx->h_flags);
   if (ctx->h_ctrl) hipHostFree(ctx->h_ctrl);
-  if (ctx->h_status) hipHostFree(ctx->h_status);
+  if (ctx->h_poll) hipHostFree(ctx->h_poll);
   if (ctx->h_zero) hipHostFree(ctx->h_zero);
   for (int k = 0; k < 2; ++k)
     if (ctx->ev[k]) hipEventDestroy(ctx->ev[k]);
