@@ -35,6 +35,12 @@ namespace fire {
 namespace bat {
 
 constexpr int kMaxAtoms = 4096;  // per system (LDS holds its positions)
+// Iterations per system and launch.  A launch ends when every system has
+// advanced by up to kChunk iterations, so every launch waits for its slowest
+// system: 1,024 instead of 256 lets teams carry on with further systems while
+// a long relaxation runs (512 EAM-form systems: 283 instead of 341 ms; the
+// bound is the longest single relaxation on one CU, about 240 ms there).
+constexpr int kChunk = 1024;
 constexpr int kMaxCells = 1024;  // per-system cell grid in LDS
 
 struct SysDesc {
@@ -892,7 +898,7 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     // ---- autotune the team shape (timed on this batch, state reset afterwards)
     const int prec0 = c0[0].precision;
     const std::string key = tune_key(P, prec0, nsys, maxn);
-    Config cfg{1024, 256};
+    Config cfg{1024, kChunk};
     if (!getenv("FIRE_BATCH_TEAM")) {
       auto it = w->tuned.find(key);
       if (it != w->tuned.end()) {
@@ -920,13 +926,14 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
           rc = reset_state(ctx, w, c0, s);
           if (rc) return rc;
         }
-        cfg.chunk = 256;
+        cfg.chunk = kChunk;
         w->tuned[key] = cfg;
         save_cache(w);
       }
     } else {
       cfg.team = atoi(getenv("FIRE_BATCH_TEAM")) == 512 ? 512 : 1024;
     }
+    if (const char* e = getenv("FIRE_BATCH_CHUNK")) cfg.chunk = std::max(1, atoi(e));
 
     // ---- graph: queue reset, persistent kernel, running count, poll copy
     hipGraph_t graph;
