@@ -140,3 +140,22 @@ def test_device_entry_point_matches_host_entry_point(api):
         assert res_d[k]["iterations"] == res_h[k]["iterations"]
         assert res_d[k]["energy"] == res_h[k]["energy"]
         assert np.array_equal(got[offs[k]:offs[k + 1]], pos_h[k])
+
+
+def test_chunk_length_does_not_change_results(api, monkeypatch):
+    """Systems advance by at most a chunk of iterations per launch, and the
+    launch is replayed until none is running: short chunks (many replays,
+    every system suspended and resumed often) give the bits of one long
+    chunk."""
+    systems = small_batch(nsys=5, seed=11)
+    pot = systems[0].potential
+    out = []
+    for chunk in ("7", "100000"):
+        monkeypatch.setenv("FIRE_BATCH_CHUNK", chunk)
+        c = api.Context(0, systems[0].fire)
+        out.append(c.fire_minimize_batched([(s.pos, s.box) for s in systems], pot, 1e-6, 20000))
+        c.close()
+    (pa, ra), (pb, rb) = out
+    for a, b, x, y in zip(pa, pb, ra, rb):
+        np.testing.assert_array_equal(a, b)
+        assert x["iterations"] == y["iterations"] and x["energy"] == y["energy"] and x["stop"] == y["stop"]
