@@ -3074,6 +3074,7 @@ int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps,
   launch_forces(ctx, s, prec);  // evaluation 0 and the set-up of iteration 1
   // graph length: short for small systems (launch-bound), longer for large ones
   ctx->graph_k = ctx->n < 20000 ? 32 : 16;
+  if (const char* e = getenv("FIRE_GRAPH_K")) ctx->graph_k = std::max(2, atoi(e) & ~1);  // even
   for (;;) {
     // two replays in flight; after the older one's event, read the status
     // word that the last node of a replay writes to host memory (the older
