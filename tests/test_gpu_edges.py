@@ -122,3 +122,41 @@ def test_context_reused_across_growing_and_shrinking_systems(api):
         f.close()
         np.testing.assert_array_equal(r["pos"], fresh["pos"])
         assert r["energy"] == fresh["energy"]
+
+
+@pytest.mark.parametrize("case", ["wide_box", "far_cluster", "cutoff_shell"])
+def test_fp32_neighbour_search_misses_no_pair(api, case):
+    """The neighbour search tests distances in FP32 (coordinates relative to
+    the cell grid's origin) against a cutoff widened by their rounding bound.
+    Cases where that matters: a sparse gas in a 240-sigma periodic box (large
+    coordinates), a crystal centred 1e4 sigma from the origin with free
+    boundaries, and pairs placed within 1e-9 of the list cutoff rc + skin and
+    of rc itself.  Forces must equal the brute-force oracle's."""
+    rng = np.random.default_rng(91)
+    pot = inputs.lj_potential(rc=2.5)
+    if case == "wide_box":
+        L = 240.0
+        pos = rng.uniform(0.0, L, (3000, 3))
+        box = inputs.Box((0.0,) * 3, (L,) * 3, (1, 1, 1))
+    elif case == "far_cluster":
+        s = inputs.lj_box(4, nvac=3, noise=0.05, seed=92, periodic=(0, 0, 0))
+        pos = s.pos + 1.0e4
+        box = inputs.Box((0.0,) * 3, (1.0,) * 3, (0, 0, 0))
+    else:
+        # pairs along x at separations just inside and outside rc and the
+        # default list cutoff 1.12 rc, far apart from each other
+        seps = [2.5 - 1e-9, 2.5 + 1e-9, 2.8 - 1e-9, 2.8 + 1e-9, 2.0, 1.2]
+        pos = []
+        for k, d in enumerate(seps):
+            base = np.array([10.0 * k, 3.0 * k, -2.0 * k])
+            pos += [base, base + [d, 0.0, 0.0]]
+        pos = np.array(pos)
+        box = inputs.Box((0.0,) * 3, (1.0,) * 3, (0, 0, 0))
+    pos = np.array(pos, dtype=np.float64)
+    c = api.Context(0, inputs.workload_fire(0.001, 1.0))
+    e, f = c.fire_energy_forces(pos, box, pot)
+    c.close()
+    e_ref, f_ref = oracle.energy_forces(pos, box, pot)
+    scale = max(1.0, np.abs(f_ref).max())
+    assert abs(e - e_ref) <= 1e-12 * max(1.0, abs(e_ref))
+    assert np.abs(f - f_ref).max() <= 1e-12 * scale
