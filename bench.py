@@ -290,6 +290,74 @@ def cpu_baseline(s, budget_s: float):
     }
 
 
+def relax_once(ctx, pos0_dev, s, max_steps: int, fire: dict):
+    """One relaxation of system s with FIRE parameters `fire` (after one
+    untimed run with the same parameters): the result and its wall time."""
+    import torch
+    ctx.fire_set_params(fire)
+    work = torch.empty_like(pos0_dev)
+    work.copy_(pos0_dev)
+    ctx.fire_minimize_dev(work, s.box, s.potential, s.tol, max_steps)
+    work.copy_(pos0_dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.fire_minimize_dev(work, s.box, s.potential, s.tol, max_steps)
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def study_integrators(args):
+    """Force evaluations to the workload's tolerance with FIRE 2.0 under each
+    integrator of Sec. 3.3 (Algorithms 3, 4 and 6) and with the original FIRE
+    (Algorithm 1): the paper's integrator comparison and its FIRE / FIRE 2.0
+    ratios, on the synthetic workloads."""
+    import torch
+    from paper_1908_02038_amd import api
+    rows = []
+    for name in ("lj_bulk", "gupta_bulk", "si_slab"):
+        s = make_system(name)
+        pos0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+        ctx = api.Context(0, s.fire, precision="fp64")
+        for variant, integrator in (("fire2", "eulerimplicit"), ("fire2", "eulerexplicit"), ("fire2", "verlet"),
+                                    ("fire1", "eulerimplicit"), ("fire1", "eulerexplicit")):
+            r, dt = relax_once(ctx, pos0, s, args.max_steps, dict(s.fire, variant=variant, integrator=integrator))
+            rows.append({"workload": name, "variant": variant, "integrator": integrator, "stop": r["stop"],
+                         "iterations": r["iterations"], "force_evals": r["force_evals"], "fmax": r["fmax"],
+                         "energy_per_atom": r["energy_per_atom"], "ms": dt * 1e3})
+            log(f"[study] {name} {variant} {integrator}: {r['stop']} after {r['force_evals']} evaluations, "
+                f"{dt * 1e3:.1f} ms, E/N {r['energy_per_atom']:.12f}")
+        ctx.close()
+    return {"study": "integrators", "max_steps": args.max_steps, "rows": rows}
+
+
+def study_sweep(args):
+    """FIRE 2.0 parameter study of Sec. 4 on the Si slab (the stand-in for the
+    paper's Si vacancy case): force evaluations to the tolerance as a function
+    of alpha0 for several tmax at dt = 1 fs, and of tmax for several dt at
+    alpha0 = 0.15.  Runs that stop without converging report their stop."""
+    import torch
+    from paper_1908_02038_amd import api
+    s = make_system("si_slab")
+    pos0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    ctx = api.Context(0, s.fire, precision="fp64")
+    rows = []
+
+    def run(alpha0, tmax, dt):
+        r, wall = relax_once(ctx, pos0, s, args.sweep_max_steps, dict(s.fire, alpha0=alpha0, tmax=tmax, dt_start=dt))
+        rows.append({"alpha0": alpha0, "tmax": tmax, "dt_ps": dt, "stop": r["stop"], "force_evals": r["force_evals"],
+                     "ms": wall * 1e3})
+        log(f"[study] alpha0 {alpha0} tmax {tmax} dt {dt * 1e3:.1f} fs: {r['stop']} after {r['force_evals']} evaluations")
+
+    for tmax in (2, 4, 6, 10, 15, 20):
+        for alpha0 in (0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.4):
+            run(alpha0, tmax, 0.001)
+    for dt in (0.0005, 0.002, 0.004):
+        for tmax in (2, 4, 6, 8, 10, 12, 15, 20):
+            run(0.15, tmax, dt)
+    ctx.close()
+    return {"study": "sweep", "workload": "si_slab", "max_steps": args.sweep_max_steps, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +375,10 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the dominant force pass (reps launches) and a plain copy of known size; "
                          "for hardware-counter runs")
+    ap.add_argument("--study", choices=["integrators", "sweep"],
+                    help="instead of the bench line: one JSON line of the integrator comparison or the parameter "
+                         "sweep")
+    ap.add_argument("--sweep-max-steps", type=int, default=20000)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -325,6 +397,10 @@ def main():
     pos0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
     if args.kernel_only:
         kernel_only(args, s, pos0)
+        return
+    if args.study:
+        out = study_integrators(args) if args.study == "integrators" else study_sweep(args)
+        print(json.dumps(out), flush=True)
         return
 
     # ---- FP64 plain path (headline)
