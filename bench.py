@@ -308,7 +308,7 @@ def relax_once(ctx, pos0_dev, s, max_steps: int, fire: dict):
 
 def study_integrators(args):
     """Force evaluations to the workload's tolerance with FIRE 2.0 under each
-    integrator of Sec. 3.3 (Algorithms 3, 4 and 6) and with the original FIRE
+    integrator of Sec. 3.1 (Algorithms 3, 4 and 6) and with the original FIRE
     (Algorithm 1): the paper's integrator comparison and its FIRE / FIRE 2.0
     ratios, on the synthetic workloads."""
     import torch
@@ -331,7 +331,7 @@ def study_integrators(args):
 
 
 def study_sweep(args):
-    """FIRE 2.0 parameter study of Sec. 4 on the Si slab (the stand-in for the
+    """FIRE 2.0 parameter study of Sec. 5.4 (Fig. 3) on the Si slab (the stand-in for the
     paper's Si vacancy case): force evaluations to the tolerance as a function
     of alpha0 for several tmax at dt = 1 fs, and of tmax for several dt at
     alpha0 = 0.15.  Runs that stop without converging report their stop."""
