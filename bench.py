@@ -358,6 +358,52 @@ def study_sweep(args):
     return {"study": "sweep", "workload": "si_slab", "max_steps": args.sweep_max_steps, "rows": rows}
 
 
+def study_batched_sweep(args):
+    """The parameter study as one batched launch: 512 copies of a 2,042-atom
+    EAM-form crystal with a vacancy-rich, noisy start, each relaxed with its own
+    (alpha0, tmax, dt) from an 8 x 8 x 8 grid (per-system fire_params), against
+    a sample of the same runs through the single-system path."""
+    import torch
+    from paper_1908_02038_amd import api, inputs
+    s = inputs.gupta_box(8, nvac=6, noise=0.08, seed=13)
+    alphas = (0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4)
+    tmaxs = (2, 4, 6, 8, 10, 12, 15, 20)
+    dts = (0.0005, 0.001, 0.0015, 0.002, 0.0025, 0.003, 0.0035, 0.004)
+    grid = [(a, t, d) for d in dts for t in tmaxs for a in alphas]
+    per = [dict(s.fire, alpha0=a, tmax=t, dt_start=d) for a, t, d in grid]
+    n = len(s.pos)
+    src = torch.tensor(np.concatenate([s.pos] * len(grid)), dtype=torch.float64, device="cuda")
+    offs = np.arange(len(grid) + 1, dtype=np.int64) * n
+    boxes = [s.box] * len(grid)
+    ctx = api.Context(0, s.fire)
+    work = src.clone()
+    ctx.fire_minimize_batched_dev(work, offs, boxes, s.potential, s.tol, args.sweep_max_steps, per_sys=per)
+    work.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.fire_minimize_batched_dev(work, offs, boxes, s.potential, s.tol, args.sweep_max_steps, per_sys=per)
+    torch.cuda.synchronize()
+    dt_batch = time.perf_counter() - t0
+    ctx.close()
+    # the single-system path on every 32nd grid point
+    ctx = api.Context(0, s.fire, precision="fp64")
+    pos0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    sample, t_plain, same = list(range(0, len(grid), 32)), 0.0, 0
+    for k in sample:
+        r, wall = relax_once(ctx, pos0, s, args.sweep_max_steps, per[k])
+        t_plain += wall
+        same += r["force_evals"] == res[k]["force_evals"]
+    ctx.close()
+    rows = [{"alpha0": a, "tmax": t, "dt_ps": d, "stop": r["stop"], "force_evals": r["force_evals"]}
+            for (a, t, d), r in zip(grid, res)]
+    log(f"[study] batched sweep: {len(grid)} relaxations of {n} atoms in {dt_batch * 1e3:.1f} ms; single-system path "
+        f"{t_plain / len(sample) * 1e3:.1f} ms per relaxation on {len(sample)} of them "
+        f"({same} with the same evaluation count)")
+    return {"study": "batched_sweep", "atoms": n, "systems": len(grid), "ms_batch": dt_batch * 1e3,
+            "ms_plain_per_relaxation": t_plain / len(sample) * 1e3, "plain_sample": len(sample),
+            "plain_same_evals": same, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,7 +421,7 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the dominant force pass (reps launches) and a plain copy of known size; "
                          "for hardware-counter runs")
-    ap.add_argument("--study", choices=["integrators", "sweep"],
+    ap.add_argument("--study", choices=["integrators", "sweep", "batched_sweep"],
                     help="instead of the bench line: one JSON line of the integrator comparison or the parameter "
                          "sweep")
     ap.add_argument("--sweep-max-steps", type=int, default=20000)
@@ -399,7 +445,8 @@ def main():
         kernel_only(args, s, pos0)
         return
     if args.study:
-        out = study_integrators(args) if args.study == "integrators" else study_sweep(args)
+        out = {"integrators": study_integrators, "sweep": study_sweep,
+               "batched_sweep": study_batched_sweep}[args.study](args)
         print(json.dumps(out), flush=True)
         return
 
