@@ -428,8 +428,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(the multi-GPU decomposition is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the FIRE path runs on one GPU only; --gpus must be 1 "
+                          "(a multi-GPU decomposition is designed but not built)"}))
         sys.exit(2)
 
     import torch

@@ -92,8 +92,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() or "
-                           "python paper_1908_02038_amd/build.py")
+        raise RuntimeError(f"{path} is not built: run python paper_1908_02038_amd/build.py")
     try:
         import torch  # noqa: F401
     except ImportError:  # pragma: no cover
