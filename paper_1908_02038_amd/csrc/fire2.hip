@@ -2054,6 +2054,7 @@ struct fire_ctx {
   size_t lds_atoms = 0, lds_limit = 0;  // halo capacity per tile block; byte limit per block
   bool lds_default = true;              // no explicit limit: the LJ pass's 512-atom tiles get kLdsLj
   size_t lds_cap = 0;                   // the device's LDS per block, less a margin for static LDS
+  size_t lds_boost = 0;                 // default reservation raised for halos that outgrew it (per call)
   int tile = kBlock;                    // atoms per tile of the current lists' halos
   double *part = nullptr, *part_emb = nullptr, *bbox_part = nullptr;
   // per-atom properties of the running minimisation: 1/m and freeze bits in
@@ -2320,6 +2321,7 @@ int prepare_system(fire_ctx* ctx, const fire_box* b, const fire_potential* p) {
   if (p->kind == FIRE_POT_HARMONIC) skin = 0.0;
   ctx->skin = skin;
   ctx->rcs = d.rc + skin;
+  ctx->lds_boost = 0;
   return FIRE_OK;
 }
 
@@ -2509,9 +2511,10 @@ constexpr long long kL2Atoms = 8LL * (4 << 20) / 96;
 
 size_t lds_budget(const fire_ctx* ctx, int tile) {
   if (!ctx->lds_default) return ctx->lds_limit;
-  if (tile == kMaxTile) return std::min(kLdsLj, ctx->lds_cap);
-  if (ctx->pot.kind == FIRE_POT_GUPTA && ctx->n > kL2Atoms) return std::min(kLdsEamLarge, ctx->lds_cap);
-  return ctx->lds_limit;
+  size_t d = ctx->lds_limit;
+  if (tile == kMaxTile) d = std::min(kLdsLj, ctx->lds_cap);
+  else if (ctx->pot.kind == FIRE_POT_GUPTA && ctx->n > kL2Atoms) d = std::min(kLdsEamLarge, ctx->lds_cap);
+  return std::max(d, std::min(ctx->lds_boost, ctx->lds_cap));
 }
 
 
@@ -2579,6 +2582,19 @@ int build_lists(fire_ctx* ctx) {
     hipFree(ctx->nbr16);
     ctx->nbr16 = nullptr;
     ctx->layout_version++;
+  }
+  // a tile's halo outgrew the default reservation: reserve room for the
+  // largest halo and an eighth more (1 KB steps) while that fits a block's
+  // LDS, and build again, instead of falling back to global gathers (fewer
+  // tile blocks per CU cost far less).  The reservation only grows, so this
+  // ends.
+  if (hcap >= 64 && (ctx->h_flags[3] & 4) && ctx->lds_default) {
+    const size_t atoms = (size_t)ctx->h_flags[2] + 1;
+    const size_t need = ((atoms + atoms / 8) * halo_bytes_per_atom(ctx) + 1023) & ~(size_t)1023;
+    if (need > limit && need <= ctx->lds_cap && need > ctx->lds_boost) {
+      ctx->lds_boost = need;
+      return build_lists(ctx);
+    }
   }
   ctx->use_lds = false;
   if (hcap >= 64 && !(ctx->h_flags[3] & 4)) {
@@ -3318,7 +3334,7 @@ int fire_init(fire_ctx** out, int device, const fire_params* params) {
     HIPCHK(hipMalloc((void**)&ctx->flags, 8 * sizeof(int)));
     HIPCHK(hipHostMalloc((void**)&ctx->h_flags, 8 * sizeof(int), hipHostMallocDefault));
     // LDS-staged pair passes with at most 52 KB per 256-atom tile block
-    // (three blocks per CU) and 80 KB per 512-atom LJ tile block (two);
+    // (three blocks per CU) and 78 KB per 512-atom LJ tile block (two);
     // FIRE_LDS=0: global gathers only; FIRE_LDS=<bytes>: that limit for both
     {
       const char* e = getenv("FIRE_LDS");

@@ -211,6 +211,33 @@ def test_halo_budget_too_small_falls_back_to_gathers(api, name, monkeypatch):
     assert a["energy"] == b["energy"]
 
 
+def test_outgrown_halo_reservation_grows_instead_of_gathering(api, monkeypatch, capfd):
+    """With a wider skin (0.25 rc) the 253,440-atom EAM-form bulk has tile
+    halos beyond the default 52 KB reservation (1,664 atoms).  The list build
+    then reserves room for them and keeps the LDS-staged passes; they give
+    the same bits as the global-gather passes."""
+    s = inputs.gupta_bulk()
+    skin = 0.25 * s.potential["r_out"]
+    monkeypatch.setenv("FIRE_DEBUG", "1")
+    c = api.Context(0, s.fire, skin=skin)
+    e_l, f_l = c.fire_energy_forces(s.pos, s.box, s.potential)
+    r_l = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 10)
+    c.close()
+    import re
+    err = capfd.readouterr().err
+    caps = [int(m) for m in re.findall(r"LDS for (\d+) atoms per tile block", err)]
+    assert len(caps) >= 2 and min(caps) > 1664, err[-2000:]
+    monkeypatch.delenv("FIRE_DEBUG")
+    monkeypatch.setenv("FIRE_LDS", "0")
+    c = api.Context(0, s.fire, skin=skin)
+    e, f = c.fire_energy_forces(s.pos, s.box, s.potential)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 10)
+    c.close()
+    assert e == e_l and np.array_equal(f, f_l)
+    np.testing.assert_array_equal(r["pos"], r_l["pos"])
+    assert r["energy"] == r_l["energy"]
+
+
 @pytest.mark.parametrize("name", ["lj_6", "gupta_5", "gupta_slab", "gupta_cluster"])
 def test_global_gather_path_matches_oracle(api, name, monkeypatch):
     """The passes that gather neighbour positions from global memory (used
