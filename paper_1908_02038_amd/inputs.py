@@ -166,8 +166,12 @@ def lj_small(seed: int = 0) -> System:
 
 def lj_bulk(seed: int = 1, ncell: int = 32) -> System:
     nsite = 4 * ncell ** 3
+    # neighbour-list skin 0.15 rc (0.375 sigma) instead of the library's
+    # default 0.12 rc: three list builds per relaxation instead of four, and
+    # a 16-cell grid per axis for this box
+    fire = dict(workload_fire(0.005, 1.0), skin=0.15 * 2.5)
     return fcc_box_system("lj_bulk", (ncell,) * 3, 1.5874, int(round(0.005 * nsite)), 0.05, "gauss",
-                          seed, lj_potential(), workload_fire(0.005, 1.0), 1e-6)
+                          seed, lj_potential(), fire, 1e-6)
 
 
 def gupta_bulk(seed: int = 2, ncell: int = 40, convention: str = "rgl") -> System:
