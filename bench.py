@@ -503,7 +503,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "atoms": n, "potential": kind, "fmax_tol": s.tol,
                    "fire": {k: s.fire[k] for k in ("dt_start", "tmax", "alpha0", "delaystep", "dtgrow",
-                                                   "dtshrink", "integrator")}},
+                                                   "dtshrink", "integrator")},
+                   "neighbour_skin": s.fire.get("skin", "library default: 0.12 x cutoff")},
         "steps_per_s": iters / dt,
         "iterations_per_relaxation": r["iterations"],
         "stop": r["stop"],
