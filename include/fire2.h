@@ -132,7 +132,9 @@ typedef struct {
   double mixed_switch; /* FIRE_MIXED: criterion value below which pair terms go to FP64;
                           <= 0 selects 100 * tol */
   double skin;         /* neighbour-list skin in length units; <= 0 selects 0.12 * cutoff,
-                          clamped to fit the box */
+                          clamped to fit the box.  Affects speed only: lists are rebuilt
+                          as soon as an atom has moved more than skin/2, so every pair
+                          within the cutoff is always seen */
   double dmax;         /* > 0: displacement cap (the maximum atomic displacement per step of
                           the melt case, Sec. 5.3).  The drift uses the step
                           min(dt, dmax / max_i |v_i|), v the velocity it moves the atoms
