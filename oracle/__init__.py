@@ -11,6 +11,13 @@ Functions (paper: Guenole et al., FIRE 2.0):
   sw_energy_direct  Stillinger-Weber E by a plain pair and triplet loop.
   sample_forces   the same for selected atoms, each computed on its own.
   hvp             analytic Hessian-vector product of the same energy.
+  pair_counts, pair_list
+                  the pair set every sum above runs over (atoms closer than
+                  the cutoff under the minimum image), per atom in index order.
+  cells           context manager: find the pair set through a cell grid
+                  instead of testing every pair.  The pairs and their order
+                  are the same, so every result is bit-identical (pinned by
+                  tests); only large systems get faster.
   fire_minimize   FIRE 2.0 (Algorithm 2) with semi-implicit Euler and mixing
                   after the kick (Algorithm 4), Table 1 parameters, Sec. 3.4
                   stop tests; original FIRE (Algorithm 1) and the explicit
@@ -79,7 +86,7 @@ def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (-O2, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-msse4.1", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -104,6 +111,12 @@ def _load():
         lib.oracle_fire_minimize_ex.argtypes = [ctypes.c_long, dp, P(_Box), P(_Pot), P(_Fire), ctypes.c_void_p, dp,
                                                 ctypes.c_double, ctypes.c_long, P(_Result), dp, dp]
         lib.oracle_sw_energy_direct.argtypes = [ctypes.c_long, dp, P(_Box), P(_Pot), dp]
+        lib.oracle_pair_counts.argtypes = [ctypes.c_long, dp, P(_Box), ctypes.c_double, P(ctypes.c_long),
+                                           P(ctypes.c_long)]
+        lib.oracle_pair_list.argtypes = [ctypes.c_long, dp, P(_Box), ctypes.c_double, ctypes.c_long,
+                                         P(ctypes.c_long), P(ctypes.c_long), P(ctypes.c_long)]
+        lib.oracle_set_cells.argtypes = [ctypes.c_int]
+        lib.oracle_get_cells.restype = ctypes.c_int
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -116,6 +129,56 @@ def threads() -> int:
 
 def set_threads(n: int) -> None:
     _load().oracle_set_threads(int(n))
+
+
+class cells:
+    """Within the block, the oracle finds pairs through a cell grid (same
+    pairs, same order, same bits as testing every pair)."""
+
+    def __init__(self, on: bool = True):
+        self.on = bool(on)
+
+    def __enter__(self):
+        lib = _load()
+        self.prev = lib.oracle_get_cells()
+        lib.oracle_set_cells(int(self.on))
+        return self
+
+    def __exit__(self, *exc):
+        _load().oracle_set_cells(self.prev)
+        return False
+
+
+def _lptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
+
+
+def pair_counts(pos, box, rc):
+    """Number of partners of each atom closer than rc (minimum image)."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    cnt = np.zeros(n, dtype=np.int64)
+    tot = ctypes.c_long()
+    b = _box(box)
+    _check(lib.oracle_pair_counts(n, _ptr(pos), ctypes.byref(b), float(rc), _lptr(cnt), ctypes.byref(tot)))
+    return cnt
+
+
+def pair_list(pos, box, rc):
+    """(start[n+1], idx): atom i's partners closer than rc are
+    idx[start[i]:start[i+1]], in increasing order."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    start = np.zeros(n + 1, dtype=np.int64)
+    tot = ctypes.c_long()
+    b = _box(box)
+    _check(lib.oracle_pair_list(n, _ptr(pos), ctypes.byref(b), float(rc), 0, _lptr(start), None, ctypes.byref(tot)))
+    idx = np.zeros(max(tot.value, 1), dtype=np.int64)
+    _check(lib.oracle_pair_list(n, _ptr(pos), ctypes.byref(b), float(rc), idx.shape[0], _lptr(start), _lptr(idx),
+                                ctypes.byref(tot)))
+    return start, idx[: tot.value]
 
 
 def _ptr(a):

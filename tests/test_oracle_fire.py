@@ -322,3 +322,123 @@ def test_dmax_keeps_a_hot_start_finite():
     r = oracle.fire_minimize(s.pos, s.box, s.potential, fire, 0.0, 400, trace=True)
     assert (r["trace"][1:, 7] == -1).sum() > 1
     assert np.isfinite(r["pos"]).all() and r["energy"] < oracle.energy_forces(s.pos, s.box, s.potential)[0]
+
+
+# ---- the placement of the mixing, hand-evaluated on a 2-D anisotropic well
+# (k = (1, 10)), where a velocity built from two different forces is not
+# parallel to the force and the mixing v <- (1 - a) v + a |v| F/|F| changes
+# it.  delaystep = 0 makes the downhill step i = 2 grow dt and decay alpha,
+# so the tests also fix whether the mixing uses alpha before or after that
+# decay, and which dt each MD step uses.  Each test also shows that the
+# other placement lands more than 1e-10 away (the comparison is to 1e-14).
+
+K2 = np.array([1.0, 10.0, 0.0])
+X2 = np.array([1.0, 0.4, 0.0])
+
+
+def f2d(x):
+    return -K2 * x
+
+
+def mixv(v, f, a):
+    return (1 - a) * v + a * np.linalg.norm(v) * f / np.linalg.norm(f)
+
+
+FA = 0.5  # alpha decay factor (a strong decay, so that alpha before and after it differ clearly)
+
+
+def run2d(steps, **over):
+    fire = params(dt_start=0.05, alpha0=0.1, delaystep=0, alphashrink=FA, **over)
+    return oracle.fire_minimize(np.array([X2]), OPEN, well(tuple(K2)), fire, 0.0, steps, trace=True,
+                                want_velocity=True)
+
+
+def first_step_dt_alpha():
+    # i = 1: P = 0 is uphill; outside the (empty) initial delay dt halves and
+    # alpha resets; v restarts from 0
+    return 0.05 * 0.5, 0.1
+
+
+def test_fire2_semi_implicit_mixing_on_2d_well():
+    """Algorithm 2 with Algorithm 4: kick, mix with the decayed alpha, drift."""
+    dt1, a1 = first_step_dt_alpha()
+    v1 = dt1 * f2d(X2)          # the mixing of a velocity parallel to F is the identity
+    x1 = X2 + dt1 * v1
+    dt2, a2 = dt1 * 1.1, a1 * FA     # i = 2: downhill, N_P>0 = 1 > delaystep
+    assert f2d(x1) @ v1 > 0
+    v = mixv(v1 + dt2 * f2d(x1), f2d(x1), a2)
+    x2 = x1 + dt2 * v
+    r = run2d(2)
+    np.testing.assert_allclose(r["pos"][0], x2, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(r["velocity"][0], v, rtol=1e-14, atol=1e-16)
+    assert r["trace"][2, 5] == pytest.approx(dt2, rel=1e-15) and r["trace"][2, 6] == pytest.approx(a2, rel=1e-15)
+    # the alpha before the decay would give another point: the test tells them apart
+    x2_wrong = x1 + dt2 * mixv(v1 + dt2 * f2d(x1), f2d(x1), a1)
+    assert np.abs(x2_wrong - x2).max() > 1e-10
+
+
+def test_fire1_mixes_before_the_md_step_with_alpha_before_decay():
+    """Algorithm 1: on a downhill step v is mixed with F(x) first, with the
+    alpha in force before this step's decay; then dt grows and the MD step
+    (kick, drift) runs with the grown dt and no further mixing."""
+    dt1, a1 = first_step_dt_alpha()
+    v1 = dt1 * f2d(X2)
+    x1 = X2 + dt1 * v1
+    f1 = f2d(x1)
+    assert f1 @ v1 > 0
+    v = mixv(v1, f1, a1)          # mixed first, alpha not yet decayed
+    dt2 = dt1 * 1.1
+    v = v + dt2 * f1
+    x2 = x1 + dt2 * v
+    r = run2d(2, variant="fire1")
+    np.testing.assert_allclose(r["pos"][0], x2, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(r["velocity"][0], v, rtol=1e-14, atol=1e-16)
+    assert r["trace"][2, 6] == pytest.approx(a1 * FA, rel=1e-15)
+    # mixing after the kick (the FIRE 2.0 placement) lands elsewhere
+    x2_after = x1 + dt2 * mixv(v1 + dt2 * f1, f1, a1)
+    assert np.abs(x2_after - x2).max() > 1e-10
+
+
+def test_fire2_explicit_euler_mixing_on_2d_well():
+    """Algorithm 3: mix, drift with the mixed v, kick with the force of the
+    old positions.  Step 1 does not move the atom; the velocity of step 2 is
+    still parallel to the first force; step 3 is the first that mixes."""
+    dt1, a1 = first_step_dt_alpha()
+    f0 = f2d(X2)
+    x1, v1 = X2.copy(), dt1 * f0                 # i = 1: drift with v = 0, kick with F0
+    dt2, a2 = dt1 * 1.1, a1 * FA               # i = 2: P = F0.v1 > 0
+    x2 = x1 + dt2 * v1                           # mixing v1 with F(x1) = F0 is the identity
+    v2 = v1 + dt2 * f0
+    f2 = f2d(x2)
+    assert f2 @ v2 > 0
+    dt3, a3 = dt2 * 1.1, a2 * FA               # i = 3
+    vm = mixv(v2, f2, a3)
+    x3 = x2 + dt3 * vm
+    v3 = vm + dt3 * f2
+    r = run2d(3, integrator="eulerexplicit")
+    np.testing.assert_allclose(r["pos"][0], x3, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(r["velocity"][0], v3, rtol=1e-14, atol=1e-16)
+    # kicking before the drift (semi-implicit order) lands elsewhere
+    assert np.abs((x2 + dt3 * mixv(v2 + dt3 * f2, f2, a3)) - x3).max() > 1e-10
+
+
+def test_fire2_velocity_verlet_mixing_on_2d_well():
+    """Algorithm 6: half kick, mix, drift, new force, half kick with it."""
+    dt1, a1 = first_step_dt_alpha()
+    f0 = f2d(X2)
+    vh = 0.5 * dt1 * f0
+    x1 = X2 + dt1 * vh
+    f1 = f2d(x1)
+    v1 = vh + 0.5 * dt1 * f1
+    assert f1 @ v1 > 0
+    dt2, a2 = dt1 * 1.1, a1 * FA
+    vh = mixv(v1 + 0.5 * dt2 * f1, f1, a2)
+    x2 = x1 + dt2 * vh
+    f2 = f2d(x2)
+    v2 = vh + 0.5 * dt2 * f2
+    r = run2d(2, integrator="verlet")
+    np.testing.assert_allclose(r["pos"][0], x2, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(r["velocity"][0], v2, rtol=1e-14, atol=1e-16)
+    # mixing after the second half kick instead lands elsewhere
+    vw = v1 + 0.5 * dt2 * f1
+    assert np.abs((x1 + dt2 * vw) - x2).max() > 1e-10
