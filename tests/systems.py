@@ -31,3 +31,28 @@ def _cluster():
     box = inputs.Box(tuple(pos.min(0) - 1), tuple(np.ptp(pos, 0) + 2), (0, 0, 0))
     return inputs.System("gupta_cluster", pos, box, inputs.gupta_potential(),
                          inputs.workload_fire(0.001, inputs.METAL_F2A), 1e-6, 26)
+
+
+def relaxed_parity(r, ref, s, label=""):
+    """Parity of a GPU relaxation r with the oracle's ref from the same start.
+
+    Both must stop for the same reason, with E/N within 1e-10 of each other
+    and every coordinate within 1e-5 (one minimum: states that both stop
+    with |F_i| < tol near it differ by ~F/k, far below that, while another
+    minimum lies ~0.1 away).  Round-off in a different summation order can
+    flip a P ~ 0 branch late in a run; the runs then reach the same minimum
+    by different paths, and these bounds still hold (the first differing
+    iteration is printed).  Returns that iteration or None."""
+    n = len(s.pos)
+    m = min(len(r["trace"]), len(ref["trace"])) if "trace" in r and "trace" in ref else 0
+    diff = np.nonzero(r["trace"][:m, 7] != ref["trace"][:m, 7])[0] if m else []
+    first = int(diff[0]) if len(diff) else None
+    en = ref["energy"] / n
+    gap = abs(r["energy_per_atom"] - en) / abs(en)
+    dx = np.abs(min_image_diff(r["pos"], ref["pos"], s.box)).max()
+    print(f"{label or s.name}: gpu {r['stop']} {r['iterations']} it, oracle {ref['stop']} {ref['iterations']} it, "
+          f"first branch difference {first}, |dE/N|/|E/N| {gap:.3e}, max|dx| {dx:.3e}")
+    assert r["stop"] == ref["stop"]
+    assert gap <= 1e-10
+    assert dx <= 1e-5
+    return first

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_1908_02038_amd import inputs
-from systems import SMALL, min_image_diff
+from systems import SMALL, min_image_diff, relaxed_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -78,17 +78,8 @@ def test_props_relaxation_matches_oracle(api, name):
     c.close()
     ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, s.tol, 50000, trace=True, frozen=frozen,
                                mass=mass)
-    n = len(s.pos)
-    m = min(len(r["trace"]), len(ref["trace"]))
-    diff = np.nonzero(r["trace"][:m, 7] != ref["trace"][:m, 7])[0]
-    first = int(diff[0]) if len(diff) else None
-    print(f"{name}: gpu {r['stop']} {r['iterations']} it, oracle {ref['stop']} {ref['iterations']} it, "
-          f"first branch difference {first}")
-    assert r["stop"] == ref["stop"] == "converged"
-    if first is None and r["iterations"] == ref["iterations"]:
-        assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
-    else:
-        assert first is not None and first >= 50
+    relaxed_parity(r, ref, s)
+    assert r["stop"] == "converged"
     frozen_components_unchanged(r["pos"], s, frozen)
     # the oracle at the GPU's final positions: same energy, masked forces below tol
     e_x, f_x = oracle.energy_forces(r["pos"], s.box, s.potential)
