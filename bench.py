@@ -61,6 +61,12 @@ FUSED = {
 }
 
 
+FP32_KERNEL = {
+    "lj": "k_lj_force<float, true, false, true>",
+    "gupta": "k_gupta_density<float, true, true> + k_gupta_force<float, true, false>",
+}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -217,7 +223,8 @@ def measure_config(name: str, precision: str, steps: int, warmup: int, max_steps
         "ms_per_relaxation": dt / steps * 1e3, "steps_per_s": sum(x["iterations"] for x in res) / dt,
         "iterations": r["iterations"], "iterations_fp32": r["iterations_low"], "rebuilds": r["rebuilds"],
         "stop": r["stop"], "energy_per_atom": r["energy_per_atom"], "fmax": r["fmax"],
-        "force_pass_us": kt * 1e3, "force_pass_kernel": alg["kernel"],
+        "force_pass_us": kt * 1e3,
+        "force_pass_kernel": alg["kernel"] if precision == "fp64" or kind == "sw" else FP32_KERNEL[kind],
         "force_pass_hbm_frac_alg": hbm / PEAK_HBM_GBS, "force_pass_hbm_GBs_alg": hbm,
         "force_pass_alu_frac_alg": alu / peak_alu, "force_pass_TFLOPs_alg": alu,
         "note": "force pass timed at the start positions with the run's first pair precision"
@@ -266,28 +273,52 @@ def kernel_only(args, s, pos0):
                       "reps": args.kernel_reps, "copy_bytes": COPY_BYTES}), flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(s, budget_s: float):
-    """The oracle as it stands (brute-force pair sums, OpenMP over atoms) on a
-    bounded sample: the first FIRE 2.0 iterations of the same workload."""
+    """The oracle as it stands (pairs found through its cell grid, O(N) per
+    evaluation; OpenMP over atoms) on a bounded sample: the first FIRE 2.0
+    iterations of the same workload, on all of the host's threads and on one.
+    Its results do not depend on the thread count."""
     import oracle
     n = len(s.pos)
-    t0 = time.perf_counter()
-    oracle.energy_forces(s.pos, s.box, s.potential)
-    t1 = time.perf_counter() - t0
-    steps = max(1, min(10, int(budget_s / max(t1, 1e-9)) - 2))
-    t0 = time.perf_counter()
-    r = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, s.tol, steps)
-    dt = time.perf_counter() - t0
-    evals = r["force_evals"]
-    return {
-        "value": n * evals / dt,
-        "unit": "atom-force-evals/s",
-        "cores": oracle.threads(),
-        "kind": "oracle",
-        "sample": f"{steps} FIRE 2.0 iterations ({evals} brute-force force evaluations) of the full {n}-atom "
-                  f"workload, {dt:.1f} s",
-        "steps_per_s": r["iterations"] / dt if dt > 0 else None,
-    }
+    out = {"unit": "atom-force-evals/s", "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    all_threads = oracle.threads()
+    legs = {}
+    with oracle.cells():
+        for label, threads, share in (("all_cores", all_threads, 0.6), ("one_core", 1, 0.4)):
+            oracle.set_threads(threads)
+            t0 = time.perf_counter()
+            oracle.energy_forces(s.pos, s.box, s.potential)
+            t1 = time.perf_counter() - t0
+            steps = max(1, min(20, int(share * budget_s / max(t1, 1e-9)) - 1))
+            t0 = time.perf_counter()
+            r = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, s.tol, steps)
+            dt = time.perf_counter() - t0
+            legs[label] = {"threads": threads, "iterations": r["iterations"], "force_evals": r["force_evals"],
+                           "seconds": dt, "value": n * r["force_evals"] / dt, "steps_per_s": r["iterations"] / dt}
+    oracle.set_threads(all_threads)
+    a = legs["all_cores"]
+    out.update({
+        "value": a["value"],
+        "cores": a["threads"],
+        "steps_per_s": a["steps_per_s"],
+        "one_core": legs["one_core"],
+        "all_cores": a,
+        "sample": f"the first {a['iterations']} FIRE 2.0 iterations ({a['force_evals']} force evaluations) of the full "
+                  f"{n}-atom workload on {a['threads']} threads ({a['seconds']:.1f} s), and "
+                  f"{legs['one_core']['iterations']} on one thread ({legs['one_core']['seconds']:.1f} s); "
+                  f"pairs through the oracle's cell grid",
+    })
+    return out
 
 
 def relax_once(ctx, pos0_dev, s, max_steps: int, fire: dict):
@@ -425,6 +456,8 @@ def main():
                     help="instead of the bench line: one JSON line of the integrator comparison or the parameter "
                          "sweep")
     ap.add_argument("--sweep-max-steps", type=int, default=20000)
+    ap.add_argument("--fp32-max-steps", type=int, default=3000,
+                    help="iteration limit of the pure FP32 run (it cannot reach 1e-6)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -522,6 +555,15 @@ def main():
         itm = sum(x["iterations"] for x in resm)
         ktm = kernel_time_ms(ctxm, args.kernel_reps)  # params say mixed -> FP32 pair kernel
         ctxm.close()
+        # the FP32 force floor: max |F_i| of FP32 pair terms at the FP64
+        # minimum just found (where the FP64 forces are below the tolerance)
+        ctx32 = api.Context(0, s.fire, precision="fp32")
+        _, f32 = ctx32.fire_energy_forces_dev(final, s.box, s.potential)
+        floor = float(torch.linalg.norm(f32, dim=1).max())
+        # the pure FP32 path (no switch to FP64 pair terms) toward the same tolerance
+        w32 = pos0.clone()
+        r32 = ctx32.fire_minimize_dev(w32, s.box, s.potential, s.tol, args.fp32_max_steps)
+        ctx32.close()
         out["mixed"] = {
             "value": n * evm / dtm,
             "ms_per_step": dtm / args.steps * 1e3,
@@ -534,10 +576,19 @@ def main():
             / abs(r["energy_per_atom"]),
             "fmax": rm["fmax"],
             "fp32_force_pass_ms": ktm,
+            "fp32_force_pass_kernel": FP32_KERNEL.get(kind, ""),
             "speedup_vs_fp64_wall": dt / args.steps / (dtm / args.steps),
+            "fp32_force_floor": floor,
+            "fp32_force_floor_note": "max |F_i| of FP32 pair terms at the FP64 path's relaxed positions",
+            "pure_fp32": {"stop": r32["stop"], "iterations": r32["iterations"], "fmax": r32["fmax"],
+                          "energy_per_atom": r32["energy_per_atom"],
+                          "energy_per_atom_rel_diff_vs_fp64": abs(r32["energy_per_atom"] - r["energy_per_atom"])
+                          / abs(r["energy_per_atom"]),
+                          "max_steps": args.fp32_max_steps},
         }
         log(f"[bench] mixed: {rm['iterations']} iterations ({rm['iterations_low']} FP32), "
-            f"{dtm / args.steps * 1e3:.1f} ms/relaxation, FP32 force pass {ktm * 1e3:.1f} us")
+            f"{dtm / args.steps * 1e3:.1f} ms/relaxation, FP32 force pass {ktm * 1e3:.1f} us; FP32 force floor "
+            f"{floor:.3e}; pure FP32: {r32['stop']} after {r32['iterations']} iterations, fmax {r32['fmax']:.3e}")
 
     if not args.no_batched:
         out["batched"] = bench_batched(args)

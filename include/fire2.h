@@ -147,7 +147,8 @@ typedef struct {
 /* Outcome of a minimisation.  iterations counts integration steps
  * (force_evals = iterations + 1). */
 typedef struct {
-  int stop_reason;          /* FIRE_STOP_* */
+  int stop_reason;          /* FIRE_STOP_*; in the batched form, a system that failed
+                               reports its FIRE_E_* code (< 0) here instead */
   int precision_switched;   /* FIRE_MIXED: 1 once the run moved to FP64 pair terms */
   long long iterations;
   long long force_evals;
@@ -224,18 +225,31 @@ int fire_hvp(fire_ctx* ctx, long long n, const double* pos, const double* u, con
              const fire_potential* pot, double* hu);
 
 /* Lowest curvature of E at pos along directions orthogonal to rigid
- * translations: k iterations of Lanczos on the Hessian (HVP kernel), started
- * from the seeded direction u0 ([n][3], NULL = built-in).  *lambda_min is the
- * smallest Ritz value (a Rayleigh quotient); a positive value indicates a
- * stable minimum. */
+ * translations: k iterations of Lanczos on the Hessian (HVP kernel, full
+ * re-orthogonalisation), started from the seeded direction u0 ([n][3],
+ * NULL = built-in).  *lambda_min is the smallest Ritz value theta, the
+ * Rayleigh quotient of its Ritz vector z, so the Hessian's lowest eigenvalue
+ * is <= theta.  residual (may be NULL) receives |H z - theta z| (|z| = 1):
+ * some eigenvalue lies within it of theta, so theta - residual > 0 shows a
+ * positive curvature there; theta < 0 shows an unstable direction (a
+ * saddle).  Whether theta has reached the lowest eigenvalue depends on k
+ * and the spectrum's gaps. */
 int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const fire_box* box,
-                          const fire_potential* pot, const double* u0, int k, double* lambda_min);
+                          const fire_potential* pot, const double* u0, int k, double* lambda_min,
+                          double* residual);
 
 /* Independent minimisations of nsys systems in one persistent launch.
  * System s owns atoms offsets[s] .. offsets[s+1]-1 of pos ([offsets[nsys]][3],
  * in/out), the box boxes[s], and the FIRE state of its own; per_sys (NULL =
  * the context's params for all) gives each system its parameters.  All
- * systems share pot.  out has nsys entries. */
+ * systems share pot.  out has nsys entries.
+ * A system that fails on its own -- two of its atoms at one place, a
+ * non-finite position or force -- stops with out[s].stop_reason set to
+ * FIRE_E_OVERLAP or FIRE_E_NONFINITE and its positions as they were at its
+ * last force evaluation; every other system runs to its own stop exactly as
+ * without it (the same bits), and the call returns FIRE_OK.  Errors of the
+ * call itself (arguments, the device) are returned as usual and then no
+ * output is written. */
 int fire_minimize_batched(fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
                           const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
                           double tol, long long max_steps, fire_result* out);
@@ -255,8 +269,8 @@ int fire_minimize_ex_dev(fire_ctx* ctx, long long n, double* d_pos, const fire_b
                          fire_result* out, void* stream);
 /* fire_minimize_batched on device positions d_pos ([offsets[nsys]][3], in
  * place); offsets, boxes, per_sys and out stay in host memory.  Returns when
- * every system has stopped.  A non-finite position is not screened on the
- * host: its system ends with FIRE_E_NONFINITE from its first force pass. */
+ * every system has stopped.  Per-system failures are reported as in
+ * fire_minimize_batched. */
 int fire_minimize_batched_dev(fire_ctx* ctx, int nsys, const long long* offsets, double* d_pos,
                               const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
                               double tol, long long max_steps, fire_result* out, void* stream);

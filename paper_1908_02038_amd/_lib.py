@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfire2.so")
 FIRE_OK = 0
 ERRORS = {-1: "FIRE_E_ARG", -2: "FIRE_E_BOX", -3: "FIRE_E_NONFINITE", -4: "FIRE_E_OVERLAP",
           -5: "FIRE_E_DEVICE", -6: "FIRE_E_OOM"}
-STOP = {1: "converged", 2: "max_steps", 3: "maxvdotf"}
+STOP = {1: "converged", 2: "max_steps", 3: "maxvdotf", -3: "nonfinite", -4: "overlap"}  # < 0: a batched system's own failure
 POT = {"lj": 1, "gupta": 2, "harmonic": 3, "sw": 4}
 CONVENTION = {"rgl": 0, "half": 1}
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
@@ -119,7 +119,7 @@ def load(path: str = LIB_PATH):
     lib.fire_minimize_traced.argtypes = [ctx_p, ll, dp, P(fire_box), P(fire_potential), ctypes.c_double, ll,
                                          P(fire_result), dp]
     lib.fire_hvp.argtypes = [ctx_p, ll, dp, dp, P(fire_box), P(fire_potential), dp]
-    lib.fire_lowest_curvature.argtypes = [ctx_p, ll, dp, P(fire_box), P(fire_potential), dp, ctypes.c_int, dp]
+    lib.fire_lowest_curvature.argtypes = [ctx_p, ll, dp, P(fire_box), P(fire_potential), dp, ctypes.c_int, dp, dp]
     lib.fire_minimize_batched.argtypes = [ctx_p, ctypes.c_int, P(ll), dp, P(fire_box), P(fire_potential),
                                           P(fire_params), ctypes.c_double, ll, P(fire_result)]
     lib.fire_energy_forces_dev.argtypes = [ctx_p, ll, ctypes.c_void_p, P(fire_box), P(fire_potential),

@@ -193,17 +193,20 @@ class Context:
                                       ctypes.byref(p), _dp(hu)))
         return hu
 
-    def fire_lowest_curvature(self, pos, box, pot, k: int = 40, u0=None) -> float:
+    def fire_lowest_curvature(self, pos, box, pot, k: int = 40, u0=None, want_residual: bool = False):
+        """Smallest Ritz value of k Lanczos steps (and its residual |Hz - theta z|)."""
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         lam = ctypes.c_double()
+        res = ctypes.c_double()
         b, p = make_box(box), make_potential(pot)
         u0p = None
         if u0 is not None:
             u0 = np.ascontiguousarray(u0, dtype=np.float64)
             u0p = _dp(u0)
         self._check(self.lib.fire_lowest_curvature(self.handle, pos.shape[0], _dp(pos), ctypes.byref(b),
-                                                   ctypes.byref(p), u0p, int(k), ctypes.byref(lam)))
-        return lam.value
+                                                   ctypes.byref(p), u0p, int(k), ctypes.byref(lam),
+                                                   ctypes.byref(res)))
+        return (lam.value, res.value) if want_residual else lam.value
 
     def fire_minimize_batched(self, systems, pot, tol: float, max_steps: int, per_sys: list | None = None):
         """systems: list of (pos (n,3), box).  Returns (list of positions, list of result dicts)."""

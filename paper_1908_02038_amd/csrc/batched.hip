@@ -526,6 +526,20 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
       sh.dtx = c->dtx;
     }
     __syncthreads();
+    if (c->evals == 0) {
+      // first visit: a non-finite input position fails this system alone
+      // (its positions stay as given; the queue moves on)
+      int bad = 0;
+      for (int a = threadIdx.x; a < d.n; a += TEAM) {
+        const double4 p = sh.x[a];
+        bad |= !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z));
+      }
+      if (__syncthreads_or(bad)) {
+        if (threadIdx.x == 0) c->status = FIRE_E_NONFINITE;
+        __syncthreads();
+        continue;
+      }
+    }
     bool ok = true;
     if (sh.viol) {  // first visit (or after a capacity change): build the list
       tm.build(nbr, nn, kb);
@@ -757,7 +771,8 @@ int reset_state(fire_ctx* ctx, Workspace* w, const std::vector<Ctrl>& c0, hipStr
 }
 
 // One replay unit: reset the queue and run the persistent kernel once.
-void launch_chunk(Workspace* w, const PotDev& P, const Config& cf, hipStream_t s, int nteams) {
+template <typename B>
+void launch_chunk(const B* w, const PotDev& P, const Config& cf, hipStream_t s, int nteams) {
   hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, w->queue);
   KernelFn fn = kernel_for(cf.team, P.kind);
   hipLaunchKernelGGL(fn, dim3(nteams), dim3(cf.team), 0, s, w->desc, w->ctrl, w->order, w->nsys, w->queue, w->pos,
@@ -792,15 +807,26 @@ void save_cache(Workspace* w) {
   for (auto& kv : w->tuned) f << kv.first << " " << kv.second.team << " " << kv.second.chunk << "\n";
 }
 
-}  // namespace
+// Systems in decreasing size, equal sizes in index order (a counting sort:
+// no allocation, sizes are at most kMaxAtoms).
+void order_by_size(const SysDesc* desc, int nsys, int* order) {
+  int count[kMaxAtoms + 2] = {0};
+  for (int q = 0; q < nsys; ++q) count[kMaxAtoms - desc[q].n + 1] += 1;
+  for (int k = 1; k <= kMaxAtoms + 1; ++k) count[k] += count[k - 1];
+  for (int q = 0; q < nsys; ++q) order[count[kMaxAtoms - desc[q].n]++] = q;
+}
 
-extern "C" void fire_batched_release(void* ws) { release(static_cast<Workspace*>(ws)); }
+struct BatchPlan {
+  int nsys, ntot, maxn, kb;
+  PotDev P;
+};
 
-extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos, bool host,
-                                const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
-                                double tol, long long max_steps, fire_result* out, hipStream_t s) {
-  if (nsys < 1 || !offsets || !pos || !boxes || !pot || !out)
-    return fire_ctx_error(ctx, FIRE_E_ARG, "batched: nsys >= 1 and non-NULL arrays are required");
+// Check the arguments of a batched call and fill the per-system descriptors,
+// the initial control records and the queue order into caller-owned arrays
+// of nsys entries.  Allocates nothing.
+int prepare_batch(fire_ctx* ctx, int nsys, const long long* offsets, const fire_box* boxes,
+                  const fire_potential* pot, const fire_params* per_sys, double tol, long long max_steps,
+                  SysDesc* desc, Ctrl* c0, int* order, BatchPlan* plan) {
   if (!(tol >= 0) || max_steps < 0) return fire_ctx_error(ctx, FIRE_E_ARG, "batched: bad tol or max_steps");
   if (pot->kind != FIRE_POT_LJ && pot->kind != FIRE_POT_GUPTA)
     return fire_ctx_error(ctx, FIRE_E_ARG, "batched: LJ or Gupta potentials only");
@@ -814,24 +840,10 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
   }
   const long long ntot_ll = offsets[nsys];
   if (ntot_ll > (1LL << 30)) return fire_ctx_error(ctx, FIRE_E_ARG, "batched: too many atoms");
-  const int ntot = (int)ntot_ll;
-  if (host)  // device positions: a non-finite one ends its system with FIRE_E_NONFINITE
-    for (long long i = 0; i < 3 * ntot_ll; ++i)
-      if (!std::isfinite(pos[i])) return fire_ctx_error(ctx, FIRE_E_NONFINITE, "batched: non-finite position");
-  PotDev P;
+  PotDev& P = plan->P;
   int rc = fire_prepare_pot(ctx, pot, &P);
   if (rc) return rc;
   const fire_params* base = fire_ctx_params(ctx);
-  void** slot = fire_ctx_batched_slot(ctx);
-  if (!*slot) {
-    *slot = new Workspace();
-    load_cache(static_cast<Workspace*>(*slot));
-  }
-  Workspace* w = static_cast<Workspace*>(*slot);
-
-  // per-system descriptors and control records
-  std::vector<SysDesc> desc(nsys);
-  std::vector<Ctrl> c0(nsys);
   double max_dens_vol = 0.0;
   for (int q = 0; q < nsys; ++q) {
     const fire_box& b = boxes[q];
@@ -864,16 +876,82 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     }
     if (all_per && vol > 0) max_dens_vol = std::max(max_dens_vol, d.n / vol * rcs * rcs * rcs);
   }
-  const double rcs_max = std::sqrt(std::max_element(desc.begin(), desc.end(), [](const SysDesc& a, const SysDesc& b) {
-                                     return a.rcs2 < b.rcs2;
-                                   })->rcs2);
-  (void)rcs_max;
   int kb = (int)(4.18879 * std::max(max_dens_vol, 0.1 * 1.0) * 1.6) + 24;
   kb = (std::max(kb, 32) + 3) & ~3;  // lists are read in groups of four
-  // the systems in decreasing size
+  order_by_size(desc, nsys, order);
+  plan->nsys = nsys;
+  plan->ntot = (int)ntot_ll;
+  plan->maxn = maxn;
+  plan->kb = kb;
+  return FIRE_OK;
+}
+
+// Team shape and chunk length: FIRE_BATCH_TEAM / FIRE_BATCH_CHUNK, else a
+// cached tuning result for this batch class, else (tune = false) 1024 threads.
+Config config_for(Workspace* w, const BatchPlan& pl, int prec0, bool* found) {
+  Config cfg{1024, kChunk};
+  *found = false;
+  if (const char* e = getenv("FIRE_BATCH_TEAM")) {
+    cfg.team = atoi(e) == 512 ? 512 : 1024;
+    *found = true;
+  } else if (w) {
+    auto it = w->tuned.find(tune_key(pl.P, prec0, pl.nsys, pl.maxn));
+    if (it != w->tuned.end()) {
+      cfg = it->second;
+      *found = true;
+    }
+  }
+  if (const char* e = getenv("FIRE_BATCH_CHUNK")) cfg.chunk = std::max(1, atoi(e));
+  return cfg;
+}
+
+// Results of a finished batch from its control records.
+void fill_results(const Ctrl* cr, const SysDesc* desc, int nsys, fire_result* out) {
+  // a system that failed (two atoms at one place, a non-finite position or
+  // force) reports its error code as its stop reason; the others keep theirs
+  for (int q = 0; q < nsys; ++q) {
+    const Ctrl& h = cr[q];
+    fire_result& o = out[q];
+    memset(&o, 0, sizeof(o));
+    o.stop_reason = h.status;
+    o.precision_switched = (h.mode == FIRE_MIXED && h.precision == 0) ? 1 : 0;
+    o.iterations = h.iter;
+    o.force_evals = h.evals;
+    o.iterations_low = h.iter_low;
+    o.energy = h.energy;
+    o.energy_per_atom = h.energy / desc[q].n;
+    o.fmax = h.fmax;
+    o.f2norm = h.f2norm;
+    o.dt = h.dt;
+    o.alpha = h.alpha;
+  }
+}
+
+}  // namespace
+
+extern "C" void fire_batched_release(void* ws) { release(static_cast<Workspace*>(ws)); }
+
+extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos, bool host,
+                                const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
+                                double tol, long long max_steps, fire_result* out, hipStream_t s) {
+  if (nsys < 1 || !offsets || !pos || !boxes || !pot || !out)
+    return fire_ctx_error(ctx, FIRE_E_ARG, "batched: nsys >= 1 and non-NULL arrays are required");
+  std::vector<SysDesc> desc(nsys);
+  std::vector<Ctrl> c0(nsys);
   std::vector<int> order(nsys);
-  for (int q = 0; q < nsys; ++q) order[q] = q;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return desc[a].n > desc[b].n; });
+  BatchPlan plan;
+  int rc = prepare_batch(ctx, nsys, offsets, boxes, pot, per_sys, tol, max_steps, desc.data(), c0.data(),
+                         order.data(), &plan);
+  if (rc) return rc;
+  const PotDev& P = plan.P;
+  const int ntot = plan.ntot, maxn = plan.maxn;
+  int kb = plan.kb;
+  void** slot = fire_ctx_batched_slot(ctx);
+  if (!*slot) {
+    *slot = new Workspace();
+    load_cache(static_cast<Workspace*>(*slot));
+  }
+  Workspace* w = static_cast<Workspace*>(*slot);
 
   for (int attempt = 0; attempt < 4; ++attempt) {
     rc = ensure(ctx, w, nsys, ntot, kb);
@@ -895,45 +973,36 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const int nteams = std::min(nsys, ncu);
 
-    // ---- autotune the team shape (timed on this batch, state reset afterwards)
+    // ---- team shape: the cached choice, else timed on this batch (state reset afterwards)
     const int prec0 = c0[0].precision;
-    const std::string key = tune_key(P, prec0, nsys, maxn);
-    Config cfg{1024, kChunk};
-    if (!getenv("FIRE_BATCH_TEAM")) {
-      auto it = w->tuned.find(key);
-      if (it != w->tuned.end()) {
-        cfg = it->second;
-      } else {
-        double best = 1e300;
-        for (int team : {1024, 512}) {
-          Config cand{team, 32};
-          hipEvent_t e0, e1;
-          BCHK(hipEventCreate(&e0));
-          BCHK(hipEventCreate(&e1));
-          launch_chunk(w, P, cand, s, nteams);  // includes the list build; not timed
-          BCHK(hipEventRecord(e0, s));
-          launch_chunk(w, P, cand, s, nteams);
-          BCHK(hipEventRecord(e1, s));
-          BCHK(hipEventSynchronize(e1));
-          float ms = 0;
-          BCHK(hipEventElapsedTime(&ms, e0, e1));
-          hipEventDestroy(e0);
-          hipEventDestroy(e1);
-          if (ms < best) {
-            best = ms;
-            cfg.team = team;
-          }
-          rc = reset_state(ctx, w, c0, s);
-          if (rc) return rc;
+    bool found = false;
+    Config cfg = config_for(w, plan, prec0, &found);
+    if (!found) {
+      double best = 1e300;
+      for (int team : {1024, 512}) {
+        Config cand{team, 32};
+        hipEvent_t e0, e1;
+        BCHK(hipEventCreate(&e0));
+        BCHK(hipEventCreate(&e1));
+        launch_chunk(w, P, cand, s, nteams);  // includes the list build; not timed
+        BCHK(hipEventRecord(e0, s));
+        launch_chunk(w, P, cand, s, nteams);
+        BCHK(hipEventRecord(e1, s));
+        BCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        BCHK(hipEventElapsedTime(&ms, e0, e1));
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (ms < best) {
+          best = ms;
+          cfg.team = team;
         }
-        cfg.chunk = kChunk;
-        w->tuned[key] = cfg;
-        save_cache(w);
+        rc = reset_state(ctx, w, c0, s);
+        if (rc) return rc;
       }
-    } else {
-      cfg.team = atoi(getenv("FIRE_BATCH_TEAM")) == 512 ? 512 : 1024;
+      w->tuned[tune_key(P, prec0, nsys, maxn)] = Config{cfg.team, kChunk};
+      save_cache(w);
     }
-    if (const char* e = getenv("FIRE_BATCH_CHUNK")) cfg.chunk = std::max(1, atoi(e));
 
     // ---- graph: queue reset, persistent kernel, running count, poll copy
     hipGraph_t graph;
@@ -970,25 +1039,9 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     hipLaunchKernelGGL(k_unstage, dim3(nsys), dim3(256), 0, s, w->pos, w->desc, host ? w->stage : pos);
     if (host) BCHK(hipMemcpyAsync(pos, w->stage, sizeof(double) * 3 * ntot, hipMemcpyDeviceToHost, s));
     BCHK(hipStreamSynchronize(s));
-    for (int q = 0; q < nsys; ++q) {
-      const Ctrl& h = cr[q];
-      if (h.status == FIRE_E_OVERLAP) return fire_ctx_error(ctx, FIRE_E_OVERLAP, "batched: two atoms coincide");
-      if (h.status == FIRE_E_NONFINITE) return fire_ctx_error(ctx, FIRE_E_NONFINITE, "batched: non-finite force");
-      fire_result& o = out[q];
-      memset(&o, 0, sizeof(o));
-      o.stop_reason = h.status;
-      o.precision_switched = (h.mode == FIRE_MIXED && h.precision == 0) ? 1 : 0;
-      o.iterations = h.iter;
-      o.force_evals = h.evals;
-      o.iterations_low = h.iter_low;
-      o.energy = h.energy;
-      o.energy_per_atom = h.energy / desc[q].n;
-      o.fmax = h.fmax;
-      o.f2norm = h.f2norm;
-      o.dt = h.dt;
-      o.alpha = h.alpha;
-    }
+    fill_results(cr.data(), desc.data(), nsys, out);
     return FIRE_OK;
   }
   return fire_ctx_error(ctx, FIRE_E_OOM, "batched: neighbour lists keep outgrowing their capacity");
 }
+

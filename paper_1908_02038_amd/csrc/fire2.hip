@@ -3270,6 +3270,51 @@ double tridiag_min_eig(const std::vector<double>& a, const std::vector<double>& 
   return 0.5 * (lo + hi);
 }
 
+// Last component of the unit eigenvector of the symmetric tridiagonal T
+// (diagonal a, off-diagonal b) for its eigenvalue lam, by inverse iteration:
+// solves (T - sigma) x = y with sigma just below lam, Gaussian elimination
+// with partial pivoting on the band.
+double tridiag_last_component(const std::vector<double>& a, const std::vector<double>& b, double lam) {
+  const int k = (int)a.size();
+  if (k == 1) return 1.0;
+  double scale = 0.0;
+  for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(a[i]) + (i < k - 1 ? std::fabs(b[i]) : 0.0));
+  const double sigma = lam - 1e-10 * std::max(scale, 1e-300);
+  std::vector<double> y(k, 1.0), x(k);
+  for (int it = 0; it < 4; ++it) {
+    // rows: d[i] on the diagonal, u1[i], u2[i] above it, l[i] below it
+    std::vector<double> d(k), u1(k, 0.0), u2(k, 0.0), l(k, 0.0), r = y;
+    for (int i = 0; i < k; ++i) {
+      d[i] = a[i] - sigma;
+      if (i < k - 1) u1[i] = b[i];
+      if (i > 0) l[i] = b[i - 1];
+    }
+    for (int i = 0; i < k - 1; ++i) {
+      if (std::fabs(l[i + 1]) > std::fabs(d[i])) {  // swap rows i and i + 1
+        std::swap(d[i], l[i + 1]);
+        std::swap(u1[i], d[i + 1]);
+        std::swap(u2[i], u1[i + 1]);
+        std::swap(r[i], r[i + 1]);
+      }
+      const double m = d[i] != 0.0 ? l[i + 1] / d[i] : 0.0;
+      d[i + 1] -= m * u1[i];
+      u1[i + 1] -= m * u2[i];
+      r[i + 1] -= m * r[i];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double t = r[i];
+      if (i + 1 < k) t -= u1[i] * x[i + 1];
+      if (i + 2 < k) t -= u2[i] * x[i + 2];
+      x[i] = t / (d[i] != 0.0 ? d[i] : 1e-300);
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < k; ++i) nrm += x[i] * x[i];
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < k; ++i) y[i] = x[i] / nrm;
+  }
+  return y[k - 1];
+}
+
 }  // namespace
 
 // Accessors for the batched path (batched.hip).
@@ -3315,6 +3360,8 @@ const char* fire_stop_name(int r) {
     case FIRE_STOP_CONVERGED: return "converged";
     case FIRE_STOP_MAX_STEPS: return "max_steps";
     case FIRE_STOP_MAXVDOTF: return "maxvdotf";
+    case FIRE_E_NONFINITE: return "nonfinite";
+    case FIRE_E_OVERLAP: return "overlap";
     default: return "unknown";
   }
 }
@@ -3596,7 +3643,8 @@ int fire_hvp_dev(fire_ctx* ctx, long long n, const double* d_pos, const double* 
 }
 
 int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const fire_box* box,
-                          const fire_potential* pot, const double* u0, int k, double* lambda_min) {
+                          const fire_potential* pot, const double* u0, int k, double* lambda_min,
+                          double* residual) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if (!lambda_min || k < 1 || k > 500) return set_err(ctx, FIRE_E_ARG, "need lambda_min and 1 <= k <= 500");
@@ -3645,6 +3693,7 @@ int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const f
   const int nb = nblocks(n);
   hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, s, V, V, (int)n, ctx->ncap, 1.0 / std::sqrt(nrm2), 0.0);
   std::vector<double> a, b;
+  double beta_last = 0.0;
   for (int j = 0; j < k; ++j) {
     double* vj = V + j * pl;
     launch_hvp(ctx, s, vj, w, pre);
@@ -3665,6 +3714,7 @@ int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const f
     rc = dev_dot(ctx, s, w, w, &bb);
     if (rc) return rc;
     double bj = std::sqrt(std::max(bb, 0.0));
+    beta_last = bj;
     if (j == k - 1 || bj < 1e-12 * std::fabs(aj)) break;
     b.push_back(bj);
     HIPCHK(hipMemcpyAsync(V + (j + 1) * pl, w, sizeof(double) * pl, hipMemcpyDeviceToDevice, s));
@@ -3672,6 +3722,8 @@ int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const f
   }
   b.resize(a.size() > 0 ? a.size() - 1 : 0);
   *lambda_min = tridiag_min_eig(a, b);
+  // |H z - theta z| of the Ritz vector z = V y is beta_k |y_k|
+  if (residual) *residual = beta_last * std::fabs(tridiag_last_component(a, b, *lambda_min));
   return FIRE_OK;
 }
 

@@ -57,3 +57,13 @@ def test_committed_traffic_summary_names_its_commands_and_calibration():
     assert rec["fetch_bytes_per_launch"] == pytest.approx(
         rec["fetch_kib_per_dispatch_raw"] * 1024 * cal["fetch_factor"], rel=1e-9)
     assert rec["bytes_per_launch"] == pytest.approx(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
+
+
+def test_cpu_baseline_record_names_the_host_and_both_thread_counts():
+    from paper_1908_02038_amd import inputs
+    rec = bench.cpu_baseline(inputs.lj_small(), 0.5)
+    assert rec["kind"] == "oracle" and rec["unit"] == "atom-force-evals/s"
+    assert rec["cores"] == rec["all_cores"]["threads"] >= 1 and rec["one_core"]["threads"] == 1
+    assert rec["value"] == rec["all_cores"]["value"] > 0 and rec["one_core"]["value"] > 0
+    assert rec["cpu_model"] and rec["nproc"] >= 1
+    assert "cell grid" in rec["sample"]

@@ -159,3 +159,36 @@ def test_chunk_length_does_not_change_results(api, monkeypatch):
     for a, b, x, y in zip(pa, pb, ra, rb):
         np.testing.assert_array_equal(a, b)
         assert x["iterations"] == y["iterations"] and x["energy"] == y["energy"] and x["stop"] == y["stop"]
+
+
+def test_a_failing_system_does_not_disturb_the_others(api):
+    """One system with a NaN coordinate (device entry point) and one with two
+    atoms at the same place (host entry point): each ends with its own error
+    as stop reason, and every other system gives the bits of a batch
+    without them."""
+    import torch
+    systems = small_batch(nsys=6, seed=12)
+    pot = systems[0].potential
+    pos_in = [s.pos.copy() for s in systems]
+    pos_in[2][7, 1] = np.nan
+    pos_in[4][3] = pos_in[4][9]
+    keep = [0, 1, 3, 5]
+    c = api.Context(0, systems[0].fire)
+    ref_pos, ref_res = c.fire_minimize_batched([(systems[k].pos, systems[k].box) for k in keep], pot, 1e-6, 20000)
+    # device entry point, NaN in system 2 (and the overlap in system 4)
+    offs = np.cumsum([0] + [len(p) for p in pos_in])
+    d = torch.tensor(np.concatenate(pos_in), dtype=torch.float64, device="cuda")
+    res_d = c.fire_minimize_batched_dev(d, offs, [s.box for s in systems], pot, 1e-6, 20000)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy()
+    # host entry point, the same poisoned batch
+    pos_h, res_h = c.fire_minimize_batched([(p, s.box) for p, s in zip(pos_in, systems)], pot, 1e-6, 20000)
+    c.close()
+    for res, out in ((res_d, [got[offs[k]:offs[k + 1]] for k in range(len(systems))]), (res_h, pos_h)):
+        assert res[2]["stop"] == "nonfinite" and res[2]["iterations"] == 0
+        assert res[4]["stop"] == "overlap"
+        assert np.isnan(out[2][7, 1])
+        for j, k in enumerate(keep):
+            assert res[k]["stop"] == ref_res[j]["stop"] == "converged"
+            assert res[k]["iterations"] == ref_res[j]["iterations"] and res[k]["energy"] == ref_res[j]["energy"]
+            assert np.array_equal(out[k], ref_pos[j])

@@ -107,16 +107,55 @@ def test_lanczos_equals_dense_spectrum(ctx, which):
         s = inputs.System("gupta_60", pos, inputs.Box(tuple(pos.min(0) - 1), tuple(np.ptp(pos, 0) + 2), (0, 0, 0)),
                           inputs.gupta_potential(), inputs.workload_fire(0.001, inputs.METAL_F2A), 1e-6, 42)
     lam = dense_lowest_off_translation(s)
-    got = ctx.fire_lowest_curvature(s.pos, s.box, s.potential, k=min(500, 3 * len(s.pos)))
-    print(f"{which}: n={len(s.pos)} lanczos {got:.12e} dense {lam[0]:.12e} (next {lam[1]:.6e})")
+    got, res = ctx.fire_lowest_curvature(s.pos, s.box, s.potential, k=min(500, 3 * len(s.pos)),
+                                         want_residual=True)
+    print(f"{which}: n={len(s.pos)} lanczos {got:.12e} dense {lam[0]:.12e} (next {lam[1]:.6e}), "
+          f"residual {res:.3e}")
     assert abs(got - lam[0]) <= 1e-8 * np.abs(lam).max()
+    assert res <= 1e-6 * np.abs(lam).max()
 
 
 def test_relaxed_crystal_has_positive_curvature(api):
     s = SMALL["lj_6"]()
     c = api.Context(0, s.fire)
     r = c.fire_minimize(s.pos, s.box, s.potential, 1e-8, 20000)
-    lam = c.fire_lowest_curvature(r["pos"], s.box, s.potential, k=60)
+    lam, res = c.fire_lowest_curvature(r["pos"], s.box, s.potential, k=60, want_residual=True)
     c.close()
+    print(f"lj_6 relaxed: lowest Ritz value {lam:.6e}, residual {res:.3e}")
     assert r["stop"] == "converged"
-    assert lam > 0
+    assert lam - res > 0
+
+
+def linear_trimer():
+    """Three LJ atoms on a line, relaxed along it: the end atoms attract
+    (2r < rc) while each bond is compressed, so the line is a stationary
+    point whose bending modes have negative curvature (a saddle)."""
+    def f_pair(r):  # -dphi/dr of 4 (r^-12 - r^-6)
+        return 24.0 * (2.0 * r ** -13 - r ** -7)
+    lo, hi = 1.0, 2.0 ** (1.0 / 6.0)
+    for _ in range(200):  # f(r) + f(2r) = 0 on the end atom: bisection
+        mid = 0.5 * (lo + hi)
+        if f_pair(mid) + f_pair(2.0 * mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    r = 0.5 * (lo + hi)
+    pos = np.array([[-r, 0.0, 0.0], [0.0, 0.0, 0.0], [r, 0.0, 0.0]]) + 10.0
+    box = inputs.Box((0.0, 0.0, 0.0), (20.0, 20.0, 20.0), (0, 0, 0))
+    return inputs.System("lj_trimer", pos, box, inputs.lj_potential(rc=2.5), inputs.workload_fire(0.005, 1.0),
+                         1e-8, 0)
+
+
+def test_lanczos_flags_a_saddle(ctx):
+    """Negative control: at the linear trimer the dense eigensolve finds a
+    negative curvature, and the Lanczos of the tests above (k as large as
+    the space allows) returns it, with a small residual."""
+    s = linear_trimer()
+    _, f = oracle.energy_forces(s.pos, s.box, s.potential)
+    assert np.abs(f).max() < 1e-12  # a stationary point
+    lam = dense_lowest_off_translation(s)
+    got, res = ctx.fire_lowest_curvature(s.pos, s.box, s.potential, k=9, want_residual=True)
+    print(f"trimer: dense {lam[:3]}, lanczos {got:.12e} residual {res:.3e}")
+    assert lam[0] < -0.1
+    assert got + res < 0
+    assert abs(got - lam[0]) <= 1e-8 * np.abs(lam).max()
