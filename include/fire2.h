@@ -275,6 +275,26 @@ int fire_minimize_batched_dev(fire_ctx* ctx, int nsys, const long long* offsets,
                               const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
                               double tol, long long max_steps, fire_result* out, void* stream);
 
+/* For callers that cannot allocate device memory (work of their own under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fire_minimize_batched_dev with no device allocation, graph or event in
+ * the call.  Its work buffers are carved out of one 64 MiB device array that
+ * each GPU the library runs on holds until the process ends (its address is
+ * taken once per device by fire_init).  Limits: at most 1,024 systems, and
+ * the batch's per-atom state plus neighbour lists must fit the array (about
+ * 160,000 atoms of the EAM-form crystals, 130,000 of the LJ ones); beyond them FIRE_E_ARG, with
+ * nothing written.  The context's device must be current (FIRE_E_DEVICE
+ * otherwise).  Every call on one GPU uses the same array: calls that
+ * overlap in time on one GPU, from any context or thread, race, and the
+ * caller must serialise them.  Each call rewrites every part of the array
+ * it reads before reading it.  Results, per-system failures and errors are
+ * those of fire_minimize_batched_dev: the same kernels, with the team shape
+ * of FIRE_BATCH_TEAM or of the context's cached tuning (1,024 threads if
+ * there is none), so the bits match whenever both calls use one shape. */
+int fire_minimize_batched_noalloc(fire_ctx* ctx, int nsys, const long long* offsets, double* d_pos,
+                                  const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
+                                  double tol, long long max_steps, fire_result* out, void* stream);
+
 /* Measurement hook: re-run the force evaluation (density and force passes for
  * the EAM form) of the system left by the last call on ctx, at its current
  * positions and neighbour list, reps times on stream, with the same kernels

@@ -29,7 +29,7 @@ EXPORTS = [
     "fire_last_error", "fire_stop_name", "fire_energy_forces", "fire_minimize", "fire_minimize_traced",
     "fire_hvp", "fire_lowest_curvature", "fire_minimize_batched", "fire_energy_forces_dev", "fire_hvp_dev",
     "fire_minimize_dev", "fire_minimize_batched_dev", "fire_repeat_forces_dev", "fire_minimize_ex",
-    "fire_minimize_ex_dev",
+    "fire_minimize_ex_dev", "fire_minimize_batched_noalloc",
 ]
 
 
@@ -131,6 +131,9 @@ def load(path: str = LIB_PATH):
     lib.fire_minimize_batched_dev.argtypes = [ctx_p, ctypes.c_int, P(ll), ctypes.c_void_p, P(fire_box),
                                               P(fire_potential), P(fire_params), ctypes.c_double, ll,
                                               P(fire_result), ctypes.c_void_p]
+    lib.fire_minimize_batched_noalloc.argtypes = [ctx_p, ctypes.c_int, P(ll), ctypes.c_void_p, P(fire_box),
+                                                  P(fire_potential), P(fire_params), ctypes.c_double, ll,
+                                                  P(fire_result), ctypes.c_void_p]
     lib.fire_repeat_forces_dev.argtypes = [ctx_p, ctypes.c_int, ctypes.c_void_p]
     lib.fire_minimize_ex.argtypes = [ctx_p, ll, dp, P(fire_box), P(fire_potential), P(fire_atoms),
                                      ctypes.c_double, ll, P(fire_result), dp]

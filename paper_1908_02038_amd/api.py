@@ -227,9 +227,11 @@ class Context:
         return out_pos, [_result(r) for r in res]
 
     def fire_minimize_batched_dev(self, pos, offsets, boxes, pot, tol: float, max_steps: int,
-                                  per_sys: list | None = None):
+                                  per_sys: list | None = None, noalloc: bool = False):
         """pos: (ntot,3) float64 cuda tensor, relaxed in place; offsets: nsys+1
-        atom offsets; boxes: nsys boxes.  Returns the list of result dicts."""
+        atom offsets; boxes: nsys boxes.  Returns the list of result dicts.
+        noalloc: call fire_minimize_batched_noalloc (no device allocation;
+        work buffers in the library's per-device scratch array)."""
         import torch
         assert pos.is_cuda and pos.dtype == torch.float64 and pos.is_contiguous()
         nsys = len(boxes)
@@ -241,7 +243,8 @@ class Context:
             prm = (L.fire_params * nsys)(*[make_params(f) for f in per_sys])
         res = (L.fire_result * nsys)()
         p = make_potential(pot)
-        self._check(self.lib.fire_minimize_batched_dev(
+        fn = self.lib.fire_minimize_batched_noalloc if noalloc else self.lib.fire_minimize_batched_dev
+        self._check(fn(
             self.handle, nsys, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
             ctypes.c_void_p(pos.data_ptr()), bx, ctypes.byref(p), prm, float(tol), int(max_steps), res,
             self._stream()))

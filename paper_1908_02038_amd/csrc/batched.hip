@@ -23,6 +23,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -614,6 +615,10 @@ __global__ void k_reset_queue(int* queue) {
   if (threadIdx.x == 0) *queue = 0;
 }
 
+__global__ void k_zero_ints(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 __global__ void k_count_running(const Ctrl* __restrict__ ctrl, int nsys, int* __restrict__ out) {
   int r = 0;
   for (int s = threadIdx.x; s < nsys; s += blockDim.x)
@@ -1045,3 +1050,183 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
   return fire_ctx_error(ctx, FIRE_E_OOM, "batched: neighbour lists keep outgrowing their capacity");
 }
 
+// ------------------------------------------------- no-allocation variant
+//
+// fire_minimize_batched_noalloc runs the same kernels as the batched entry
+// points on work buffers carved out of one file-scope device array (each GPU
+// holds its own copy while the process lives), without graphs, for callers
+// that must not allocate device memory.  Everything else it needs is set up
+// once per context by fire_init: the array's device address (per device),
+// a pinned word for the status polls and host staging records.
+
+namespace fire {
+namespace bat {
+constexpr size_t kScratchBytes = size_t(64) << 20;  // work buffers of one call
+constexpr int kNoAllocMaxSys = 1024;                  // systems per call
+}  // namespace bat
+}  // namespace fire
+
+static __device__ __align__(256) unsigned char scratch[fire::bat::kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64] = {};
+
+// Device address of this device's scratch array (the device must be current).
+int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= 64) return FIRE_E_DEVICE;
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FIRE_E_DEVICE;
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return FIRE_OK;
+}
+
+struct NoAlloc {
+  int device = -1;
+  unsigned char* base = nullptr;  // scratch on `device`
+  int* h_poll = nullptr;          // pinned: queue head, running count, flags
+  SysDesc* h_desc = nullptr;      // host staging, kNoAllocMaxSys records each
+  Ctrl* h_ctrl = nullptr;
+  int* h_order = nullptr;
+};
+
+// Work buffers of one call, 256-byte aligned, in the scratch array.
+struct Carve {
+  int nsys = 0, ntot = 0, kb = 0;
+  SysDesc* desc = nullptr;
+  Ctrl* ctrl = nullptr;
+  int* order = nullptr;
+  int* queue = nullptr;
+  double* stage = nullptr;
+  double4 *pos = nullptr, *vel = nullptr, *frc = nullptr, *xref = nullptr;
+  unsigned short *nn = nullptr, *nbr = nullptr;
+  size_t bytes = 0;
+};
+
+Carve carve(unsigned char* base, int nsys, int ntot, int kb) {
+  Carve c;
+  c.nsys = nsys;
+  c.ntot = ntot;
+  c.kb = kb;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return base + o;
+  };
+  c.desc = static_cast<SysDesc*>(take(sizeof(SysDesc) * nsys));
+  c.ctrl = static_cast<Ctrl*>(take(sizeof(Ctrl) * nsys));
+  c.order = static_cast<int*>(take(sizeof(int) * nsys));
+  c.queue = static_cast<int*>(take(sizeof(int) * 8));
+  c.stage = static_cast<double*>(take(sizeof(double) * 3 * (size_t)ntot));
+  c.pos = static_cast<double4*>(take(sizeof(double4) * (size_t)ntot));
+  c.vel = static_cast<double4*>(take(sizeof(double4) * (size_t)ntot));
+  c.frc = static_cast<double4*>(take(sizeof(double4) * (size_t)ntot));
+  c.xref = static_cast<double4*>(take(sizeof(double4) * (size_t)ntot));
+  c.nn = static_cast<unsigned short*>(take(sizeof(unsigned short) * (size_t)ntot));
+  c.nbr = static_cast<unsigned short*>(take(sizeof(unsigned short) * (size_t)ntot * kb));
+  c.bytes = off;
+  return c;
+}
+
+}  // namespace
+
+extern "C" int fire_noalloc_init(int device, void** slot) {
+  NoAlloc* na = new NoAlloc();
+  void* base = nullptr;
+  int rc = scratch_address(device, &base);
+  if (!rc && hipHostMalloc((void**)&na->h_poll, 8 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    rc = FIRE_E_OOM;
+  if (rc) {
+    delete na;
+    return rc;
+  }
+  na->device = device;
+  na->base = static_cast<unsigned char*>(base);
+  na->h_desc = new SysDesc[kNoAllocMaxSys];
+  na->h_ctrl = new Ctrl[kNoAllocMaxSys];
+  na->h_order = new int[kNoAllocMaxSys];
+  *slot = na;
+  return FIRE_OK;
+}
+
+extern "C" void fire_noalloc_release(void* p) {
+  NoAlloc* na = static_cast<NoAlloc*>(p);
+  if (!na) return;
+  if (na->h_poll) (void)hipHostFree(na->h_poll);
+  delete[] na->h_desc;
+  delete[] na->h_ctrl;
+  delete[] na->h_order;
+  delete na;
+}
+
+extern "C" int fire_batched_run_noalloc(fire_ctx* ctx, void* slot, int nsys, const long long* offsets,
+                                        double* d_pos, const fire_box* boxes, const fire_potential* pot,
+                                        const fire_params* per_sys, double tol, long long max_steps,
+                                        fire_result* out, hipStream_t s) {
+  NoAlloc* na = static_cast<NoAlloc*>(slot);
+  if (!na) return fire_ctx_error(ctx, FIRE_E_DEVICE, "batched (no alloc): the context has no scratch set-up");
+  if (nsys < 1 || !offsets || !d_pos || !boxes || !pot || !out)
+    return fire_ctx_error(ctx, FIRE_E_ARG, "batched: nsys >= 1 and non-NULL arrays are required");
+  if (nsys > kNoAllocMaxSys)
+    return fire_ctx_error(ctx, FIRE_E_ARG, "batched (no alloc): at most 1024 systems per call");
+  int dev = -1;
+  BCHK(hipGetDevice(&dev));
+  if (dev != na->device)
+    return fire_ctx_error(ctx, FIRE_E_DEVICE, "batched (no alloc): the context's device must be current");
+  BatchPlan plan;
+  int rc = prepare_batch(ctx, nsys, offsets, boxes, pot, per_sys, tol, max_steps, na->h_desc, na->h_ctrl,
+                         na->h_order, &plan);
+  if (rc) return rc;
+  const PotDev& P = plan.P;
+  bool found = false;
+  const Config cfg = config_for(static_cast<Workspace*>(*fire_ctx_batched_slot(ctx)), plan,
+                                na->h_ctrl[0].precision, &found);
+  int ncu = 256;
+  BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int nteams = std::min(nsys, ncu);
+  int kb = plan.kb;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    if (carve(nullptr, nsys, plan.ntot, kb).bytes > kScratchBytes)
+      return fire_ctx_error(ctx, FIRE_E_ARG,
+                            "batched (no alloc): the batch and its neighbour lists exceed the 64 MiB scratch "
+                            "(about 160,000 atoms of the EAM-form crystals)");
+    const Carve w = carve(na->base, nsys, plan.ntot, kb);
+    // every buffer the kernels read is written here first: the array keeps
+    // the contents of the previous call on this device
+    BCHK(hipMemcpyAsync(w.desc, na->h_desc, sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(w.order, na->h_order, sizeof(int) * nsys, hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(w.ctrl, na->h_ctrl, sizeof(Ctrl) * nsys, hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(w.stage, d_pos, sizeof(double) * 3 * plan.ntot, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, w.queue, 8);
+    hipLaunchKernelGGL(k_stage, dim3((plan.ntot + 255) / 256), dim3(256), 0, s, w.stage, plan.ntot, w.pos, w.vel,
+                       w.frc, w.xref);
+    const long long max_rounds = max_steps / cfg.chunk + 4;
+    bool need_more = false;
+    for (long long r = 0; r <= max_rounds; ++r) {
+      launch_chunk(&w, P, cfg, s, nteams);
+      BCHK(hipMemcpyAsync(na->h_poll, w.queue, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      BCHK(hipStreamSynchronize(s));
+      if (na->h_poll[2]) {  // a list outgrew its capacity
+        need_more = true;
+        break;
+      }
+      if (na->h_poll[1] == 0) break;
+    }
+    if (need_more) {
+      kb = ((kb * 3 / 2 + 16) + 3) & ~3;
+      continue;
+    }
+    BCHK(hipMemcpyAsync(na->h_ctrl, w.ctrl, sizeof(Ctrl) * nsys, hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_unstage, dim3(nsys), dim3(256), 0, s, w.pos, w.desc, d_pos);
+    BCHK(hipStreamSynchronize(s));
+    fill_results(na->h_ctrl, na->h_desc, nsys, out);
+    return FIRE_OK;
+  }
+  return fire_ctx_error(ctx, FIRE_E_ARG, "batched (no alloc): neighbour lists keep outgrowing their capacity");
+}

@@ -2096,11 +2096,18 @@ struct fire_ctx {
   long long graph_key[2] = {-1, -1};
   long long layout_version = 0;
 
-  // batched workspace is owned by batched.hip
+  // batched workspace and the no-allocation set-up are owned by batched.hip
   void* batched = nullptr;
+  void* noalloc = nullptr;
 };
 
 extern "C" void fire_batched_release(void* ws);
+extern "C" __attribute__((visibility("hidden"))) int fire_noalloc_init(int device, void** slot);
+extern "C" __attribute__((visibility("hidden"))) void fire_noalloc_release(void* p);
+extern "C" __attribute__((visibility("hidden"))) int fire_batched_run_noalloc(
+    fire_ctx* ctx, void* slot, int nsys, const long long* offsets, double* d_pos, const fire_box* boxes,
+    const fire_potential* pot, const fire_params* per_sys, double tol, long long max_steps, fire_result* out,
+    hipStream_t s);
 extern "C" __attribute__((visibility("hidden"))) int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offsets, double* pos, bool host,
                                 const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
                                 double tol, long long max_steps, fire_result* out, hipStream_t s);
@@ -3406,6 +3413,9 @@ int fire_init(fire_ctx** out, int device, const fire_params* params) {
     HIPCHK(hipHostMalloc((void**)&ctx->h_zero, sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming));
+    // the scratch array of fire_minimize_batched_noalloc on this device
+    const int na = fire_noalloc_init(device, &ctx->noalloc);
+    if (na) return set_err(ctx, na, "no-allocation scratch set-up failed");
     return FIRE_OK;
   };
   rc = init();
@@ -3442,6 +3452,7 @@ void fire_finalize(fire_ctx* ctx) {
   for (int k = 0; k < 2; ++k)
     if (ctx->ev[k]) hipEventDestroy(ctx->ev[k]);
   fire_batched_release(ctx->batched);
+  fire_noalloc_release(ctx->noalloc);
   if (ctx->stream) hipStreamDestroy(ctx->stream);
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   delete ctx;
@@ -3777,6 +3788,17 @@ int fire_minimize_batched_dev(fire_ctx* ctx, int nsys, const long long* offsets,
   if (rc) return rc;
   return fire_batched_run(ctx, nsys, offsets, d_pos, false, boxes, pot, per_sys, tol, max_steps, out,
                           pick_stream(ctx, stream));
+}
+
+int fire_minimize_batched_noalloc(fire_ctx* ctx, int nsys, const long long* offsets, double* d_pos,
+                                  const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
+                                  double tol, long long max_steps, fire_result* out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = batched_no_dmax(ctx, nsys, per_sys);
+  if (rc) return rc;
+  return fire_batched_run_noalloc(ctx, ctx->noalloc, nsys, offsets, d_pos, boxes, pot, per_sys, tol, max_steps,
+                                  out, pick_stream(ctx, stream));
 }
 
 }  // extern "C"
