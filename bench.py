@@ -210,6 +210,7 @@ def measure_config(name: str, precision: str, steps: int, warmup: int, max_steps
     ctx = api.Context(0, s.fire, precision=precision)
     dt, res, _ = time_relaxations(ctx, pos0, s, steps, warmup, max_steps)
     kt = kernel_time_ms(ctx, kernel_reps)
+    tuning = ctx.fire_tuning_info()
     ctx.close()
     r = res[-1]
     staged = os.environ.get("FIRE_LDS", "1") != "0" and kind != "sw"
@@ -227,8 +228,9 @@ def measure_config(name: str, precision: str, steps: int, warmup: int, max_steps
         "force_pass_kernel": alg["kernel"] if precision == "fp64" or kind == "sw" else FP32_KERNEL[kind],
         "force_pass_hbm_frac_alg": hbm / PEAK_HBM_GBS, "force_pass_hbm_GBs_alg": hbm,
         "force_pass_alu_frac_alg": alu / peak_alu, "force_pass_TFLOPs_alg": alu,
-        "note": "force pass timed at the start positions with the run's first pair precision"
+        "note": "force pass timed at the relaxed positions with the run's first pair precision"
                 if precision != "fp64" else "",
+        "tuning": tuning,
     }
 
 

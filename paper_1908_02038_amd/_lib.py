@@ -29,7 +29,7 @@ EXPORTS = [
     "fire_last_error", "fire_stop_name", "fire_energy_forces", "fire_minimize", "fire_minimize_traced",
     "fire_hvp", "fire_lowest_curvature", "fire_minimize_batched", "fire_energy_forces_dev", "fire_hvp_dev",
     "fire_minimize_dev", "fire_minimize_batched_dev", "fire_repeat_forces_dev", "fire_minimize_ex",
-    "fire_minimize_ex_dev", "fire_minimize_batched_noalloc",
+    "fire_minimize_ex_dev", "fire_minimize_batched_noalloc", "fire_tuning_info",
 ]
 
 
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH):
     lib.fire_get_params.argtypes = [ctx_p, P(fire_params)]
     lib.fire_last_error.argtypes = [ctx_p]
     lib.fire_last_error.restype = ctypes.c_char_p
+    lib.fire_tuning_info.argtypes = [ctx_p]
+    lib.fire_tuning_info.restype = ctypes.c_char_p
     lib.fire_stop_name.argtypes = [ctypes.c_int]
     lib.fire_stop_name.restype = ctypes.c_char_p
     lib.fire_energy_forces.argtypes = [ctx_p, ll, dp, P(fire_box), P(fire_potential), dp, dp]

@@ -136,6 +136,10 @@ class Context:
         p = make_params(fire, **over)
         self._check(self.lib.fire_set_params(self.handle, ctypes.byref(p)))
 
+    def fire_tuning_info(self) -> str:
+        """The speed-only choices of the last minimisation (list order)."""
+        return self.lib.fire_tuning_info(self.handle).decode()
+
     def fire_get_params(self) -> L.fire_params:
         p = L.fire_params()
         self._check(self.lib.fire_get_params(self.handle, ctypes.byref(p)))

@@ -26,7 +26,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fire2.h"
@@ -520,12 +522,16 @@ __global__ __launch_bounds__(kBlock) void k_pos_f32(const double4* __restrict__ 
 __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict__ pos,
                                                       const float4* __restrict__ posf, int n, Grid g,
                                                       const int* __restrict__ cell_rank,
-                                                      const int* __restrict__ start, float rcs2f, int kcap,
-                                                      int dummy, int* __restrict__ nbr, int* __restrict__ wcnt,
-                                                      int* __restrict__ flags) {
+                                                      const int* __restrict__ start, float rcs2f, float split2f,
+                                                      float cut2f, int kcap, int dummy, int* __restrict__ nbr,
+                                                      int* __restrict__ wcnt, int* __restrict__ flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = i >> 6, lane = threadIdx.x & 63;
-  int cnt = 0;
+  // Three classes of entries by their distance at build time: near
+  // (r^2 < split2f), middle (split2f <= r^2 < cut2f) and far.  Near entries
+  // fill the list from the front, the others from the back (middle ones
+  // stored as -(j + 1)); each class stays in slot order.
+  int cn = 0, cb = 0;
   bool overlap = false;
   if (i < n) {
     const double4 pi = pos[i];
@@ -587,16 +593,34 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
             if (q.x == pi.x && q.y == pi.y && q.z == pi.z) overlap = true;
           }
           if (r2 < rcs2f) {
-            if (cnt < kcap) nbr[lidx(w, cnt, lane, kcap)] = j;
-            ++cnt;
+            const bool near = r2 < split2f, mid = !near && r2 < cut2f;
+            if (cn + cb < kcap) nbr[lidx(w, near ? cn : kcap - 1 - cb, lane, kcap)] = mid ? -(j + 1) : j;
+            cn += near;
+            cb += !near;
           }
         }
       }
     }
   }
-  const int m = wave_max_i(cnt);
-  const int kw = min((m + 3) & ~3, kcap);
-  for (int k = cnt; k < kw; ++k) nbr[lidx(w, k, lane, kcap)] = dummy;
+  // Final layout of each list: near, middle, then far entries, then padding
+  // to the wave's longest list (a multiple of four).  Groups of four past
+  // every lane's near + middle count hold far entries or padding only, so a
+  // pass can skip such a group with one wave-uniform test when no lane of it
+  // is within the cutoff.  The moves from the back must not overwrite an
+  // entry not yet moved: that needs cn + 2 cb <= kcap, which the reported
+  // size includes (a larger capacity and another build otherwise).
+  const int m = wave_max_i(cn + 2 * cb);
+  int kw = 0;
+  if (m <= kcap) {
+    int q = cn;
+    for (int pass = 0; pass < 2; ++pass)  // middle entries, then far ones
+      for (int f = 0; f < cb; ++f) {
+        const int v = nbr[lidx(w, kcap - 1 - f, lane, kcap)];
+        if ((v < 0) == (pass == 0)) nbr[lidx(w, q++, lane, kcap)] = v < 0 ? -v - 1 : v;
+      }
+    kw = (wave_max_i(q) + 3) & ~3;
+    for (int k = q; k < kw; ++k) nbr[lidx(w, k, lane, kcap)] = dummy;
+  }
   if (lane == 0) {
     wcnt[w] = kw;
     atomicMax(&flags[1], m);
@@ -1247,7 +1271,9 @@ __device__ __forceinline__ Halo stage_halo(const double4* __restrict__ pos, cons
 }
 
 // Neighbour loop shared by the pair kernels: one lane per atom, wave-uniform
-// trip count, four neighbours per step, software-pipelined: index groups are
+// trip count, four neighbours per step (handed to group() together, so their
+// terms interleave and a wave-uniform test can skip all four at once),
+// software-pipelined: index groups are
 // fetched two steps ahead (one 8- or 16-byte load per lane), and for global
 // gathers the positions one step ahead.  Neighbouring lanes hold neighbouring
 // atoms, so at each step they gather nearby (often identical) neighbours.
@@ -1256,7 +1282,7 @@ __device__ __forceinline__ Halo stage_halo(const double4* __restrict__ pos, cons
 template <bool LDS, bool W, typename F>
 __device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, const Halo& halo,
                                                const int* __restrict__ nbr, const Tiles& tl,
-                                               const int* __restrict__ wcnt, int kcap, int i, F&& pair) {
+                                               const int* __restrict__ wcnt, int kcap, int i, F&& group) {
   const int w = i >> 6, lane = threadIdx.x & 63;
   const int ng = __builtin_amdgcn_readfirstlane(wcnt[w]) >> 2;
   const size_t base = (size_t)w * (kcap >> 2) * 64 + lane;
@@ -1274,11 +1300,7 @@ __device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, 
       const ushort4 c = a;
       a = b;
       if (g + 2 < ng) b = l4[(size_t)(g + 2) * 64];
-      const double4 p0 = at(c.x), p1 = at(c.y), p2 = at(c.z), p3 = at(c.w);
-      pair(p0);
-      pair(p1);
-      pair(p2);
-      pair(p3);
+      group(at(c.x), at(c.y), at(c.z), at(c.w));
     }
   } else {
     const int4* l4 = reinterpret_cast<const int4*>(nbr) + base;
@@ -1303,10 +1325,7 @@ __device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, 
       }
       a = b;
       if (g + 3 < ng) b = l4[(size_t)(g + 3) * 64];
-      pair(p0);
-      pair(p1);
-      pair(p2);
-      pair(p3);
+      group(p0, p1, p2, p3);
     }
   }
 }
@@ -1410,6 +1429,47 @@ __device__ __forceinline__ double4 own_update(const UpdArgs& ua, const UpdCoef& 
   return make_double4(x[0], x[1], x[2], p.w);
 }
 
+__device__ __forceinline__ double sep2(const double4& a, const double4& b) {
+  const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  return dx * dx + dy * dy + dz * dz;
+}
+
+// One group of four neighbours of the EAM-form passes.  Nothing is added
+// when no lane has one of them within the cutoff (the far entries of the
+// lists and their padding); the taper is evaluated only when some lane has
+// one of them past r_in (in range), which in a relaxed crystal is a few
+// groups per list: pair(p, taper) with taper a compile-time bool.  The
+// taper threshold is widened by 1e-12 relative so that rounding of r never
+// skips it where it differs from 1.
+template <typename T, typename F>
+__device__ __forceinline__ void group_terms(const double4& pi, const double4& p0, const double4& p1,
+                                            const double4& p2, const double4& p3, const PotDev& pot, F&& pair) {
+  if constexpr (sizeof(T) == 4) {
+    // FP32 terms: branch-free (measured faster there; their arithmetic per
+    // entry is short enough that the tests do not pay)
+    pair(p0, std::true_type{});
+    pair(p1, std::true_type{});
+    pair(p2, std::true_type{});
+    pair(p3, std::true_type{});
+    return;
+  }
+  const double a0 = sep2(pi, p0), a1 = sep2(pi, p1), a2 = sep2(pi, p2), a3 = sep2(pi, p3);
+  if (!wave_any(a0 < pot.rc2 || a1 < pot.rc2 || a2 < pot.rc2 || a3 < pot.rc2)) return;
+  const double t2 = pot.r_in * pot.r_in * (1.0 - 1e-12);
+  auto past = [&](double a) { return a < pot.rc2 && a > t2; };
+  if (wave_any(past(a0) || past(a1) || past(a2) || past(a3))) {
+    pair(p0, std::true_type{});
+    pair(p1, std::true_type{});
+    pair(p2, std::true_type{});
+    pair(p3, std::true_type{});
+  } else {
+    pair(p0, std::false_type{});
+    pair(p1, std::false_type{});
+    pair(p2, std::false_type{});
+    pair(p3, std::false_type{});
+  }
+}
+
 // Energy-shifted LJ.  Separations and the r^2 < rc^2 test in FP64; the pair
 // terms and per-atom accumulation in T (double, or float for the mixed path).
 // WE: accumulate the energy (the FIRE logic itself needs only forces).
@@ -1451,11 +1511,11 @@ __global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict
     pi = pos[i];
   }
   const T eps24 = (T)(24.0 * pot.eps), eps4 = (T)(4.0 * pot.eps), sig2 = (T)pot.sig2, sh = (T)pot.shift;
-  for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
+  auto pair = [&](const double4& pj) {
     const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    // branch-free: out-of-range lanes (including the far padding) evaluate at
-    // r = 1 and get a zero weight, so the pairs of a step interleave
+    // branch-free within the wave: out-of-range lanes (including the far
+    // padding) evaluate at r = 1 and get a zero weight
     const bool in = r2 < pot.rc2;
     T ir2;
     if constexpr (sizeof(T) == 8) ir2 = rcp_d(in ? r2 : 1.0);
@@ -1466,7 +1526,14 @@ __global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict
     ay += fr * (T)dy;
     az += fr * (T)dz;
     if constexpr (WE) ae += in ? (T)0.5 * (eps4 * s6 * (s6 - (T)1) - sh) : (T)0;
-  });
+  };
+  for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i,
+                             [&](const double4& p0, const double4& p1, const double4& p2, const double4& p3) {
+                               pair(p0);
+                               pair(p1);
+                               pair(p2);
+                               pair(p3);
+                             });
   force_epilogue<kMaxTile>(i, valid, (double)ax, (double)ay, (double)az, (double)ae, ep, frc, vel, ncap, part, 0.0,
                            b, ctrl, trace, pr, UPD);
 }
@@ -1503,18 +1570,26 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
   }
   const T qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in, inv_w = (T)pot.inv_w;
   T rho = 0;
-  for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
-    const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
+  auto pair = [&](const double4& pj, auto taper) {
+    const double r2 = sep2(pi, pj);
     const bool in = r2 < pot.rc2;
     T r;
     if constexpr (sizeof(T) == 8) r = sqrt(in ? r2 : 1.0);
     else r = sqrtf(in ? (float)r2 : 1.0f);
-    const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
-    const T S = (1 - s) * (1 - s) * (1 + 2 * s);
-    const T v = exp(-qr0 * (r - r0)) * S;
-    rho += in ? v : (T)0;
-  });
+    T S = 1;  // the taper is 1 below r_in
+    if constexpr (decltype(taper)::value) {
+      const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
+      S = (1 - s) * (1 - s) * (1 + 2 * s);
+    }
+    T e;
+    if constexpr (sizeof(T) == 8) e = exp_d(-qr0 * (r - r0));
+    else e = exp(-qr0 * (r - r0));
+    rho += in ? e * S : (T)0;
+  };
+  for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i,
+                             [&](const double4& p0, const double4& p1, const double4& p2, const double4& p3) {
+                               group_terms<T>(pi, p0, p1, p2, p3, pot, pair);
+                             });
   if (i < n) {
     double fp = 0.0;
     if (rho > 0) {
@@ -1560,7 +1635,7 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
   const double4 pi = pos[i];
   const T A = (T)pot.A, pr0 = (T)pot.pr0, qr0 = (T)pot.qr0, r0 = (T)pot.r0, r_in = (T)pot.r_in,
           inv_w = (T)pot.inv_w, cpair = (T)pot.cpair, epair = (T)pot.epair, fpi = (T)pi.w;
-  for_neighbours<LDS, true>(pos, halo, nbr, tl, wcnt, kcap, i, [&](const double4& pj) {
+  auto pair = [&](const double4& pj, auto taper) {
     const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     const bool in = r2 < pot.rc2;
@@ -1569,11 +1644,20 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
     if constexpr (sizeof(T) == 8) ir = rsqrt_d(r2c);
     else ir = rsqrt_f((float)r2c);
     const T r = (T)r2c * ir;
-    const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
-    const T S = (1 - s) * (1 - s) * (1 + 2 * s);
-    const T dS = (T)(-6) * s * (1 - s) * inv_w;
-    const T ph = A * exp(-pr0 * (r - r0));
-    const T rh = exp(-qr0 * (r - r0));
+    T S = 1, dS = 0;  // the taper and its slope are 1 and 0 below r_in
+    if constexpr (decltype(taper)::value) {
+      const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);
+      S = (1 - s) * (1 - s) * (1 + 2 * s);
+      dS = (T)(-6) * s * (1 - s) * inv_w;
+    }
+    T ph, rh;
+    if constexpr (sizeof(T) == 8) {
+      ph = A * exp_d(-pr0 * (r - r0));
+      rh = exp_d(-qr0 * (r - r0));
+    } else {
+      ph = A * exp(-pr0 * (r - r0));
+      rh = exp(-qr0 * (r - r0));
+    }
     const T dph = ph * (dS - pr0 * S);
     const T drh = rh * (dS - qr0 * S);
     const T fpj = in ? (T)pj.w : (T)0;
@@ -1583,7 +1667,11 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
     ay += fr * (T)dy;
     az += fr * (T)dz;
     if constexpr (WE) ae += in ? epair * ph * S : (T)0;
-  });
+  };
+  for_neighbours<LDS, true>(pos, halo, nbr, tl, wcnt, kcap, i,
+                            [&](const double4& p0, const double4& p1, const double4& p2, const double4& p3) {
+                              group_terms<T>(pi, p0, p1, p2, p3, pot, pair);
+                            });
   force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, ep, frc, vel, ncap, part, emb, b,
                  ctrl, trace, pr);
 }
@@ -2089,6 +2177,11 @@ struct fire_ctx {
   Grid grid{};
   double rcs = 0.0, skin = 0.0;
   bool have_list = false;
+  // speed-only choices of the single-system path (see tune_single)
+  bool list_classes = false;
+  bool tune_loaded = false;
+  std::map<std::string, int> tuned;
+  std::string tuning_info = "none";
 
   // captured iteration graphs: [precision]
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -2551,6 +2644,16 @@ int build_lists(fire_ctx* ctx) {
     if (ctx->grid.inv[k] > 0) ext = std::max(ext, ctx->grid.n[k] / ctx->grid.inv[k]);
   const double widen = 4.0 * std::sqrt(3.0) * ext * std::ldexp(1.0, -24);
   const float rcs2f = (float)((ctx->rcs + widen) * (ctx->rcs + widen) * (1.0 + std::ldexp(1.0, -20)));
+  // Order of each list (speed only: every entry is tested against the
+  // cutoff at every evaluation).  One class in slot order, or (EAM form, when
+  // the tuner picks it) entries closer than the start of the taper at build
+  // time, then those within the cutoff, then the rest of the skin, so that
+  // the FP64 passes skip the taper in most groups and whole groups beyond
+  // the cutoff, at the price of neighbouring lanes reading less related
+  // neighbours at each step.
+  const bool classes = ctx->pot.kind == FIRE_POT_GUPTA && ctx->list_classes;
+  const float split2f = classes ? (float)(ctx->pot.r_in * ctx->pot.r_in) : rcs2f;
+  const float cut2f = classes ? (float)ctx->pot.rc2 : rcs2f;
   hipLaunchKernelGGL(k_pos_f32, dim3(nblocks(n + ctx->ng)), dim3(kBlock), 0, s, ctx->pos, n + ctx->ng, ctx->grid,
                      ctx->posf);
   const bool was = ctx->use_lds;
@@ -2574,7 +2677,8 @@ int build_lists(fire_ctx* ctx) {
     }
     HIPCHK(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), s));
     hipLaunchKernelGGL(k_nbr_build, dim3(ctx->ncap / kBlock), dim3(kBlock), 0, s, ctx->pos, ctx->posf, n, ctx->grid,
-                       ctx->cell_rank, ctx->cell_start, rcs2f, ctx->kcap, dummy, ctx->nbr, ctx->wcnt, ctx->flags);
+                       ctx->cell_rank, ctx->cell_start, rcs2f, split2f, cut2f, ctx->kcap, dummy, ctx->nbr,
+                       ctx->wcnt, ctx->flags);
     if (hcap >= 64) {
       if (tile == kMaxTile)
         hipLaunchKernelGGL(k_tile_halo<kMaxTile>, dim3(nt), dim3(kMaxTile), 0, s, ctx->srank, ctx->cell_start,
@@ -3094,9 +3198,117 @@ int resume(fire_ctx* ctx, hipStream_t s) {
   return FIRE_OK;
 }
 
+// Average time of one force evaluation of the current system and lists, as
+// inside the loop (see fire_repeat_forces_dev), in milliseconds.
+int time_evaluation(fire_ctx* ctx, hipStream_t s, int prec, int reps, float* ms) {
+  ctrl_defaults(ctx, *ctx->h_ctrl, 0.0, 0, 1);
+  HIPCHK(hipMemcpyAsync(ctx->ctrl, ctx->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  auto one = [&]() {
+    if (fold_update(ctx)) launch_pairs<false>(ctx, s, prec, 0);
+    else launch_forces(ctx, s, prec, false);
+  };
+  one();
+  one();
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) one();
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  HIPCHK(hipEventElapsedTime(ms, e0, e1));
+  *ms /= reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (fold_update(ctx))  // the passes wrote the second state set and its index
+    hipLaunchKernelGGL(k_ghost_refresh, dim3(1), dim3(kBlock), 0, s, ctx->n, 0, ctx->pos, ctx->real_of, ctx->gcode,
+                       ctx->box, ctx->ctrl);
+  return FIRE_OK;
+}
+
+std::string tune_cache_path() {
+  const char* p = getenv("FIRE_TUNE_CACHE");
+  if (p && *p) return std::string(p) + ".single";
+  const char* h = getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/fire2_tune_single.txt";
+}
+
+// The single-system autotuner.  Some choices change speed only; the first
+// minimisation of a class of systems (potential, starting pair precision,
+// size in powers of two, periodic axes) times one force evaluation of its
+// start positions under each candidate, keeps the fastest, and records it in
+// the context and in a cache file that later processes read
+// ($FIRE_TUNE_CACHE.single, default ~/.cache/fire2_tune_single.txt).  Today
+// the one choice is the list order of the EAM form (FIRE_LIST_CLASSES=0|1
+// fixes it); small systems keep one class without timing.  The start lists
+// are rebuilt with the choice before the run begins.
+int tune_single(fire_ctx* ctx, hipStream_t s) {
+  if (ctx->pot.kind != FIRE_POT_GUPTA) return FIRE_OK;
+  bool want = ctx->list_classes;
+  if (const char* e = getenv("FIRE_LIST_CLASSES")) {
+    want = e[0] == '1';
+    ctx->tuning_info = std::string("list order ") + (want ? "classes" : "slot") + " (FIRE_LIST_CLASSES)";
+  } else if (ctx->n < 16384) {
+    want = false;
+    ctx->tuning_info = "list order slot (small system, not tuned)";
+  } else {
+    const int prec = ctx->params.precision == FIRE_FP64 ? 0 : 1;
+    int lg = 0;
+    while ((1 << (lg + 1)) <= ctx->n) ++lg;
+    char key[96];
+    snprintf(key, sizeof key, "gupta_prec%d_n2e%d_per%d%d%d", prec, lg, ctx->box.per[0], ctx->box.per[1],
+             ctx->box.per[2]);
+    if (!ctx->tune_loaded) {
+      ctx->tune_loaded = true;
+      FILE* f = fopen(tune_cache_path().c_str(), "r");
+      if (f) {
+        char k[96];
+        int v;
+        while (fscanf(f, "%95s %d", k, &v) == 2) ctx->tuned[k] = v;
+        fclose(f);
+      }
+    }
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) {
+      want = it->second != 0;
+      ctx->tuning_info = std::string("list order ") + (want ? "classes" : "slot") + " (cached for " + key + ")";
+    } else {
+      float t[2] = {0, 0};
+      for (int c = 0; c < 2; ++c) {
+        ctx->list_classes = c == 1;
+        int rc = rebuild(ctx);
+        if (rc) return rc;
+        rc = time_evaluation(ctx, s, prec, 6, &t[c]);
+        if (rc) return rc;
+      }
+      want = t[1] < t[0];
+      ctx->tuned[key] = want ? 1 : 0;
+      char info[192];
+      snprintf(info, sizeof info, "list order %s (tuned for %s: %.1f us slot, %.1f us classes)",
+               want ? "classes" : "slot", key, 1e3 * t[0], 1e3 * t[1]);
+      ctx->tuning_info = info;
+      FILE* f = fopen(tune_cache_path().c_str(), "w");
+      if (f) {
+        for (auto& kv : ctx->tuned) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+        fclose(f);
+      }
+      if (want) return FIRE_OK;  // the lists of the last candidate are the chosen ones
+      ctx->list_classes = false;
+      return rebuild(ctx);
+    }
+  }
+  if (want != ctx->list_classes) {
+    ctx->list_classes = want;
+    return rebuild(ctx);
+  }
+  return FIRE_OK;
+}
+
 int minimize_impl(fire_ctx* ctx, hipStream_t s, double tol, long long max_steps, fire_result* out) {
   if (max_steps < 0) return set_err(ctx, FIRE_E_ARG, "max_steps must be >= 0");
   int rc = rebuild(ctx);
+  if (rc) return rc;
+  rc = tune_single(ctx, s);
   if (rc) return rc;
   long long rebuilds = 1;
   ctrl_defaults(ctx, *ctx->h_ctrl, tol, max_steps, 0);
@@ -3374,6 +3586,8 @@ const char* fire_stop_name(int r) {
 }
 
 const char* fire_last_error(const fire_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+const char* fire_tuning_info(const fire_ctx* ctx) { return ctx ? ctx->tuning_info.c_str() : "no context"; }
 
 int fire_init(fire_ctx** out, int device, const fire_params* params) {
   if (!out) return FIRE_E_ARG;

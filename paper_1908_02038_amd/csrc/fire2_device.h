@@ -34,6 +34,38 @@ __device__ __forceinline__ double rsqrt_d(double x) {
   return y * fma(-h * y, y, 1.5);
 }
 __device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// True in every lane when any active lane has c (a wave-uniform branch).
+__device__ __forceinline__ bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
+
+// e^x in FP64 for the pair terms (arguments of a few tens at most): with
+// k = rint(x / ln 2) and r = x - k ln 2, |r| <= ln(2)/2, e^x = 2^k e^r and
+// e^r is its Taylor series to r^13 (the remainder is below 1e-17 of the
+// result).  ln 2 enters as a 32-bit leading part, whose product with k is
+// exact, plus the rest (Cody and Waite's reduction).  No special cases:
+// callers keep x finite and far from the overflow and underflow limits.
+__device__ __forceinline__ double exp_d(double x) {
+  constexpr double kLog2e = 1.4426950408889634074;
+  constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 to 32 bits
+  constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - kLn2Hi
+  const double k = __builtin_rint(x * kLog2e);
+  const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, x));
+  double p = 1.0 / 6227020800.0;  // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)k);
+}
 __device__ __forceinline__ float rsqrt_f(float x) {
   float y = __builtin_amdgcn_rsqf(x);
   return y * fmaf(-0.5f * x * y, y, 1.5f);
