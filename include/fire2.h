@@ -194,8 +194,9 @@ int fire_set_params(fire_ctx* ctx, const fire_params* params);
 int fire_get_params(const fire_ctx* ctx, fire_params* params);
 const char* fire_last_error(const fire_ctx* ctx);
 /* The speed-only choices the single-system path made for the last
- * minimisation on ctx, as text: the list order of the EAM form, timed on
- * the system's start positions the first time a class of systems is seen
+ * minimisation on ctx, as text: the list order of the EAM form and the LDS
+ * reservation of its tile blocks, timed on the system's start positions the
+ * first time a class of systems is seen
  * (potential, starting precision, size in powers of two, periodic axes) and
  * cached per context and in $FIRE_TUNE_CACHE.single (default
  * ~/.cache/fire2_tune_single.txt).  Results differ between choices only by

@@ -26,6 +26,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fire2.h"
@@ -133,7 +134,10 @@ struct Team {
 
   // Cell list and neighbour list of the current positions (wrapped into the
   // box on periodic axes).  Lists: nbr[off*kb + k*n + a], counts nn[off + a].
-  __device__ void build(unsigned short* __restrict__ nbr, unsigned short* __restrict__ nn, int kb) {
+  // Each list holds the atoms within the cutoff (rc2) at build time first,
+  // then the rest of the skin, each part in the order of the cell sweep, so
+  // that the FP64 passes can skip groups of four beyond the cutoff.
+  __device__ void build(unsigned short* __restrict__ nbr, unsigned short* __restrict__ nn, int kb, double rc2) {
     double lo3[3], hi3[3];
     for (int q = 0; q < 3; ++q) {
       lo3[q] = INFINITY;
@@ -271,7 +275,7 @@ struct Team {
       const double4 pa = sh.x[a];
       const int c0 = cell_of(pa);
       const int cc[3] = {c0 % sh.nc[0], (c0 / sh.nc[0]) % sh.nc[1], c0 / (sh.nc[0] * sh.nc[1])};
-      int m = 0;
+      int m = 0, mb = 0;  // entries from the front (within rc) and from the back (the rest)
       for (int oz = sh.lo_off[2]; oz <= sh.hi_off[2]; ++oz) {
         int cz = cc[2] + oz;
         if (d.box.per[2]) cz = (cz + sh.nc[2]) % sh.nc[2];
@@ -294,14 +298,21 @@ struct Team {
               const double r2 = dx * dx + dy * dy + dz * dz;
               if (r2 == 0.0) atomicOr(&sh.overflow, 2);
               if (r2 < d.rcs2) {
-                if (m < kb) nbr[nidx(base, n, a, m)] = (unsigned short)j;
-                ++m;
+                const bool in = r2 < rc2;
+                if (m + mb < kb) nbr[nidx(base, n, a, in ? m : kb - 1 - mb)] = (unsigned short)j;
+                m += in;
+                mb += !in;
               }
             }
           }
         }
       }
-      if (m > kb) atomicOr(&sh.overflow, 1);
+      // the skin entries move from the back to follow the others: that must
+      // not overwrite one not yet moved, so the capacity must hold m + 2 mb
+      if (m + 2 * mb > kb) atomicOr(&sh.overflow, 1);
+      else
+        for (int f = 0; f < mb; ++f) nbr[nidx(base, n, a, m + f)] = nbr[nidx(base, n, a, kb - 1 - f)];
+      m += mb;
       for (int q = m; q < ((m + 3) & ~3) && q < kb; ++q) nbr[nidx(base, n, a, q)] = (unsigned short)a;
       nn[d.off + a] = (unsigned short)min(m, kb);
     }
@@ -310,13 +321,18 @@ struct Team {
 };
 
 // Pair terms shared by the passes (branch-free; callers mask by `in`).
-template <typename T>
+template <typename T, bool TAPER = true>
 __device__ __forceinline__ T gupta_density_term(double r2, const PotDev& P) {
   T r;
   if constexpr (sizeof(T) == 8) r = sqrt(r2);
   else r = sqrtf((float)r2);
-  const T s = fmin(fmax((r - (T)P.r_in) * (T)P.inv_w, (T)0), (T)1);
-  return exp(-(T)P.qr0 * (r - (T)P.r0)) * (1 - s) * (1 - s) * (1 + 2 * s);
+  T S = 1;  // the taper is 1 below r_in
+  if constexpr (TAPER) {
+    const T s = fmin(fmax((r - (T)P.r_in) * (T)P.inv_w, (T)0), (T)1);
+    S = (1 - s) * (1 - s) * (1 + 2 * s);
+  }
+  if constexpr (sizeof(T) == 8) return exp_d(-P.qr0 * (r - P.r0)) * S;
+  else return exp(-(T)P.qr0 * (r - (T)P.r0)) * S;
 }
 
 // Neighbour loop of the team passes: groups of four indices, the next group
@@ -326,7 +342,7 @@ template <int TEAM, int MAXPT, typename F>
 __device__ __forceinline__ void for_team_neighbours(const Team<TEAM, MAXPT>& tm,
                                                     const unsigned short* __restrict__ nbr,
                                                     const unsigned short* __restrict__ nn, size_t base, int a,
-                                                    F&& pair) {
+                                                    F&& group) {
   const int m = nn[tm.d.off + a];
   const int ng = (m + 3) >> 2;
   const ushort4* l4 = reinterpret_cast<const ushort4*>(nbr + base) + a;
@@ -335,11 +351,51 @@ __device__ __forceinline__ void for_team_neighbours(const Team<TEAM, MAXPT>& tm,
   for (int g = 0; g < ng; ++g) {
     const ushort4 c = cur;
     if (g + 1 < ng) cur = l4[(size_t)(g + 1) * stride];
-    const double4 p0 = tm.sh.x[c.x], p1 = tm.sh.x[c.y], p2 = tm.sh.x[c.z], p3 = tm.sh.x[c.w];
-    pair(4 * g, m, p0);
-    pair(4 * g + 1, m, p1);
-    pair(4 * g + 2, m, p2);
-    pair(4 * g + 3, m, p3);
+    group(4 * g, m, tm.sh.x[c.x], tm.sh.x[c.y], tm.sh.x[c.z], tm.sh.x[c.w]);
+  }
+}
+
+// One group of four list entries (numbers q0 .. q0+3 of m) of the team
+// passes: pair(q, pj, taper) for each.  In FP64 the group is skipped when
+// no active lane has an entry of it within the cutoff, and the taper is
+// evaluated only when one is past r_in; FP32 terms stay branch-free (as in
+// the single-system passes).
+template <typename T, typename F>
+__device__ __forceinline__ void team_group(const Img& img, const double4& pa, const PotDev& P, int q0, int m,
+                                           const double4& p0, const double4& p1, const double4& p2,
+                                           const double4& p3, F&& pair) {
+  if constexpr (sizeof(T) == 4) {
+    pair(q0, p0, std::true_type{});
+    pair(q0 + 1, p1, std::true_type{});
+    pair(q0 + 2, p2, std::true_type{});
+    pair(q0 + 3, p3, std::true_type{});
+  } else {
+    auto r2of = [&](const double4& pj) {
+      double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
+      img.apply(dx, dy, dz);
+      return dx * dx + dy * dy + dz * dz;
+    };
+    const double a[4] = {r2of(p0), r2of(p1), r2of(p2), r2of(p3)};
+    bool any = false, past = false;
+    const double t2 = P.kind == FIRE_POT_GUPTA ? P.r_in * P.r_in * (1.0 - 1e-12) : P.rc2;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = q0 + u < m && a[u] < P.rc2;
+      any = any || in;
+      past = past || (in && a[u] > t2);
+    }
+    if (!wave_any(any)) return;
+    if (wave_any(past)) {
+      pair(q0, p0, std::true_type{});
+      pair(q0 + 1, p1, std::true_type{});
+      pair(q0 + 2, p2, std::true_type{});
+      pair(q0 + 3, p3, std::true_type{});
+    } else {
+      pair(q0, p0, std::false_type{});
+      pair(q0 + 1, p1, std::false_type{});
+      pair(q0 + 2, p2, std::false_type{});
+      pair(q0 + 3, p3, std::false_type{});
+    }
   }
 }
 
@@ -357,14 +413,18 @@ __device__ void density_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsig
     if (a >= tm.n) continue;
     const double4 pa = tm.sh.x[a];
     T rho = 0;
-    for_team_neighbours(tm, nbr, nn, base, a, [&](int q, int m, const double4& pj) {
+    const int m = nn[d.off + a];  // list length (entries past it are padding)
+    auto pair = [&](int q, const double4& pj, auto taper) {
       double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
       img.apply(dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
       const bool in = q < m && r2 < P.rc2;
-      const T v = gupta_density_term<T>(in ? r2 : 1.0, P);
+      const T v = gupta_density_term<T, decltype(taper)::value>(in ? r2 : 1.0, P);
       rho += in ? v : (T)0;
-    });
+    };
+    for_team_neighbours(tm, nbr, nn, base, a,
+                        [&](int q0, int mm, const double4& p0, const double4& p1, const double4& p2,
+                            const double4& p3) { team_group<T>(img, pa, P, q0, mm, p0, p1, p2, p3, pair); });
     double fp = 0.0;
     if (rho > 0) {
       const double sq = sqrt((double)rho);
@@ -395,7 +455,8 @@ __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigne
     if (a >= tm.n) continue;
     const double4 pa = tm.sh.x[a];
     T ax = 0, ay = 0, az = 0, ae = 0;
-    for_team_neighbours(tm, nbr, nn, base, a, [&](int q, int m, const double4& pj) {
+    const int m = nn[d.off + a];  // list length (entries past it are padding)
+    auto pair = [&](int q, const double4& pj, auto taper) {
       double dx = pa.x - pj.x, dy = pa.y - pj.y, dz = pa.z - pj.z;
       img.apply(dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
@@ -414,11 +475,20 @@ __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigne
         if constexpr (sizeof(T) == 8) ir = rsqrt_d(r2c);
         else ir = rsqrt_f((float)r2c);
         const T rr = (T)r2c * ir;
-        const T s = fmin(fmax((rr - (T)P.r_in) * (T)P.inv_w, (T)0), (T)1);
-        const T S = (1 - s) * (1 - s) * (1 + 2 * s);
-        const T dS = (T)(-6) * s * (1 - s) * (T)P.inv_w;
-        const T ph = (T)P.A * exp(-(T)P.pr0 * (rr - (T)P.r0));
-        const T rh = exp(-(T)P.qr0 * (rr - (T)P.r0));
+        T S = 1, dS = 0;  // the taper and its slope are 1 and 0 below r_in
+        if constexpr (decltype(taper)::value) {
+          const T s = fmin(fmax((rr - (T)P.r_in) * (T)P.inv_w, (T)0), (T)1);
+          S = (1 - s) * (1 - s) * (1 + 2 * s);
+          dS = (T)(-6) * s * (1 - s) * (T)P.inv_w;
+        }
+        T ph, rh;
+        if constexpr (sizeof(T) == 8) {
+          ph = P.A * exp_d(-P.pr0 * (rr - P.r0));
+          rh = exp_d(-P.qr0 * (rr - P.r0));
+        } else {
+          ph = (T)P.A * exp(-(T)P.pr0 * (rr - (T)P.r0));
+          rh = exp(-(T)P.qr0 * (rr - (T)P.r0));
+        }
         const T dEdr = (T)P.cpair * ph * (dS - (T)P.pr0 * S) + ((T)pa.w + (T)pj.w) * rh * (dS - (T)P.qr0 * S);
         fr = -dEdr * ir;
         e = (T)P.epair * ph * S;
@@ -428,7 +498,10 @@ __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigne
       ay += fr * (T)dy;
       az += fr * (T)dz;
       ae += in ? e : (T)0;
-    });
+    };
+    for_team_neighbours(tm, nbr, nn, base, a,
+                        [&](int q0, int mm, const double4& p0, const double4& p1, const double4& p2,
+                            const double4& p3) { team_group<T>(img, pa, P, q0, mm, p0, p1, p2, p3, pair); });
     double4 v = tm.vel[a];
     const double fx = ax, fy = ay, fz = az;
     tm.frc[a] = make_double4(fx, fy, fz, 0.0);
@@ -543,7 +616,7 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
     }
     bool ok = true;
     if (sh.viol) {  // first visit (or after a capacity change): build the list
-      tm.build(nbr, nn, kb);
+      tm.build(nbr, nn, kb, P.rc2);
       if (sh.overflow) ok = false;
     }
     if (ok && c->evals == 0) {  // evaluation 0 and the set-up of iteration 1
@@ -587,7 +660,7 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
       if (viol) sh.viol = 1;
       __syncthreads();
       if (sh.viol) {
-        tm.build(nbr, nn, kb);
+        tm.build(nbr, nn, kb, P.rc2);
         if (sh.overflow) {
           ok = false;
           break;

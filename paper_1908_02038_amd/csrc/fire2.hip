@@ -2179,6 +2179,7 @@ struct fire_ctx {
   bool have_list = false;
   // speed-only choices of the single-system path (see tune_single)
   bool list_classes = false;
+  int eam_two_blocks = -1;  // EAM-form LDS reservation: -1 by size, 0: three blocks per CU, 1: two
   bool tune_loaded = false;
   std::map<std::string, int> tuned;
   std::string tuning_info = "none";
@@ -2621,8 +2622,9 @@ constexpr long long kL2Atoms = 8LL * (4 << 20) / 96;
 size_t lds_budget(const fire_ctx* ctx, int tile) {
   if (!ctx->lds_default) return ctx->lds_limit;
   size_t d = ctx->lds_limit;
+  const bool large = ctx->eam_two_blocks < 0 ? ctx->n > kL2Atoms : ctx->eam_two_blocks > 0;
   if (tile == kMaxTile) d = std::min(kLdsLj, ctx->lds_cap);
-  else if (ctx->pot.kind == FIRE_POT_GUPTA && ctx->n > kL2Atoms) d = std::min(kLdsEamLarge, ctx->lds_cap);
+  else if (ctx->pot.kind == FIRE_POT_GUPTA && large) d = std::min(kLdsEamLarge, ctx->lds_cap);
   return std::max(d, std::min(ctx->lds_boost, ctx->lds_cap));
 }
 
@@ -3238,10 +3240,13 @@ std::string tune_cache_path() {
 // size in powers of two, periodic axes) times one force evaluation of its
 // start positions under each candidate, keeps the fastest, and records it in
 // the context and in a cache file that later processes read
-// ($FIRE_TUNE_CACHE.single, default ~/.cache/fire2_tune_single.txt).  Today
-// the one choice is the list order of the EAM form (FIRE_LIST_CLASSES=0|1
-// fixes it); small systems keep one class without timing.  The start lists
-// are rebuilt with the choice before the run begins.
+// ($FIRE_TUNE_CACHE.single, default ~/.cache/fire2_tune_single.txt).  The
+// choices are those of the EAM form: the list order (one class in slot
+// order, or three distance classes; FIRE_LIST_CLASSES=0|1 fixes it) and the
+// LDS reservation of its tile blocks (three or two blocks per CU; the size
+// rule decides when FIRE_LIST_CLASSES is set).  Small systems keep one class
+// and the size rule without timing.  The start lists are rebuilt with the
+// choice before the run begins.
 int tune_single(fire_ctx* ctx, hipStream_t s) {
   if (ctx->pot.kind != FIRE_POT_GUPTA) return FIRE_OK;
   bool want = ctx->list_classes;
@@ -3268,34 +3273,47 @@ int tune_single(fire_ctx* ctx, hipStream_t s) {
         fclose(f);
       }
     }
+    auto describe = [](int c) {
+      return std::string("list order ") + ((c & 1) ? "classes" : "slot") + ", " + ((c & 2) ? "two" : "three") +
+             " EAM blocks per CU";
+    };
     auto it = ctx->tuned.find(key);
+    int choice;
     if (it != ctx->tuned.end()) {
-      want = it->second != 0;
-      ctx->tuning_info = std::string("list order ") + (want ? "classes" : "slot") + " (cached for " + key + ")";
+      choice = it->second & 3;
+      ctx->tuning_info = describe(choice) + " (cached for " + key + ")";
     } else {
-      float t[2] = {0, 0};
-      for (int c = 0; c < 2; ++c) {
-        ctx->list_classes = c == 1;
+      float t[4] = {0, 0, 0, 0};
+      for (int c = 0; c < 4; ++c) {
+        ctx->list_classes = (c & 1) != 0;
+        ctx->eam_two_blocks = (c >> 1) & 1;
         int rc = rebuild(ctx);
         if (rc) return rc;
         rc = time_evaluation(ctx, s, prec, 6, &t[c]);
         if (rc) return rc;
       }
-      want = t[1] < t[0];
-      ctx->tuned[key] = want ? 1 : 0;
-      char info[192];
-      snprintf(info, sizeof info, "list order %s (tuned for %s: %.1f us slot, %.1f us classes)",
-               want ? "classes" : "slot", key, 1e3 * t[0], 1e3 * t[1]);
-      ctx->tuning_info = info;
+      choice = 0;
+      for (int c = 1; c < 4; ++c)
+        if (t[c] < t[choice]) choice = c;
+      ctx->tuned[key] = choice;
+      char info[256];
+      snprintf(info, sizeof info, " (tuned for %s: slot/three %.1f, classes/three %.1f, slot/two %.1f, "
+               "classes/two %.1f us)", key, 1e3 * t[0], 1e3 * t[1], 1e3 * t[2], 1e3 * t[3]);
+      ctx->tuning_info = describe(choice) + info;
       FILE* f = fopen(tune_cache_path().c_str(), "w");
       if (f) {
         for (auto& kv : ctx->tuned) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
         fclose(f);
       }
-      if (want) return FIRE_OK;  // the lists of the last candidate are the chosen ones
-      ctx->list_classes = false;
+    }
+    const bool cls = (choice & 1) != 0;
+    const int two = (choice >> 1) & 1;
+    if (cls != ctx->list_classes || two != ctx->eam_two_blocks || it == ctx->tuned.end()) {
+      ctx->list_classes = cls;
+      ctx->eam_two_blocks = two;
       return rebuild(ctx);
     }
+    return FIRE_OK;
   }
   if (want != ctx->list_classes) {
     ctx->list_classes = want;
