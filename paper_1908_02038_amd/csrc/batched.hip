@@ -538,7 +538,7 @@ __device__ void evaluate(Team<TEAM, MAXPT>& tm, Ctrl* __restrict__ c, const PotD
   if (threadIdx.x == 0) {
     // unit masses: the mass-weighted sums are P and |F|^2
     const double q[kCtl] = {r[0], r[1], r[2], r[3], r[4], r[5], r[1], r[2]};
-    fire_control(c, q, nullptr);
+    fire_control(*c, c, q, nullptr);
     if (c->status == ST_PAUSED && c->pause == PAUSE_PRECISION) {
       c->status = ST_RUNNING;  // the team switches its own pair precision
       c->pause = 0;

@@ -40,29 +40,30 @@ namespace fire {
 // ------------------------------------------------------------------ helpers
 
 // Block-level reduction of NS sums followed by NM maxima; result valid in
-// thread 0.  Order is fixed by the thread layout, so results are
-// reproducible run to run.  MAXB: the largest block size of the caller (its
-// LDS scratch is sized for it; kernels at the LDS limit keep the default).
+// the first wave (thread 0 among them).  Each wave reduces by lane moves,
+// then the first wave reduces the per-wave results the same way.  The order
+// is fixed by the thread layout, so results are reproducible run to run.
+// MAXB: the largest block size of the caller (its LDS scratch is sized for
+// it; kernels at the LDS limit keep the default).
 template <int NS, int NM, int MAXB = kBlock>
 __device__ __forceinline__ void block_reduce(double (&v)[NS + NM]) {
-  __shared__ double red[MAXB / 64][NS + NM];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ double red[NS + NM][MAXB / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int k = 0; k < NS; ++k) v[k] = wave_sum(v[k]);
 #pragma unroll
   for (int k = NS; k < NS + NM; ++k) v[k] = wave_max(v[k]);
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < NS + NM; ++k) red[w][k] = v[k];
+    for (int k = 0; k < NS + NM; ++k) red[k][w] = v[k];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+  if (w == 0) {
+    const bool has = lane < nw;
 #pragma unroll
-      for (int k = 0; k < NS; ++k) v[k] += red[q][k];
+    for (int k = 0; k < NS; ++k) v[k] = wave_sum(has ? red[k][lane % (MAXB / 64)] : 0.0);
 #pragma unroll
-      for (int k = NS; k < NS + NM; ++k) v[k] = fmax(v[k], red[q][k]);
-    }
+    for (int k = NS; k < NS + NM; ++k) v[k] = wave_max(has ? red[k][lane % (MAXB / 64)] : -INFINITY);
   }
 }
 
@@ -1165,47 +1166,89 @@ __device__ __forceinline__ void force_epilogue(int i, bool valid, double fx, dou
     // matters: such a fence writes back and invalidates the XCD's whole L2
     // under every other block still running there.  Later kernels see the
     // rest of this pass's output through the kernel boundary.
-    double* o = part + (size_t)kRed * rec;
+    // Records are stored field by field (field k of block b at k * grid + b),
+    // so the last block's lanes read consecutive words.
     const double vals[kCtl] = {r[0] + emb, r[1], r[2], r[3], r[4], r[5], rm[0], rm[1]};
     const int nv = pr.sinv ? kCtl : 6;
-    for (int k = 0; k < nv; ++k) __hip_atomic_store(o + k, vals[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int k = 0; k < nv; ++k)
+      __hip_atomic_store(part + (size_t)k * gridDim.x + rec, vals[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_s_waitcnt(0);
     const unsigned int t = __hip_atomic_fetch_add(&ctrl->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (t == gridDim.x - 1);
   }
   __syncthreads();
   if (!is_last) return;
-  double q[6] = {0, 0, 0, 0, 0, 0};
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-    const double* o = part + (size_t)kRed * b;
-    q[0] += ld_cohere(o + R_E);
-    q[1] += ld_cohere(o + R_P);
-    q[2] += ld_cohere(o + R_F2);
-    q[3] += ld_cohere(o + R_V2);
-    q[4] = fmax(q[4], ld_cohere(o + R_FMAX2));
-    q[5] = fmax(q[5], ld_cohere(o + R_VMAX2));
+  // Second stage: each lane reads up to four records per round with all
+  // their loads in flight at once (one memory round trip per round), then the
+  // lanes reduce.  Up to 256 records one wave does it alone (no LDS, no
+  // barrier); beyond that the whole block reads and reduces.  Either order
+  // is fixed for a given grid.  Without masses the mass-weighted sums are P
+  // and |F|^2 exactly and are not read.
+  const int nb = (int)gridDim.x;
+  const bool one_wave = nb <= 4 * 64;
+  if (one_wave && threadIdx.x >= 64) return;
+  const int lanes = one_wave ? 64 : (int)blockDim.x;
+  const int nv = pr.sinv ? kCtl : 6;
+  // The control record and the skin flag, read once, in flight with the
+  // records: nothing writes the record during the pass but this thread below,
+  // and every block set the flag (device-scope atomic, completed) before
+  // taking its ticket.
+  Ctrl snap;
+  int viol = 0;
+  if (threadIdx.x == 0) {
+    snap = *ctrl;
+    if (check_viol) viol = __hip_atomic_load(&ctrl->viol, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  block_reduce<4, 2, MAXB>(q);
-  // without masses the mass-weighted sums are P and |F|^2 exactly
-  double qm[2] = {q[R_P], q[R_F2]};
-  if (pr.sinv) {
-    qm[0] = qm[1] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-      qm[0] += ld_cohere(part + (size_t)kRed * b + R_SVF);
-      qm[1] += ld_cohere(part + (size_t)kRed * b + R_SFF);
+  double q[6] = {0, 0, 0, 0, 0, 0};
+  double qm[2] = {0, 0};
+  for (int b0 = 0; b0 < nb; b0 += 4 * lanes) {
+    double t[4][kCtl];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * lanes + (int)threadIdx.x;
+#pragma unroll
+      for (int k = 0; k < kCtl; ++k) t[u][k] = (b < nb && k < nv) ? ld_cohere(part + (size_t)k * nb + b) : 0.0;
     }
-    block_reduce<2, 0, MAXB>(qm);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      q[0] += t[u][R_E];
+      q[1] += t[u][R_P];
+      q[2] += t[u][R_F2];
+      q[3] += t[u][R_V2];
+      q[4] = fmax(q[4], t[u][R_FMAX2]);
+      q[5] = fmax(q[5], t[u][R_VMAX2]);
+      qm[0] += t[u][R_SVF];
+      qm[1] += t[u][R_SFF];
+    }
+  }
+  if (one_wave) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = wave_sum(q[k]);
+    q[4] = wave_max(q[4]);
+    q[5] = wave_max(q[5]);
+    if (pr.sinv) {
+      qm[0] = wave_sum(qm[0]);
+      qm[1] = wave_sum(qm[1]);
+    }
+  } else {
+    block_reduce<4, 2, MAXB>(q);
+    if (pr.sinv) block_reduce<2, 0, MAXB>(qm);
+  }
+  if (!pr.sinv) {
+    qm[0] = q[R_P];
+    qm[1] = q[R_F2];
   }
   if (threadIdx.x == 0) {
     const double qc[kCtl] = {q[0], q[1], q[2], q[3], q[4], q[5], qm[0], qm[1]};
     ctrl->ticket = 0;
-    if (check_viol && __hip_atomic_load(&ctrl->viol, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (viol) {
       // the update applied in this pass moved an atom past its skin: these
       // forces used a stale list; hand over for a rebuild, FIRE state unchanged
-      ctrl->pause |= PAUSE_REBUILD;
+      ctrl->pause = snap.pause | PAUSE_REBUILD;
       __hip_atomic_store(&ctrl->status, ST_PAUSED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      fire_control(ctrl, qc, trace);
+      snap.ticket = 0;
+      fire_control(snap, ctrl, qc, trace);
     }
   }
 }

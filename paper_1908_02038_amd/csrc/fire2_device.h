@@ -9,15 +9,48 @@
 
 namespace fire {
 
+// A double moved across lanes by a DPP control (two 32-bit moves).  Lanes
+// in rows that ROWS leaves out receive id.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_d(double v, double id) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned long long o = __builtin_bit_cast(unsigned long long, id);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double lane63(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum (max) over the 64 lanes, returned to every lane.  Register-to-register
+// lane moves in a fixed order: neighbours in a quad (lane ^ 1, lane ^ 2),
+// the mirrored half row and row (eight, then sixteen lanes), then lane 15 of
+// each row into the next row and lane 31 into the upper two rows; lane 63
+// then holds the total.  The same order every time, so results repeat bit
+// for bit.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1>(v, 0.0);        // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v, 0.0);        // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v, 0.0);       // row_half_mirror
+  v += dpp_d<0x140>(v, 0.0);       // row_mirror
+  v += dpp_d<0x142, 0xa>(v, 0.0);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v, 0.0);  // row_bcast:31 into rows 2 and 3
+  return lane63(v);
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_d<0xB1>(v, -INFINITY));
+  v = fmax(v, dpp_d<0x4E>(v, -INFINITY));
+  v = fmax(v, dpp_d<0x141>(v, -INFINITY));
+  v = fmax(v, dpp_d<0x140>(v, -INFINITY));
+  v = fmax(v, dpp_d<0x142, 0xa>(v, -INFINITY));
+  v = fmax(v, dpp_d<0x143, 0xc>(v, -INFINITY));
+  return lane63(v);
 }
 
 // 1/x and 1/sqrt(x) from the hardware estimates plus Newton steps (one step
@@ -71,138 +104,167 @@ __device__ __forceinline__ float rsqrt_f(float x) {
   return y * fmaf(-0.5f * x * y, y, 1.5f);
 }
 
+// What the P test at the start of iteration i decides (Algorithm 2, or
+// Algorithm 1 for the original FIRE): the new dt and alpha, the alpha the
+// original FIRE mixes with (the one before this test), the counters of
+// consecutive P > 0 and P <= 0 steps, and whether P <= 0 has now held more
+// than N_P<=0max times in a row (the MAXVDOTF stop).
+struct Adapt {
+  double dt, alpha, alpha_mix;
+  long long npos, nneg;
+  int neg, stop;
+};
+
+__device__ inline Adapt fire_adapt(const Ctrl& c, double P, long long i) {
+  Adapt a{c.dt, c.alpha, c.alpha, c.npos, c.nneg, P > 0.0 ? 0 : 1, 0};
+  if (!a.neg) {
+    a.npos += 1;
+    a.nneg = 0;
+    if (a.npos > c.delaystep) {
+      a.dt = fmin(a.dt * c.dtgrow, c.dtmax);
+      a.alpha *= c.alphashrink;
+    }
+    return a;
+  }
+  a.npos = 0;
+  if (c.variant != FIRE_VARIANT_FIRE2) {  // original FIRE: shrink and reset at once
+    a.dt *= c.dtshrink;
+    a.alpha = c.alpha0;
+    return a;
+  }
+  a.nneg += 1;
+  if (a.nneg > c.vdfmax) {
+    a.stop = 1;
+    return a;
+  }
+  if (!(c.initialdelay && i < c.delaystep)) {  // no shrink during the initial delay
+    if (a.dt * c.dtshrink >= c.dtmin) a.dt *= c.dtshrink;
+    a.alpha = c.alpha0;
+  }
+  return a;
+}
+
+// Coefficients of the next update for the chosen integrator (Algorithms 3,
+// 4, 6): kick before the drift (k1), kick with the drift's old force (k2,
+// explicit Euler), kick after the new force (k3), and the mixing
+// v <- cv v + cf |v| F / |F|, applied after the first kick (FIRE 2.0) or at
+// the start of the step (original FIRE, mix_first).
+struct UpdCoefs {
+  double k1, k2, k3, cv, cf;
+  int mix_first;
+};
+
+__device__ inline UpdCoefs fire_coefficients(const Ctrl& c, const Adapt& a, double V2, double F2, double SvF,
+                                             double SFF) {
+  const double dtf = a.dt * c.f2a;
+  UpdCoefs u{dtf, 0.0, 0.0, 0.0, 0.0, 0};
+  if (c.integrator == FIRE_INT_EULER_EXPLICIT) {
+    u.k1 = 0.0;
+    u.k2 = dtf;
+  } else if (c.integrator == FIRE_INT_VERLET) {
+    u.k1 = 0.5 * dtf;
+    u.k3 = 0.5 * dtf;
+  }
+  const double fn = sqrt(F2);
+  if (c.variant == FIRE_VARIANT_FIRE2) {
+    // |v| of the velocity being mixed, from the reductions: the kick gives
+    // atom i v_i + k1 s_i F_i, so |v|^2 = V2 + 2 k1 sum s v.F + k1^2 sum s^2 F^2
+    // (after P <= 0 the velocities are zero: V2 and sum s v.F drop out)
+    const double V2e = a.neg ? 0.0 : V2, SvFe = a.neg ? 0.0 : SvF;
+    const double vn = sqrt(fmax(V2e + 2.0 * u.k1 * SvFe + u.k1 * u.k1 * SFF, 0.0));
+    u.cv = 1.0 - a.alpha;
+    u.cf = fn > 0.0 ? a.alpha * vn / fn : 0.0;
+  } else {
+    u.mix_first = 1;
+    u.cv = a.neg ? 1.0 : 1.0 - a.alpha_mix;
+    u.cf = (a.neg || !(fn > 0.0)) ? 0.0 : a.alpha_mix * sqrt(V2) / fn;
+  }
+  return u;
+}
+
 // The scalar FIRE logic (one thread) on the reduced E, P, |F|^2, |v|^2,
 // max|F_i|^2, max|v_i|^2, sum s_i v_i.F_i, sum s_i^2 |F_i|^2 of the force
 // evaluation just finished (the last two equal P and |F|^2 when every
-// s_i = 1/m_i is 1): stop tests, then the branch of Algorithm 2 (or 1) for
-// the next iteration and the coefficients of the next update.
-__device__ inline void fire_control(Ctrl* __restrict__ c, const double (&r)[kCtl], double* __restrict__ trace) {
+// s_i = 1/m_i is 1): stop tests, then the P test for the next iteration and
+// the coefficients of the next update.  c is a snapshot of *cp taken by the
+// caller (one load of the whole record, so no field costs a memory round
+// trip of its own); the fields this step changes are written to *cp.
+__device__ inline void fire_control(const Ctrl c, Ctrl* __restrict__ cp, const double (&r)[kCtl],
+                                    double* __restrict__ trace) {
   const double E = r[0], P = r[1], F2 = r[2], V2 = r[3], fm = sqrt(r[4]), vm = sqrt(r[5]);
-  c->energy = E;
-  c->P = P;
-  c->F2 = F2;
-  c->v2 = V2;
-  c->fmax = fm;
-  c->f2norm = sqrt(F2);
-  c->vmax = vm;
-  c->evals += 1;
-  const long long it = c->iter;
-  if (c->precision) c->iter_low += (it > 0);
-  if (c->error & ERR_OVERLAP) {
-    c->status = FIRE_E_OVERLAP;
+  cp->energy = E;
+  cp->P = P;
+  cp->F2 = F2;
+  cp->v2 = V2;
+  cp->fmax = fm;
+  cp->f2norm = sqrt(F2);
+  cp->vmax = vm;
+  cp->evals = c.evals + 1;
+  const long long it = c.iter;
+  if (c.precision) cp->iter_low = c.iter_low + (it > 0);
+  if (c.error & ERR_OVERLAP) {
+    cp->status = FIRE_E_OVERLAP;
     return;
   }
-  if (!isfinite(E) || !isfinite(F2) || (c->error & ERR_NONFINITE)) {
-    c->status = FIRE_E_NONFINITE;
+  if (!isfinite(E) || !isfinite(F2) || (c.error & ERR_NONFINITE)) {
+    cp->status = FIRE_E_NONFINITE;
     return;
   }
-  if (c->eval_only) return;
-  if (trace && it < c->trace_cap) {
+  if (c.eval_only) return;
+  if (trace && it < c.trace_cap) {
     double* t = trace + (size_t)FIRE_TRACE_COLS * it;
     t[0] = (double)it;
     t[1] = E;
     t[2] = fm;
     t[3] = sqrt(F2);
-    t[4] = c->P_used;
-    t[5] = c->dt;
-    t[6] = c->alpha;
-    t[7] = (double)c->branch;
-    t[8] = (double)c->npos;
+    t[4] = c.P_used;
+    t[5] = c.dt;
+    t[6] = c.alpha;
+    t[7] = (double)c.branch;
+    t[8] = (double)c.npos;
   }
-  const double crit = c->criterion == FIRE_CRIT_FMAX ? fm : sqrt(F2);
-  if (crit < c->tol) {
-    c->status = FIRE_STOP_CONVERGED;
+  const double crit = c.criterion == FIRE_CRIT_FMAX ? fm : sqrt(F2);
+  if (crit < c.tol) {
+    cp->status = FIRE_STOP_CONVERGED;
     return;
   }
-  if (it >= c->max_steps) {
-    c->status = FIRE_STOP_MAX_STEPS;
+  if (it >= c.max_steps) {
+    cp->status = FIRE_STOP_MAX_STEPS;
     return;
   }
   int pause = 0;
-  if (c->precision && c->mode == FIRE_MIXED && crit < c->switch_tol) {
-    c->precision = 0;
+  if (c.precision && c.mode == FIRE_MIXED && crit < c.switch_tol) {
+    cp->precision = 0;
     pause |= PAUSE_PRECISION;
   }
-  // ---- start of iteration i = it + 1: the branch of Algorithm 2 (or 1)
-  const long long i = it + 1;
-  double dt = c->dt, alpha = c->alpha;
-  const double alpha_mix = alpha;  // Algorithm 1 mixes before alpha decays
-  int neg;
-  if (P > 0.0) {
-    neg = 0;
-    c->npos += 1;
-    c->nneg = 0;
-    if (c->npos > c->delaystep) {
-      dt = fmin(dt * c->dtgrow, c->dtmax);
-      alpha *= c->alphashrink;
-    }
-  } else {
-    neg = 1;
-    c->npos = 0;
-    if (c->variant == FIRE_VARIANT_FIRE2) {
-      c->nneg += 1;
-      if (c->nneg > c->vdfmax) {
-        c->status = FIRE_STOP_MAXVDOTF;
-        return;
-      }
-      if (!(c->initialdelay && i < c->delaystep)) {
-        if (dt * c->dtshrink >= c->dtmin) dt *= c->dtshrink;
-        alpha = c->alpha0;
-      }
-    } else {
-      dt *= c->dtshrink;
-      alpha = c->alpha0;
-    }
+  const Adapt a = fire_adapt(c, P, it + 1);
+  cp->npos = a.npos;
+  cp->nneg = a.nneg;
+  if (a.stop) {
+    cp->status = FIRE_STOP_MAXVDOTF;
+    return;
   }
-  const double dtf = dt * c->f2a;
-  const double fn = sqrt(F2);
-  const double V2e = neg ? 0.0 : V2, SvFe = neg ? 0.0 : r[R_SVF], SFF = r[R_SFF];
-  double k1, k2, k3, cv, cf;
-  int mix_first = 0;
-  if (c->integrator == FIRE_INT_EULER_EXPLICIT) {
-    k1 = 0.0;
-    k2 = dtf;
-    k3 = 0.0;
-  } else if (c->integrator == FIRE_INT_VERLET) {
-    k1 = 0.5 * dtf;
-    k2 = 0.0;
-    k3 = 0.5 * dtf;
-  } else {
-    k1 = dtf;
-    k2 = 0.0;
-    k3 = 0.0;
-  }
-  if (c->variant == FIRE_VARIANT_FIRE2) {
-    // |v| of the velocity being mixed, from the reductions: the kick gives
-    // atom i v_i + k1 s_i F_i, so |v|^2 = V2 + 2 k1 sum s v.F + k1^2 sum s^2 F^2
-    const double vn = sqrt(fmax(V2e + 2.0 * k1 * SvFe + k1 * k1 * SFF, 0.0));
-    cv = 1.0 - alpha;
-    cf = fn > 0.0 ? alpha * vn / fn : 0.0;
-  } else {
-    mix_first = 1;
-    cv = neg ? 1.0 : 1.0 - alpha_mix;
-    cf = (neg || !(fn > 0.0)) ? 0.0 : alpha_mix * sqrt(V2) / fn;
-  }
-  c->dt = dt;
-  c->alpha = alpha;
-  c->branch = neg ? -1 : 1;
-  c->P_used = P;
-  c->neg = neg;
-  c->mix_first = mix_first;
+  const UpdCoefs u = fire_coefficients(c, a, V2, F2, r[R_SVF], r[R_SFF]);
+  cp->dt = a.dt;
+  cp->alpha = a.alpha;
+  cp->branch = a.neg ? -1 : 1;
+  cp->P_used = P;
+  cp->neg = a.neg;
+  cp->mix_first = u.mix_first;
   // the half step back undoes half of a step; with a displacement cap that
   // step is min(dt, dmax / max_i |v_i|) of the velocity being undone
-  const double dth = (c->dmax > 0.0 && vm * dt > c->dmax) ? c->dmax / vm : dt;
-  c->hsb = (neg && c->variant == FIRE_VARIANT_FIRE2 && c->halfstepback) ? 0.5 * dth : 0.0;
-  c->kick1 = k1;
-  c->kick2 = k2;
-  c->kick3 = k3;
-  c->cv = cv;
-  c->cf = cf;
-  c->dtx = dt;
-  c->iter = i;
+  const double dth = (c.dmax > 0.0 && vm * a.dt > c.dmax) ? c.dmax / vm : a.dt;
+  cp->hsb = (a.neg && c.variant == FIRE_VARIANT_FIRE2 && c.halfstepback) ? 0.5 * dth : 0.0;
+  cp->kick1 = u.k1;
+  cp->kick2 = u.k2;
+  cp->kick3 = u.k3;
+  cp->cv = u.cv;
+  cp->cf = u.cf;
+  cp->dtx = a.dt;
+  cp->iter = it + 1;
   if (pause) {
-    c->pause = pause;
-    c->status = ST_PAUSED;
+    cp->pause = pause;
+    cp->status = ST_PAUSED;
   }
 }
 
