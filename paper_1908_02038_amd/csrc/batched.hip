@@ -114,6 +114,7 @@ struct TeamShared {
   // coefficients of the next update
   int neg, mix_first, prec;
   double hsb, k1, k2, k3, cv, cf, dtx;
+  double etab[32];  // table of the FP64 exponential
 };
 
 template <int TEAM, int MAXPT>
@@ -322,16 +323,16 @@ struct Team {
 
 // Pair terms shared by the passes (branch-free; callers mask by `in`).
 template <typename T, bool TAPER = true>
-__device__ __forceinline__ T gupta_density_term(double r2, const PotDev& P) {
+__device__ __forceinline__ T gupta_density_term(double r2, const PotDev& P, const double* __restrict__ etab) {
   T r;
-  if constexpr (sizeof(T) == 8) r = sqrt(r2);
+  if constexpr (sizeof(T) == 8) r = r2 * rsqrt_d(r2);
   else r = sqrtf((float)r2);
   T S = 1;  // the taper is 1 below r_in
   if constexpr (TAPER) {
     const T s = fmin(fmax((r - (T)P.r_in) * (T)P.inv_w, (T)0), (T)1);
     S = (1 - s) * (1 - s) * (1 + 2 * s);
   }
-  if constexpr (sizeof(T) == 8) return exp_d(-P.qr0 * (r - P.r0)) * S;
+  if constexpr (sizeof(T) == 8) return exp_t(-P.qr0 * (r - P.r0), etab) * S;
   else return exp(-(T)P.qr0 * (r - (T)P.r0)) * S;
 }
 
@@ -419,7 +420,7 @@ __device__ void density_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsig
       img.apply(dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
       const bool in = q < m && r2 < P.rc2;
-      const T v = gupta_density_term<T, decltype(taper)::value>(in ? r2 : 1.0, P);
+      const T v = gupta_density_term<T, decltype(taper)::value>(in ? r2 : 1.0, P, tm.sh.etab);
       rho += in ? v : (T)0;
     };
     for_team_neighbours(tm, nbr, nn, base, a,
@@ -483,8 +484,8 @@ __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigne
         }
         T ph, rh;
         if constexpr (sizeof(T) == 8) {
-          ph = P.A * exp_d(-P.pr0 * (rr - P.r0));
-          rh = exp_d(-P.qr0 * (rr - P.r0));
+          ph = P.A * exp_t(-P.pr0 * (rr - P.r0), tm.sh.etab);
+          rh = exp_t(-P.qr0 * (rr - P.r0), tm.sh.etab);
         } else {
           ph = (T)P.A * exp(-(T)P.pr0 * (rr - (T)P.r0));
           rh = exp(-(T)P.qr0 * (rr - (T)P.r0));
@@ -568,6 +569,7 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
                                                   unsigned short* __restrict__ nbr, unsigned short* __restrict__ nn,
                                                   int kb, PotDev P, int chunk, int* __restrict__ flags) {
   __shared__ TeamShared sh;
+  exp_table_fill(sh.etab);  // published by the loop's first barrier
   for (;;) {
     if (threadIdx.x == 0) {
       const int q = atomicAdd(queue, 1);

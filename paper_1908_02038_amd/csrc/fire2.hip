@@ -1617,8 +1617,12 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
     const double r2 = sep2(pi, pj);
     const bool in = r2 < pot.rc2;
     T r;
-    if constexpr (sizeof(T) == 8) r = sqrt(in ? r2 : 1.0);
-    else r = sqrtf(in ? (float)r2 : 1.0f);
+    if constexpr (sizeof(T) == 8) {
+      const double r2c = in ? r2 : 1.0;
+      r = r2c * rsqrt_d(r2c);
+    } else {
+      r = sqrtf(in ? (float)r2 : 1.0f);
+    }
     T S = 1;  // the taper is 1 below r_in
     if constexpr (decltype(taper)::value) {
       const T s = fmin(fmax((r - r_in) * inv_w, (T)0), (T)1);

@@ -99,6 +99,52 @@ __device__ __forceinline__ double exp_d(double x) {
   p = fma(p, r, 1.0);
   return __builtin_ldexp(p, (int)k);
 }
+
+// 2^(j/32), j = 0..31, each rounded to the nearest double: the table of the
+// FP64 exponential below.  Blocks that use it copy it to LDS first.
+static __constant__ double kExp2Frac32[32] = {
+    0x1.0000000000000p+0, 0x1.059b0d3158574p+0, 0x1.0b5586cf9890fp+0, 0x1.11301d0125b51p+0,
+    0x1.172b83c7d517bp+0, 0x1.1d4873168b9aap+0, 0x1.2387a6e756238p+0, 0x1.29e9df51fdee1p+0,
+    0x1.306fe0a31b715p+0, 0x1.371a7373aa9cbp+0, 0x1.3dea64c123422p+0, 0x1.44e086061892dp+0,
+    0x1.4bfdad5362a27p+0, 0x1.5342b569d4f82p+0, 0x1.5ab07dd485429p+0, 0x1.6247eb03a5585p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.71f75e8ec5f74p+0, 0x1.7a11473eb0187p+0, 0x1.82589994cce13p+0,
+    0x1.8ace5422aa0dbp+0, 0x1.93737b0cdc5e5p+0, 0x1.9c49182a3f090p+0, 0x1.a5503b23e255dp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b7f76f2fb5e47p+0, 0x1.c199bdd85529cp+0, 0x1.cb720dcef9069p+0,
+    0x1.d5818dcfba487p+0, 0x1.dfc97337b9b5fp+0, 0x1.ea4afa2a490dap+0, 0x1.f50765b6e4540p+0,
+};
+
+// Threads 0..31 copy the table to the block's LDS array t; the caller's
+// next barrier publishes it.
+__device__ __forceinline__ void exp_table_fill(double* t) {
+  if (threadIdx.x < 32) t[threadIdx.x] = kExp2Frac32[threadIdx.x];
+}
+
+// e^x in FP64 for the pair terms, table-driven (Tang's method, 1989): with
+// k = rint(32 x / ln 2) = 32 m + j (0 <= j < 32) and r = x - k ln 2 / 32,
+// |r| <= ln 2 / 64 and e^x = 2^m 2^(j/32) e^r.  e^r - 1 is its Taylor series
+// to r^6 (the remainder is below 4e-18) and joins the table entry in one
+// fma.  ln 2 / 32 enters as a leading part of 32 bits, whose product with k
+// is exact, plus the rest (Cody and Waite's reduction).  No special cases:
+// callers keep x finite and far from the overflow and underflow limits.
+// tab: the LDS copy of the table.
+__device__ __forceinline__ double exp_t(double x, const double* __restrict__ tab) {
+  constexpr double kScale = 46.166241308446829036;              // 32 / ln 2
+  constexpr double kHi = 6.93147180369123816490e-01 / 32;      // exact: ln 2 to 32 bits, over 32
+  constexpr double kLo = 1.90821492927058770002e-10 / 32;
+  const double kd = __builtin_rint(x * kScale);
+  const double r = fma(-kd, kLo, fma(-kd, kHi, x));
+  const int k = (int)kd;
+  double q = 1.0 / 720.0;
+  q = fma(q, r, 1.0 / 120.0);
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  q *= r;  // e^r - 1
+  const double t = tab[k & 31];
+  return __builtin_ldexp(fma(t, q, t), k >> 5);
+}
+
 __device__ __forceinline__ float rsqrt_f(float x) {
   float y = __builtin_amdgcn_rsqf(x);
   return y * fmaf(-0.5f * x * y, y, 1.5f);
