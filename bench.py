@@ -256,13 +256,18 @@ COPY_BYTES = 256 << 20
 
 
 def kernel_only(args, s, pos0):
-    """Force pass alone (list built from the workload's start positions), then
-    one plain device copy of COPY_BYTES: the copy reads and writes exactly
-    COPY_BYTES each, which calibrates the byte counters of the same run."""
+    """Force pass alone (lists built from the workload's start positions as a
+    relaxation builds them; FIRE_LIST_CLASSES fixes the list order without
+    the tuner's timing runs), then one plain device copy of COPY_BYTES: the
+    copy reads and writes exactly COPY_BYTES each, which calibrates the byte
+    counters of the same run."""
     import torch
     from paper_1908_02038_amd import api
-    ctx = api.Context(0, s.fire, precision="fp64")
-    ctx.fire_energy_forces_dev(pos0, s.box, s.potential)
+    ctx = api.Context(0, s.fire, precision=args.kernel_precision)
+    # a minimisation of no steps: lists built (and the list order chosen) as
+    # a relaxation of this workload starts
+    work = pos0.clone()
+    ctx.fire_minimize_dev(work, s.box, s.potential, s.tol, 0)
     torch.cuda.synchronize()
     kt = kernel_time_ms(ctx, args.kernel_reps)
     ctx.close()
@@ -271,7 +276,8 @@ def kernel_only(args, s, pos0):
     torch.cuda.synchronize()
     b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"kernel_only": args.workload, "atoms": len(s.pos), "ms_per_launch": kt,
+    print(json.dumps({"kernel_only": args.workload, "precision": args.kernel_precision, "atoms": len(s.pos),
+                      "ms_per_launch": kt,
                       "reps": args.kernel_reps, "copy_bytes": COPY_BYTES}), flush=True)
 
 
@@ -301,7 +307,7 @@ def cpu_baseline(s, budget_s: float):
             t0 = time.perf_counter()
             oracle.energy_forces(s.pos, s.box, s.potential)
             t1 = time.perf_counter() - t0
-            steps = max(1, min(20, int(share * budget_s / max(t1, 1e-9)) - 1))
+            steps = max(1, min(500, int(share * budget_s / max(t1, 1e-9)) - 1))
             t0 = time.perf_counter()
             r = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, s.tol, steps)
             dt = time.perf_counter() - t0
@@ -454,6 +460,8 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the dominant force pass (reps launches) and a plain copy of known size; "
                          "for hardware-counter runs")
+    ap.add_argument("--kernel-precision", choices=["fp64", "mixed", "fp32"], default="fp64",
+                    help="pair precision of the --kernel-only passes (mixed starts with FP32 pair terms)")
     ap.add_argument("--study", choices=["integrators", "sweep", "batched_sweep"],
                     help="instead of the bench line: one JSON line of the integrator comparison or the parameter "
                          "sweep")

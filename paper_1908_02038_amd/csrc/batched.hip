@@ -326,14 +326,14 @@ template <typename T, bool TAPER = true>
 __device__ __forceinline__ T gupta_density_term(double r2, const PotDev& P, const double* __restrict__ etab) {
   T r;
   if constexpr (sizeof(T) == 8) r = r2 * rsqrt_d(r2);
-  else r = sqrtf((float)r2);
+  else r = sqrt_f((float)r2);
   T S = 1;  // the taper is 1 below r_in
   if constexpr (TAPER) {
     const T s = fmin(fmax((r - (T)P.r_in) * (T)P.inv_w, (T)0), (T)1);
     S = (1 - s) * (1 - s) * (1 + 2 * s);
   }
   if constexpr (sizeof(T) == 8) return exp_t(-P.qr0 * (r - P.r0), etab) * S;
-  else return exp(-(T)P.qr0 * (r - (T)P.r0)) * S;
+  else return exp_f(-(T)P.qr0 * (r - (T)P.r0)) * S;
 }
 
 // Neighbour loop of the team passes: groups of four indices, the next group
@@ -487,8 +487,8 @@ __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigne
           ph = P.A * exp_t(-P.pr0 * (rr - P.r0), tm.sh.etab);
           rh = exp_t(-P.qr0 * (rr - P.r0), tm.sh.etab);
         } else {
-          ph = (T)P.A * exp(-(T)P.pr0 * (rr - (T)P.r0));
-          rh = exp(-(T)P.qr0 * (rr - (T)P.r0));
+          ph = (T)P.A * exp_f(-(T)P.pr0 * (rr - (T)P.r0));
+          rh = exp_f(-(T)P.qr0 * (rr - (T)P.r0));
         }
         const T dEdr = (T)P.cpair * ph * (dS - (T)P.pr0 * S) + ((T)pa.w + (T)pj.w) * rh * (dS - (T)P.qr0 * S);
         fr = -dEdr * ir;

@@ -1621,7 +1621,7 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
       const double r2c = in ? r2 : 1.0;
       r = r2c * rsqrt_d(r2c);
     } else {
-      r = sqrtf(in ? (float)r2 : 1.0f);
+      r = sqrt_f(in ? (float)r2 : 1.0f);
     }
     T S = 1;  // the taper is 1 below r_in
     if constexpr (decltype(taper)::value) {
@@ -1630,7 +1630,7 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
     }
     T e;
     if constexpr (sizeof(T) == 8) e = exp_d(-qr0 * (r - r0));
-    else e = exp(-qr0 * (r - r0));
+    else e = exp_f(-qr0 * (r - r0));
     rho += in ? e * S : (T)0;
   };
   for_neighbours<LDS, false>(pos, halo, nbr, tl, wcnt, kcap, i,
@@ -1702,8 +1702,8 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
       ph = A * exp_d(-pr0 * (r - r0));
       rh = exp_d(-qr0 * (r - r0));
     } else {
-      ph = A * exp(-pr0 * (r - r0));
-      rh = exp(-qr0 * (r - r0));
+      ph = A * exp_f(-pr0 * (r - r0));
+      rh = exp_f(-qr0 * (r - r0));
     }
     const T dph = ph * (dS - pr0 * S);
     const T drh = rh * (dS - qr0 * S);

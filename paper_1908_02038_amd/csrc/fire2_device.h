@@ -145,6 +145,24 @@ __device__ __forceinline__ double exp_t(double x, const double* __restrict__ tab
   return __builtin_ldexp(fma(t, q, t), k >> 5);
 }
 
+// FP32 pair terms: the hardware square root (within 1 ulp; the arguments
+// are squared separations of a few A^2, far from denormals).
+__device__ __forceinline__ float sqrt_f(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// e^x in FP32 for the pair terms: x log2(e) as the rounded product plus its
+// rounding error (one fma) and the error of log2(e) in float, the integer
+// part applied by ldexp and 2^(the rest) by the hardware base-2 exponential.
+// Arguments stay within a few tens, so there is no overflow or underflow
+// handling.
+__device__ __forceinline__ float exp_f(float x) {
+  constexpr float kL = 1.44269502162933349609375f;  // log2(e) rounded to float
+  constexpr float kLlo = 1.925962991126617e-8f;     // log2(e) - kL
+  const float ph = x * kL;
+  const float pl = fmaf(x, kL, -ph) + x * kLlo;
+  const float e = __builtin_rintf(ph);
+  return __builtin_ldexpf(__builtin_amdgcn_exp2f((ph - e) + pl), (int)e);
+}
+
 __device__ __forceinline__ float rsqrt_f(float x) {
   float y = __builtin_amdgcn_rsqf(x);
   return y * fmaf(-0.5f * x * y, y, 1.5f);
