@@ -47,7 +47,8 @@ def test_missing_traffic_file_gives_null(tmp_path, monkeypatch):
 def test_committed_traffic_summary_names_its_commands_and_calibration():
     path = os.path.join(ROOT, "profiles", "traffic_k_lj_force_fused_lj_bulk.json")
     rec = json.load(open(path))
-    assert all(c.startswith("cd /tmp && rocprofv3 --pmc ") for c in rec["commands"])
+    assert all(c.startswith("cd /tmp && ") and " rocprofv3 --pmc " in c and " -- python3 $R/bench.py " in c
+               for c in rec["commands"])
     cal = rec["calibration"]
     # the factors scale raw counter KiB to the bytes a copy of known size
     # reads (and writes)
