@@ -155,7 +155,22 @@ def bench_batched(args):
         res = ctx.fire_minimize_batched_dev(work, offs, boxes, pot, tol, args.max_steps)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    tuning = ctx.fire_tuning_info()
     ctx.close()
+    # the same batch with FP32 pair terms until each system's criterion falls
+    # below its switch, then FP64
+    ctxm = api.Context(0, fire, precision="mixed")
+    for _ in range(max(1, args.warmup)):
+        work.copy_(src)
+        ctxm.fire_minimize_batched_dev(work, offs, boxes, pot, tol, args.max_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        work.copy_(src)
+        res_m = ctxm.fire_minimize_batched_dev(work, offs, boxes, pot, tol, args.max_steps)
+    torch.cuda.synchronize()
+    dtm = (time.perf_counter() - t0) / args.steps
+    ctxm.close()
     atom_evals = sum(len(s.pos) * r["force_evals"] for s, r in zip(systems, res))
     iters = sum(r["iterations"] for r in res)
     stops = [r["stop"] for r in res]
@@ -194,6 +209,11 @@ def bench_batched(args):
         "plain_fp64_steps_per_s": plain_iters / tp,
         "plain_sample": f"every 16th system ({len(sample)}), relaxed one after another by fire_minimize_dev",
         "speedup_vs_plain": val / plain,
+        "tuning": tuning,
+        "mixed": {"ms_per_batch": dtm * 1e3,
+                  "value": sum(len(s.pos) * r["force_evals"] for s, r in zip(systems, res_m)) / dtm,
+                  "all_converged": all(r["stop"] == "converged" for r in res_m),
+                  "max_iterations": max(r["iterations"] for r in res_m)},
     }
 
 

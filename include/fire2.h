@@ -193,14 +193,16 @@ void fire_finalize(fire_ctx* ctx);
 int fire_set_params(fire_ctx* ctx, const fire_params* params);
 int fire_get_params(const fire_ctx* ctx, fire_params* params);
 const char* fire_last_error(const fire_ctx* ctx);
-/* The speed-only choices the single-system path made for the last
- * minimisation on ctx, as text: the list order of the EAM form and the LDS
+/* The speed-only choices of the last minimisation on ctx, as text.  After
+ * a single-system call: the list order of the EAM form and the LDS
  * reservation of its tile blocks, timed on the system's start positions the
  * first time a class of systems is seen
  * (potential, starting precision, size in powers of two, periodic axes) and
  * cached per context and in $FIRE_TUNE_CACHE.single (default
- * ~/.cache/fire2_tune_single.txt).  Results differ between choices only by
- * summation order. */
+ * ~/.cache/fire2_tune_single.txt).  After a batched call: the team size of
+ * the persistent kernel and its chunk length, timed or from
+ * $FIRE_TUNE_CACHE.  Results differ between choices only by summation
+ * order.  The pointer stays valid until the next call on ctx. */
 const char* fire_tuning_info(const fire_ctx* ctx);
 const char* fire_stop_name(int stop_reason);
 

@@ -791,6 +791,7 @@ hipStream_t fire_ctx_stream(fire_ctx* ctx);
 const fire_params* fire_ctx_params(fire_ctx* ctx);
 void** fire_ctx_batched_slot(fire_ctx* ctx);
 int fire_ctx_error(fire_ctx* ctx, int code, const char* msg);
+void fire_ctx_set_tuning_info(fire_ctx* ctx, const char* info);
 int fire_prepare_pot(fire_ctx* ctx, const fire_potential* p, PotDev* out);
 void fire_ctrl_from_params(const fire_params* p, double tol, long long max_steps, double skin, int natoms, Ctrl* c);
 
@@ -1057,8 +1058,13 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     const int prec0 = c0[0].precision;
     bool found = false;
     Config cfg = config_for(w, plan, prec0, &found);
+    char info[192];
+    snprintf(info, sizeof info, "batched: %d-thread teams, chunks of %d iterations (%s)", cfg.team, cfg.chunk,
+             getenv("FIRE_BATCH_TEAM") ? "FIRE_BATCH_TEAM" : "cached");
     if (!found) {
       double best = 1e300;
+      float t[2] = {0, 0};
+      int ti = 0;
       for (int team : {1024, 512}) {
         Config cand{team, 32};
         hipEvent_t e0, e1;
@@ -1073,6 +1079,7 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
         BCHK(hipEventElapsedTime(&ms, e0, e1));
         hipEventDestroy(e0);
         hipEventDestroy(e1);
+        t[ti++] = ms;
         if (ms < best) {
           best = ms;
           cfg.team = team;
@@ -1082,7 +1089,10 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
       }
       w->tuned[tune_key(P, prec0, nsys, maxn)] = Config{cfg.team, kChunk};
       save_cache(w);
+      snprintf(info, sizeof info, "batched: %d-thread teams, chunks of %d iterations (tuned: a 32-iteration chunk took "
+               "%.2f ms with 1024-thread teams, %.2f with 512)", cfg.team, cfg.chunk, t[0], t[1]);
     }
+    fire_ctx_set_tuning_info(ctx, info);
 
     // ---- graph: queue reset, persistent kernel, running count, poll copy
     hipGraph_t graph;

@@ -3606,6 +3606,7 @@ hipStream_t fire_ctx_stream(fire_ctx* ctx) { return ctx->stream; }
 const fire_params* fire_ctx_params(fire_ctx* ctx) { return &ctx->params; }
 void** fire_ctx_batched_slot(fire_ctx* ctx) { return &ctx->batched; }
 int fire_ctx_error(fire_ctx* ctx, int code, const char* msg) { return set_err(ctx, code, msg); }
+void fire_ctx_set_tuning_info(fire_ctx* ctx, const char* info) { ctx->tuning_info = info; }
 int fire_prepare_pot(fire_ctx* ctx, const fire_potential* p, PotDev* out) { return prepare_pot(ctx, p, *out); }
 void fire_ctrl_from_params(const fire_params* p, double tol, long long max_steps, double skin, int natoms, Ctrl* c) {
   ctrl_from_params(*p, tol, max_steps, 0.25 * skin * skin, natoms, *c);

@@ -192,3 +192,14 @@ def test_a_failing_system_does_not_disturb_the_others(api):
             assert res[k]["stop"] == ref_res[j]["stop"] == "converged"
             assert res[k]["iterations"] == ref_res[j]["iterations"] and res[k]["energy"] == ref_res[j]["energy"]
             assert np.array_equal(out[k], ref_pos[j])
+
+
+def test_tuning_info_names_the_batched_team_shape(api):
+    """After a batched call the context reports the persistent kernel's team
+    size and chunk length (speed-only choices) and where they came from."""
+    systems = small_batch(nsys=3, seed=14)
+    c = api.Context(0, systems[0].fire)
+    c.fire_minimize_batched([(s.pos, s.box) for s in systems], systems[0].potential, 1e-6, 20000)
+    info = c.fire_tuning_info()
+    c.close()
+    assert info.startswith("batched: ") and "-thread teams" in info and "chunks of" in info
