@@ -91,6 +91,20 @@ def load_traffic(tag: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
+def load_limiter(tag: str, workload: str):
+    """What the hardware counters say binds the dominant kernel (VALU busy
+    share, share of wave life spent waiting, resident waves per SIMD), from a
+    committed rocprofv3 counter summary, or None when the kernel source
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"counters_{tag}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash():
+        return None
+    return {k: rec[k] for k in ("valu_busy", "wait_share", "lds_wait_share", "waves_per_simd", "reading")}
+
+
 def make_system(name: str):
     from paper_1908_02038_amd import inputs
     return inputs.WORKLOADS[name]()
@@ -542,6 +556,7 @@ def main():
         roof = {"bound": "hbm", "achieved": hbm_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": hbm_ach / PEAK_HBM_GBS}
     roof.update({"traffic": traffic,
+                 "limiter": load_limiter(alg["tag"], args.workload),
                  "kernel": kname if (staged or kind == "sw") else kname + "<double, false, false>",
                  "ms_per_launch": kt,
                  "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops_launch,

@@ -68,3 +68,18 @@ def test_cpu_baseline_record_names_the_host_and_both_thread_counts():
     assert rec["value"] == rec["all_cores"]["value"] > 0 and rec["one_core"]["value"] > 0
     assert rec["cpu_model"] and rec["nproc"] >= 1
     assert "cell grid" in rec["sample"]
+
+
+@pytest.mark.parametrize("matches", [True, False])
+def test_limiter_is_null_once_the_source_changed(tmp_path, monkeypatch, matches):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"source_hash": "abcdefabcdef", "valu_busy": 0.4, "wait_share": 0.5, "lds_wait_share": 0.02,
+           "waves_per_simd": 1.5, "reading": "latency"}
+    (prof / "counters_k_x_w.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: "abcdefabcdef" if matches else "ffffffffffff")
+    got = bench.load_limiter("k_x", "w")
+    assert (got is not None) == matches
+    if matches:
+        assert got["valu_busy"] == 0.4 and got["reading"] == "latency"
