@@ -93,6 +93,9 @@ def test_a_stopped_system_does_not_disturb_the_others(api):
 
 
 def test_mixed_precision_batch(api):
+    """FP32 pair terms, then FP64 below the switch: each system converges,
+    the oracle agrees with its final state, and its E/N lies within 1e-6 of
+    the oracle's own FP64 relaxation from the same start."""
     systems = small_batch(nsys=4, seed=10)
     c = api.Context(0, systems[0].fire, precision="mixed")
     pos, res = c.fire_minimize_batched([(s.pos, s.box) for s in systems], systems[0].potential, 1e-6, 20000)
@@ -103,6 +106,11 @@ def test_mixed_precision_batch(api):
         e_x, f_x = oracle.energy_forces(p, s.box, s.potential)
         assert np.linalg.norm(f_x, axis=1).max() < 1e-6 * (1 + 1e-6)
         assert abs(e_x - r["energy"]) <= 1e-12 * abs(e_x)
+        ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 1e-6, 20000)
+        gap = abs(r["energy"] - ref["energy"]) / abs(ref["energy"])
+        print(f"n {len(s.pos)}: mixed {r['iterations']} it ({r['iterations_low']} FP32), oracle {ref['iterations']} it, "
+              f"|dE/N|/|E/N| {gap:.3e}")
+        assert ref["stop"] == "converged" and gap <= 1e-6
 
 
 def test_full_batched_workload_converges(api):

@@ -196,3 +196,26 @@ def test_batched_sample_matches_oracle(api, golden):
         assert gap <= 1e-10
         assert dx <= 1e-5
     print(f"worst E/N gap over the sample {worst:.3e}")
+
+
+def test_batched_sample_mixed_matches_fp64_oracle(api, golden):
+    """The 512-system batch with FP32 pair terms until each system's
+    criterion falls below its switch (100 tol), then FP64: every system
+    converges, and the 16 systems the oracle relaxed in FP64 agree with it
+    to 1e-6 in E/N (the mixed path's bound)."""
+    g = golden["batched_sample"]
+    systems = inputs.batched()
+    c = api.Context(0, systems[0].fire, precision="mixed")
+    pos, res = c.fire_minimize_batched([(s.pos, s.box) for s in systems], systems[0].potential, 1e-6, 20000)
+    c.close()
+    assert all(r["stop"] == "converged" and r["fmax"] < 1e-6 for r in res)
+    worst = 0.0
+    for rec in g["systems"]:
+        q = rec["system"]
+        r = res[q]
+        assert r["precision_switched"] and 0 < r["iterations_low"] < r["iterations"]
+        en = rec["energy_per_atom"]
+        gap = abs(r["energy_per_atom"] - en) / abs(en)
+        worst = max(worst, gap)
+        assert gap <= 1e-6
+    print(f"mixed batch: worst E/N gap to the FP64 oracle over the sample {worst:.3e}")
