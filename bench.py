@@ -67,6 +67,14 @@ FP32_KERNEL = {
 }
 
 
+def with_tile(kernel: str, tuning: str) -> str:
+    """The EAM-form kernels carry their tile size as a last template argument
+    when the tuner picked 512-atom tiles."""
+    if "512-atom tiles" not in (tuning or "") or "k_gupta" not in kernel:
+        return kernel
+    return kernel.replace(", true>", ", true, 512>").replace(", false>", ", false, 512>")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -259,7 +267,8 @@ def measure_config(name: str, precision: str, steps: int, warmup: int, max_steps
         "iterations": r["iterations"], "iterations_fp32": r["iterations_low"], "rebuilds": r["rebuilds"],
         "stop": r["stop"], "energy_per_atom": r["energy_per_atom"], "fmax": r["fmax"],
         "force_pass_us": kt * 1e3,
-        "force_pass_kernel": alg["kernel"] if precision == "fp64" or kind == "sw" else FP32_KERNEL[kind],
+        "force_pass_kernel": with_tile(alg["kernel"] if precision == "fp64" or kind == "sw" else FP32_KERNEL[kind],
+                                       tuning),
         "force_pass_hbm_frac_alg": hbm / PEAK_HBM_GBS, "force_pass_hbm_GBs_alg": hbm,
         "force_pass_alu_frac_alg": alu / peak_alu, "force_pass_TFLOPs_alg": alu,
         "note": "force pass timed at the relaxed positions with the run's first pair precision"

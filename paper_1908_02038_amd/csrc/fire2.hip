@@ -1586,8 +1586,8 @@ __global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict
 // UPD: the pass first applies the pending update (as in k_lj_force) and
 // writes the new positions, with F'(rho) in .w, of its atoms and their
 // periodic images to ua.dst.pos; requires LDS.
-template <typename T, bool LDS, bool UPD = false>
-__global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ pos, const int* __restrict__ nbr,
+template <typename T, bool LDS, bool UPD = false, int TILE = kBlock>
+__global__ __launch_bounds__(TILE) void k_gupta_density(double4* __restrict__ pos, const int* __restrict__ nbr,
                                                           Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
                                                           int ncap, PotDev pot, const int* __restrict__ gcnt,
                                                           const int* __restrict__ glist,
@@ -1657,14 +1657,14 @@ __global__ __launch_bounds__(kBlock) void k_gupta_density(double4* __restrict__ 
     }
   }
   double r[1] = {emb};
-  block_reduce<1, 0>(r);
+  block_reduce<1, 0, TILE>(r);
   if (threadIdx.x == 0) part_emb[b] = r[0];
 }
 
 // Gupta force pass: F_i = -sum_j [c phi_t'(r) + (F'_i + F'_j) rho_t'(r)] d/r,
 // e_i = w_e sum_j phi_t(r).
-template <typename T, bool LDS, bool WE>
-__global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
+template <typename T, bool LDS, bool WE, int TILE = kBlock>
+__global__ __launch_bounds__(TILE) void k_gupta_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
                                                         Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
                                                         int ncap, PotDev pot, double* __restrict__ frc,
                                                         double* __restrict__ vel, double* __restrict__ part,
@@ -1719,7 +1719,7 @@ __global__ __launch_bounds__(kBlock) void k_gupta_force(const double4* __restric
                             [&](const double4& p0, const double4& p1, const double4& p2, const double4& p3) {
                               group_terms<T>(pi, p0, p1, p2, p3, pot, pair);
                             });
-  force_epilogue(i, valid, (double)ax, (double)ay, (double)az, (double)ae, ep, frc, vel, ncap, part, emb, b,
+  force_epilogue<TILE>(i, valid, (double)ax, (double)ay, (double)az, (double)ae, ep, frc, vel, ncap, part, emb, b,
                  ctrl, trace, pr);
 }
 
@@ -2226,7 +2226,7 @@ struct fire_ctx {
   bool have_list = false;
   // speed-only choices of the single-system path (see tune_single)
   bool list_classes = false;
-  int eam_two_blocks = -1;  // EAM-form LDS reservation: -1 by size, 0: three blocks per CU, 1: two
+  int eam_layout = -1;  // EAM-form tiles: -1 by size; 0: 256 atoms, three blocks per CU; 1: 256, two; 2: 512 atoms
   bool tune_loaded = false;
   std::map<std::string, int> tuned;
   std::string tuning_info = "none";
@@ -2647,35 +2647,43 @@ size_t halo_bytes_per_atom(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_P
 // Tiles of the LDS-staged passes.  The LJ pass takes 512 atoms per tile: its
 // halo grows less than the tile (1.6 against 2 times), so fewer halo atoms
 // are staged per atom, and its one pass per evaluation runs 29.1 instead of
-// 30.3 us per launch on the 130,417-atom box.  The EAM form's two passes
-// measured faster on 256-atom tiles (104 against 110 us).  78 KB of LDS per
-// LJ tile block (halos up to 3,328 atoms; the 130,417-atom box's largest is
-// 2,670) keeps two blocks, with their static LDS, within a CU's 160 KB.
+// 30.3 us per launch on the 130,417-atom box.  78 KB of LDS per 512-atom
+// tile block (LJ halos up to 3,328 atoms, EAM-form ones up to 2,496; the
+// 130,417-atom LJ box's largest is 2,670) keeps two blocks, with their static
+// LDS, within a CU's 160 KB.
+//
+// The EAM form has three layouts.  256-atom tiles reserve 52 KB (three
+// force-pass blocks per CU) or 56 KB (two; the density pass keeps three);
+// 512-atom tiles reserve 78 KB.  While an XCD's share of the per-atom state
+// (about 96 B per atom: positions, velocities, forces, F'(rho), the
+// staged-update reads) fits its 4 MB L2, three 256-atom blocks per CU are
+// fastest (253,440-atom bulk: 85.8 us per FP64 evaluation against 91.7 with
+// 512-atom tiles); beyond, the passes stream their halos from beyond the L2,
+// and 512-atom tiles, which stage fewer halo atoms per atom, are fastest
+// (2,037,760-atom slab: 581 against 638 us per FP32 evaluation with two
+// 256-atom blocks per CU, 673 against 705 in FP64).  That size rule is the
+// default; the single-system tuner times all three.
 constexpr size_t kLdsLj = 78 * 1024;
-int tile_atoms(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_POT_LJ ? kMaxTile : kBlock; }
-
-// EAM-form tile blocks reserve 52 KB (three force-pass blocks per CU) while
-// an XCD's share of the per-atom state (about 96 B per atom: positions,
-// velocities, forces, F'(rho), the staged-update reads) fits its 4 MB L2,
-// and 56 KB (two force-pass blocks per CU, the density pass keeps three)
-// beyond.  Past that size the passes stream their halos from beyond the L2
-// and a third block per CU only adds misses: on the 2,037,760-atom slab the
-// FP64 passes take 752 instead of 950 us per evaluation, while the
-// 253,440-atom bulk, whose share stays in the L2, is faster with three
-// (103 against 108 us).
 constexpr size_t kLdsEamLarge = 56 * 1024;
 constexpr long long kL2Atoms = 8LL * (4 << 20) / 96;
+
+int eam_layout(const fire_ctx* ctx) {
+  return ctx->eam_layout >= 0 ? ctx->eam_layout : (ctx->n > kL2Atoms ? 2 : 0);
+}
+
+int tile_atoms(const fire_ctx* ctx) {
+  if (ctx->pot.kind == FIRE_POT_LJ) return kMaxTile;
+  if (ctx->pot.kind == FIRE_POT_GUPTA && eam_layout(ctx) == 2) return kMaxTile;
+  return kBlock;
+}
 
 size_t lds_budget(const fire_ctx* ctx, int tile) {
   if (!ctx->lds_default) return ctx->lds_limit;
   size_t d = ctx->lds_limit;
-  const bool large = ctx->eam_two_blocks < 0 ? ctx->n > kL2Atoms : ctx->eam_two_blocks > 0;
   if (tile == kMaxTile) d = std::min(kLdsLj, ctx->lds_cap);
-  else if (ctx->pot.kind == FIRE_POT_GUPTA && large) d = std::min(kLdsEamLarge, ctx->lds_cap);
+  else if (ctx->pot.kind == FIRE_POT_GUPTA && eam_layout(ctx) == 1) d = std::min(kLdsEamLarge, ctx->lds_cap);
   return std::max(d, std::min(ctx->lds_boost, ctx->lds_cap));
 }
-
-
 
 // Neighbour lists (and, with the LDS budget, tile halos) of the current
 // slots; one flag read for both kernels.  Grows the list capacity until every
@@ -2911,10 +2919,10 @@ UpdArgs upd_args(fire_ctx* ctx, int parity) {
 // `parity` and writing the other (LDS-staged passes only).
 template <typename T, bool LDS, bool WE>
 void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
-  // the LJ pass runs on its tiles' blocks also with global gathers, so both
-  // forms reduce over the same atom groups and give the same bits
+  // the pair passes run on their tiles' blocks also with global gathers, so
+  // both forms reduce over the same atom groups and give the same bits
   const int tile = tile_atoms(ctx);
-  const int n = ctx->n, nb = nblocks(n), nt = nblocks(n, tile), kc = ctx->kcap, nc = ctx->ncap;
+  const int n = ctx->n, nt = nblocks(n, tile), kc = ctx->kcap, nc = ctx->ncap;
   const PotDev& P = ctx->pot;
   const Tiles tl{ctx->tile_h, ctx->hslot, ctx->hsrc, ctx->nbr16, ctx->hcap};
   const size_t sm = LDS ? ctx->lds_atoms * 24 : 0;     // x, y, z
@@ -2927,10 +2935,16 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
       if (P.kind == FIRE_POT_LJ) {
         hipLaunchKernelGGL((k_lj_force<T, true, WE, true>), dim3(nt), dim3(tile), sm, s, ua.src.pos, ctx->nbr, tl,
                            ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
+      } else if (tile == kMaxTile) {
+        hipLaunchKernelGGL((k_gupta_density<T, true, true, kMaxTile>), dim3(nt), dim3(tile), sm, s, ua.src.pos,
+                           ctx->nbr, tl, ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
+        hipLaunchKernelGGL((k_gupta_force<T, true, WE, kMaxTile>), dim3(nt), dim3(tile), smw, s, d.pos, ctx->nbr, tl,
+                           ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace,
+                           pr);
       } else {
-        hipLaunchKernelGGL((k_gupta_density<T, true, true>), dim3(nb), dim3(kBlock), sm, s, ua.src.pos, ctx->nbr,
+        hipLaunchKernelGGL((k_gupta_density<T, true, true>), dim3(nt), dim3(tile), sm, s, ua.src.pos, ctx->nbr,
                            tl, ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
-        hipLaunchKernelGGL((k_gupta_force<T, true, WE>), dim3(nb), dim3(kBlock), smw, s, d.pos, ctx->nbr, tl,
+        hipLaunchKernelGGL((k_gupta_force<T, true, WE>), dim3(nt), dim3(tile), smw, s, d.pos, ctx->nbr, tl,
                            ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->part_emb, ctx->ctrl, ctx->trace,
                            pr);
       }
@@ -2940,10 +2954,16 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
   if (P.kind == FIRE_POT_LJ) {
     hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nt), dim3(tile), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt, n,
                        kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
+  } else if (tile == kMaxTile) {
+    hipLaunchKernelGGL((k_gupta_density<T, LDS, false, kMaxTile>), dim3(nt), dim3(tile), sm, s, ctx->pos, ctx->nbr,
+                       tl, ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
+    hipLaunchKernelGGL((k_gupta_force<T, LDS, WE, kMaxTile>), dim3(nt), dim3(tile), smw, s, ctx->pos, ctx->nbr, tl,
+                       ctx->wcnt, n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl,
+                       ctx->trace, pr);
   } else {
-    hipLaunchKernelGGL((k_gupta_density<T, LDS>), dim3(nb), dim3(kBlock), sm, s, ctx->pos, ctx->nbr, tl,
+    hipLaunchKernelGGL((k_gupta_density<T, LDS>), dim3(nt), dim3(tile), sm, s, ctx->pos, ctx->nbr, tl,
                        ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
-    hipLaunchKernelGGL((k_gupta_force<T, LDS, WE>), dim3(nb), dim3(kBlock), smw, s, ctx->pos, ctx->nbr, tl,
+    hipLaunchKernelGGL((k_gupta_force<T, LDS, WE>), dim3(nt), dim3(tile), smw, s, ctx->pos, ctx->nbr, tl,
                        ctx->wcnt, n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->part_emb, ctx->ctrl,
                        ctx->trace, pr);
   }
@@ -3289,27 +3309,36 @@ std::string tune_cache_path() {
 // the context and in a cache file that later processes read
 // ($FIRE_TUNE_CACHE.single, default ~/.cache/fire2_tune_single.txt).  The
 // choices are those of the EAM form: the list order (one class in slot
-// order, or three distance classes; FIRE_LIST_CLASSES=0|1 fixes it) and the
-// LDS reservation of its tile blocks (three or two blocks per CU; the size
-// rule decides when FIRE_LIST_CLASSES is set).  Small systems keep one class
-// and the size rule without timing.  The start lists are rebuilt with the
-// choice before the run begins.
+// order, or three distance classes) and the tile layout (256-atom tiles at
+// three or two blocks per CU, or 512-atom tiles).  FIRE_LIST_CLASSES=0|1 and
+// FIRE_EAM_LAYOUT=0|1|2 fix either; the size rule then gives the layout
+// unless it is fixed too.  Small systems keep one class and the size rule
+// without timing.  The start lists are rebuilt with the choice before the
+// run begins.
 int tune_single(fire_ctx* ctx, hipStream_t s) {
   if (ctx->pot.kind != FIRE_POT_GUPTA) return FIRE_OK;
-  bool want = ctx->list_classes;
-  if (const char* e = getenv("FIRE_LIST_CLASSES")) {
-    want = e[0] == '1';
-    ctx->tuning_info = std::string("list order ") + (want ? "classes" : "slot") + " (FIRE_LIST_CLASSES)";
-  } else if (ctx->n < 16384) {
-    want = false;
-    ctx->tuning_info = "list order slot (small system, not tuned)";
+  const char* ec = getenv("FIRE_LIST_CLASSES");
+  const char* el = getenv("FIRE_EAM_LAYOUT");
+  const int fixed_layout = el ? std::min(2, std::max(0, atoi(el))) : -1;
+  auto describe = [](bool cls, int layout) {
+    static const char* kLayout[3] = {"256-atom tiles, three blocks per CU", "256-atom tiles, two blocks per CU",
+                                     "512-atom tiles"};
+    return std::string("list order ") + (cls ? "classes" : "slot") + ", " +
+           (layout < 0 ? std::string("tiles by the size rule") : std::string(kLayout[layout]));
+  };
+  bool cls = ctx->list_classes;
+  int layout = ctx->eam_layout;
+  if (ec || ctx->n < 16384) {
+    cls = ec ? ec[0] == '1' : false;
+    layout = fixed_layout;
+    ctx->tuning_info = describe(cls, layout) + (ec ? " (FIRE_LIST_CLASSES)" : " (small system, not tuned)");
   } else {
     const int prec = ctx->params.precision == FIRE_FP64 ? 0 : 1;
     int lg = 0;
     while ((1 << (lg + 1)) <= ctx->n) ++lg;
     char key[96];
-    snprintf(key, sizeof key, "gupta_prec%d_n2e%d_per%d%d%d", prec, lg, ctx->box.per[0], ctx->box.per[1],
-             ctx->box.per[2]);
+    snprintf(key, sizeof key, "eam_prec%d_n2e%d_per%d%d%d_layout%d", prec, lg, ctx->box.per[0], ctx->box.per[1],
+             ctx->box.per[2], fixed_layout);
     if (!ctx->tune_loaded) {
       ctx->tune_loaded = true;
       FILE* f = fopen(tune_cache_path().c_str(), "r");
@@ -3320,50 +3349,57 @@ int tune_single(fire_ctx* ctx, hipStream_t s) {
         fclose(f);
       }
     }
-    auto describe = [](int c) {
-      return std::string("list order ") + ((c & 1) ? "classes" : "slot") + ", " + ((c & 2) ? "two" : "three") +
-             " EAM blocks per CU";
-    };
     auto it = ctx->tuned.find(key);
-    int choice;
-    if (it != ctx->tuned.end()) {
-      choice = it->second & 3;
-      ctx->tuning_info = describe(choice) + " (cached for " + key + ")";
+    const bool cached = it != ctx->tuned.end();
+    int choice;  // bit 0: distance classes; bits 1-2: the layout
+    if (cached) {
+      choice = it->second;
+      ctx->tuning_info = describe(choice & 1, choice >> 1) + " (cached for " + key + ")";
     } else {
-      float t[4] = {0, 0, 0, 0};
-      for (int c = 0; c < 4; ++c) {
-        ctx->list_classes = (c & 1) != 0;
-        ctx->eam_two_blocks = (c >> 1) & 1;
-        int rc = rebuild(ctx);
-        if (rc) return rc;
-        rc = time_evaluation(ctx, s, prec, 6, &t[c]);
-        if (rc) return rc;
+      std::string times;
+      float best = 0.0f;
+      choice = -1;
+      for (int lay = 0; lay < 3; ++lay) {
+        if (fixed_layout >= 0 && lay != fixed_layout) continue;
+        for (int c = 0; c < 2; ++c) {
+          ctx->list_classes = c != 0;
+          ctx->eam_layout = lay;
+          int rc = rebuild(ctx);
+          if (rc) return rc;
+          float t = 0.0f;
+          rc = time_evaluation(ctx, s, prec, 6, &t);
+          if (rc) return rc;
+          static const char* kShort[3] = {"256x3", "256x2", "512"};
+          char one[64];
+          snprintf(one, sizeof one, "%s%s/%s %.1f", times.empty() ? "" : ", ", c ? "classes" : "slot", kShort[lay],
+                   1e3 * t);
+          times += one;
+          if (choice < 0 || t < best) {
+            best = t;
+            choice = c | (lay << 1);
+          }
+        }
       }
-      choice = 0;
-      for (int c = 1; c < 4; ++c)
-        if (t[c] < t[choice]) choice = c;
       ctx->tuned[key] = choice;
-      char info[256];
-      snprintf(info, sizeof info, " (tuned for %s: slot/three %.1f, classes/three %.1f, slot/two %.1f, "
-               "classes/two %.1f us)", key, 1e3 * t[0], 1e3 * t[1], 1e3 * t[2], 1e3 * t[3]);
-      ctx->tuning_info = describe(choice) + info;
+      ctx->tuning_info = describe(choice & 1, choice >> 1) + " (tuned for " + key + ": " + times +
+                         " us per evaluation; tile atoms x blocks per CU)";
       FILE* f = fopen(tune_cache_path().c_str(), "w");
       if (f) {
         for (auto& kv : ctx->tuned) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
         fclose(f);
       }
     }
-    const bool cls = (choice & 1) != 0;
-    const int two = (choice >> 1) & 1;
-    if (cls != ctx->list_classes || two != ctx->eam_two_blocks || it == ctx->tuned.end()) {
+    cls = (choice & 1) != 0;
+    layout = choice >> 1;
+    if (!cached) {  // the timing runs left the last candidate's lists
       ctx->list_classes = cls;
-      ctx->eam_two_blocks = two;
+      ctx->eam_layout = layout;
       return rebuild(ctx);
     }
-    return FIRE_OK;
   }
-  if (want != ctx->list_classes) {
-    ctx->list_classes = want;
+  if (cls != ctx->list_classes || layout != ctx->eam_layout) {
+    ctx->list_classes = cls;
+    ctx->eam_layout = layout;
     return rebuild(ctx);
   }
   return FIRE_OK;
