@@ -68,11 +68,12 @@ FP32_KERNEL = {
 
 
 def with_tile(kernel: str, tuning: str) -> str:
-    """The EAM-form kernels carry their tile size as a last template argument
-    when the tuner picked 512-atom tiles."""
-    if "512-atom tiles" not in (tuning or "") or "k_gupta" not in kernel:
+    """The EAM-form kernels carry their tile size (256 or 512 atoms, the
+    tuner's choice) as a last template argument."""
+    if "k_gupta" not in kernel:
         return kernel
-    return kernel.replace(", true>", ", true, 512>").replace(", false>", ", false, 512>")
+    tile = 512 if "512-atom tiles" in (tuning or "") else 256
+    return kernel.replace(", true>", f", true, {tile}>").replace(", false>", f", false, {tile}>")
 
 
 def log(*a):

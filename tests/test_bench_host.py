@@ -89,6 +89,7 @@ def test_eam_kernel_label_follows_the_tuned_tile():
     k = "k_gupta_density<float, true, true> + k_gupta_force<float, true, false>"
     assert bench.with_tile(k, "list order slot, 512-atom tiles (cached for x)") == \
         "k_gupta_density<float, true, true, 512> + k_gupta_force<float, true, false, 512>"
-    assert bench.with_tile(k, "list order classes, 256-atom tiles, three blocks per CU") == k
+    assert bench.with_tile(k, "list order classes, 256-atom tiles, three blocks per CU") == \
+        "k_gupta_density<float, true, true, 256> + k_gupta_force<float, true, false, 256>"
     assert bench.with_tile("k_lj_force<double, true, false, true>", "512-atom tiles") == \
         "k_lj_force<double, true, false, true>"
