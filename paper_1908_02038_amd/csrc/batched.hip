@@ -44,6 +44,11 @@ constexpr int kMaxAtoms = 4096;  // per system (LDS holds its positions)
 // bound is the longest single relaxation on one CU, about 240 ms there).
 constexpr int kChunk = 1024;
 constexpr int kMaxCells = 1024;  // per-system cell grid in LDS
+constexpr int kRedWidth = 10;    // values per wave in a team reduction
+constexpr int kMaxPairs = 512;   // pairs of teams per launch
+// Longest wait of a block at a pair barrier, in ticks of the 100 MHz
+// constant clock (2 s; a partner is never more than one pass behind).
+constexpr long long kPairWaitTicks = 200000000LL;
 
 struct SysDesc {
   int off, n;    // first atom in the concatenated arrays, atom count
@@ -79,23 +84,26 @@ __device__ __forceinline__ size_t nidx(size_t base, int n, int a, int q) {
   return base + ((size_t)(q >> 2) * n + a) * 4 + (q & 3);
 }
 
-template <int TEAM>
-__device__ __forceinline__ void team_reduce(double (&v)[6], double (*red)[6]) {
+// Team reduction of NS sums followed by NM maxima; the results are valid in
+// thread 0.  Each value is reduced on its own (lanes of a wave, then the
+// waves in order), so its bits do not depend on the other values of the call.
+template <int TEAM, int NS, int NM>
+__device__ __forceinline__ void team_reduce(double (&v)[NS + NM], double (*red)[kRedWidth]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+  for (int k = 0; k < NS; ++k) v[k] = wave_sum(v[k]);
 #pragma unroll
-  for (int k = 4; k < 6; ++k) v[k] = wave_max(v[k]);
+  for (int k = NS; k < NS + NM; ++k) v[k] = wave_max(v[k]);
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) red[w][k] = v[k];
+    for (int k = 0; k < NS + NM; ++k) red[w][k] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int q = 1; q < TEAM / 64; ++q) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] += red[q][k];
+      for (int k = 0; k < NS; ++k) v[k] += red[q][k];
 #pragma unroll
-      for (int k = 4; k < 6; ++k) v[k] = fmax(v[k], red[q][k]);
+      for (int k = NS; k < NS + NM; ++k) v[k] = fmax(v[k], red[q][k]);
     }
   }
   __syncthreads();
@@ -107,15 +115,84 @@ struct TeamShared {
   unsigned short cat[kMaxAtoms];  // atoms sorted by cell
   int cstart[kMaxCells + 1];
   int cnt[kMaxCells];
-  double red[16][6];
+  double red[16][kRedWidth];
   double lo[3], inv[3];
   int nc[3], lo_off[3], hi_off[3];
   int sys, status, viol, overflow;
+  int phase, fetch;  // pair barriers passed, systems fetched by a pair (this launch)
   // coefficients of the next update
   int neg, mix_first, prec;
   double hsb, k1, k2, k3, cv, cf, dtx;
   double etab[32];  // table of the FP64 exponential
+  Ctrl mine;        // the system's control record while the team works on it
 };
+
+// Two blocks (on two CUs) can share one large system as a pair: each takes
+// one of the system's two halves of atoms (Team below).  Each block updates,
+// lists and evaluates its own atoms and keeps all positions in its LDS; the
+// blocks meet at barriers where they exchange positions, F'(rho), the skin
+// and list-overflow flags and their reduction records through
+// device-coherent loads and stores.  Both then run the same FIRE control on
+// the same combined record, and the first block writes the system's control
+// record back.  A team alone works through both halves with the same thread
+// mapping, keeps them in separate records and combines them the same way, so
+// a system gets the same bits whether a pair or a team alone relaxes it.
+struct PairSlot {
+  int bar;       // arrivals at the pair's barriers in this launch
+  int sys[2];    // the system the first block fetched (by parity of the fetch; -1: none left)
+  int vflag[2];  // per block: one of its atoms left its skin
+  int oflag[2];  // per block: its list build overflowed or found coinciding atoms
+  int pad;
+  double rec[2][8];  // per block: its reduction record
+  double pad2[12];
+};
+static_assert(sizeof(PairSlot) == 256, "one pair slot per 256 bytes");
+static_assert(sizeof(Ctrl) % 8 == 0, "control records are copied in 8-byte words");
+
+__device__ __forceinline__ void st_co(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_co(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_co_i(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_co_i(const int* p) {
+  return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier of the two blocks of a pair.  Every thread's device-coherent stores
+// have completed before its block arrives (no cache-wide fence: the data the
+// blocks exchange is stored and loaded device-coherently).  The wait is
+// bounded: a partner that does not arrive within kPairWaitTicks sets *err and
+// the function returns false, after which the caller leaves the kernel.
+__device__ bool pair_barrier(PairSlot* ps, TeamShared& sh, int* err) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0 && sh.phase >= 0) {
+    const int target = 2 * (++sh.phase);
+    __hip_atomic_fetch_add(&ps->bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    while (ld_co_i(&ps->bar) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (wall_clock64() - t0 > kPairWaitTicks) {
+        atomicOr(err, 1);
+        sh.phase = -1;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  return sh.phase >= 0;
+}
+
+// A control record copied between global memory and LDS by the whole block.
+__device__ __forceinline__ void copy_ctrl(Ctrl* __restrict__ dst, const Ctrl* __restrict__ src) {
+  const long long* s = reinterpret_cast<const long long*>(src);
+  long long* d = reinterpret_cast<long long*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 8); i += blockDim.x) d[i] = s[i];
+}
 
 template <int TEAM, int MAXPT>
 struct Team {
@@ -127,18 +204,42 @@ struct Team {
   double4* __restrict__ vel;
   double4* __restrict__ frc;
   double4* __restrict__ xref;
+  PairSlot* ps;  // the pair's slot (null: a team alone)
+  int half;      // 0 or 1 within a pair
+  // The atoms form two halves, [0, m) and [m, n): m = (n + 1) / 2 above 1.5
+  // team widths, else min(n, TEAM) (so a team alone needs no extra round of
+  // its threads for a system of up to 1.5 widths).  A pair's block h works on
+  // half h; a team alone on both, one after the other, each half in its own
+  // reduction record.
+  int m;       // start of the second half
+  int h0, h1;  // the halves this block works on: [h0, h1)
 
-  __device__ Team(TeamShared& s, const SysDesc& desc, double4* v, double4* f, double4* xr)
-      : sh(s), d(desc), n(desc.n), vel(v + desc.off), frc(f + desc.off), xref(xr + desc.off) {}
+  __device__ Team(TeamShared& s, const SysDesc& desc, double4* v, double4* f, double4* xr, PairSlot* slot, int h)
+      : sh(s), d(desc), n(desc.n), vel(v + desc.off), frc(f + desc.off), xref(xr + desc.off), ps(slot),
+        half(slot ? h : 0) {
+    m = 2 * n > 3 * TEAM ? (n + 1) / 2 : min(n, TEAM);
+    h0 = slot ? h : 0;
+    h1 = slot ? h + 1 : 2;
+  }
 
-  __device__ int atom(int k) const { return threadIdx.x + k * TEAM; }
+  __device__ bool paired() const { return ps != nullptr; }
+  // the k-th atom of this thread in half h (increasing in k; >= end(h): none)
+  __device__ int atom(int h, int k) const { return (h ? m : 0) + (int)threadIdx.x + k * TEAM; }
+  __device__ int end(int h) const { return h ? n : m; }
+  // the k-th of all atoms (cell lists are built over the whole system)
+  __device__ int any_atom(int k) const { return (int)threadIdx.x + k * TEAM; }
+  __device__ bool owns(int a) const { return !ps || (half ? a >= m : a < m); }
 
   // Cell list and neighbour list of the current positions (wrapped into the
   // box on periodic axes).  Lists: nbr[off*kb + k*n + a], counts nn[off + a].
   // Each list holds the atoms within the cutoff (rc2) at build time first,
   // then the rest of the skin, each part in the order of the cell sweep, so
-  // that the FP64 passes can skip groups of four beyond the cutoff.
-  __device__ void build(unsigned short* __restrict__ nbr, unsigned short* __restrict__ nn, int kb, double rc2) {
+  // that the FP64 passes can skip groups of four beyond the cutoff.  Each
+  // block of a pair wraps and sorts all atoms (the same arithmetic, so both
+  // LDS copies agree) and lists its own; the blocks then share their overflow
+  // flags.  Returns false when a pair barrier timed out.
+  __device__ bool build(unsigned short* __restrict__ nbr, unsigned short* __restrict__ nn, int kb, double rc2,
+                        int* err) {
     double lo3[3], hi3[3];
     for (int q = 0; q < 3; ++q) {
       lo3[q] = INFINITY;
@@ -146,8 +247,8 @@ struct Team {
     }
 #pragma unroll 1
     for (int k = 0; k < MAXPT; ++k) {
-      const int a = atom(k);
-      if (a >= n) continue;
+      const int a = any_atom(k);
+      if (a >= n) break;
       double4 p = sh.x[a];
       double r[3] = {p.x, p.y, p.z};
       for (int q = 0; q < 3; ++q) {
@@ -162,7 +263,7 @@ struct Team {
         hi3[q] = fmax(hi3[q], r[q]);
       }
       sh.x[a] = make_double4(r[0], r[1], r[2], p.w);
-      xref[a] = make_double4(r[0], r[1], r[2], 0.0);
+      if (owns(a)) xref[a] = make_double4(r[0], r[1], r[2], 0.0);
     }
     // bounding box of the free axes
     double bb[6] = {-lo3[0], -lo3[1], -lo3[2], hi3[0], hi3[1], hi3[2]};
@@ -231,8 +332,8 @@ struct Team {
     __syncthreads();
 #pragma unroll 1
     for (int k = 0; k < MAXPT; ++k) {
-      const int a = atom(k);
-      if (a >= n) continue;
+      const int a = any_atom(k);
+      if (a >= n) break;
       atomicAdd(&sh.cnt[cell_of(sh.x[a])], 1);
     }
     __syncthreads();
@@ -248,8 +349,8 @@ struct Team {
     __syncthreads();
 #pragma unroll 1
     for (int k = 0; k < MAXPT; ++k) {
-      const int a = atom(k);
-      if (a >= n) continue;
+      const int a = any_atom(k);
+      if (a >= n) break;
       const int c = cell_of(sh.x[a]);
       sh.cat[sh.cstart[c] + atomicAdd(&sh.cnt[c], 1)] = (unsigned short)a;
     }
@@ -270,9 +371,11 @@ struct Team {
     const size_t base = (size_t)d.off * kb;
     const Img img(d);
 #pragma unroll 1
+    for (int h = h0; h < h1; ++h)
+#pragma unroll 1
     for (int k = 0; k < MAXPT; ++k) {
-      const int a = atom(k);
-      if (a >= n) continue;
+      const int a = atom(h, k);
+      if (a >= end(h)) break;
       const double4 pa = sh.x[a];
       const int c0 = cell_of(pa);
       const int cc[3] = {c0 % sh.nc[0], (c0 / sh.nc[0]) % sh.nc[1], c0 / (sh.nc[0] * sh.nc[1])};
@@ -318,6 +421,13 @@ struct Team {
       nn[d.off + a] = (unsigned short)min(m, kb);
     }
     __syncthreads();
+    if (ps) {
+      if (threadIdx.x == 0) st_co_i(&ps->oflag[half], sh.overflow);
+      if (!pair_barrier(ps, sh, err)) return false;
+      if (threadIdx.x == 0) sh.overflow |= ld_co_i(&ps->oflag[half ^ 1]);
+      __syncthreads();
+    }
+    return true;
   }
 };
 
@@ -401,17 +511,21 @@ __device__ __forceinline__ void team_group(const Img& img, const double4& pa, co
 }
 
 template <int TEAM, int MAXPT, typename T>
-__device__ void density_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigned short* __restrict__ nbr,
-                             const unsigned short* __restrict__ nn, int kb, double& emb) {
+__device__ bool density_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigned short* __restrict__ nbr,
+                             const unsigned short* __restrict__ nn, int kb, double* __restrict__ xfp, int* err,
+                             double& embA, double& embB) {
   const SysDesc& d = tm.d;
   const size_t base = (size_t)d.off * kb;
   const Img img(d);
   // F'(rho) of the team's atoms is parked in frc[a].w (the force pass
-  // rewrites frc) until every neighbour read of the old values is done
+  // rewrites frc) until every neighbour read of the old values is done; a
+  // pair also stores it device-coherently in xfp for the partner
+#pragma unroll 1
+  for (int h = tm.h0; h < tm.h1; ++h)
 #pragma unroll 1
   for (int k = 0; k < MAXPT; ++k) {
-    const int a = tm.atom(k);
-    if (a >= tm.n) continue;
+    const int a = tm.atom(h, k);
+    if (a >= tm.end(h)) break;
     const double4 pa = tm.sh.x[a];
     T rho = 0;
     const int m = nn[d.off + a];  // list length (entries past it are padding)
@@ -430,30 +544,49 @@ __device__ void density_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsig
     if (rho > 0) {
       const double sq = sqrt((double)rho);
       fp = -0.5 * P.xi / sq;
-      emb += -P.xi * sq;
+      if (h) embB += -P.xi * sq;
+      else embA += -P.xi * sq;
     }
     reinterpret_cast<double*>(&tm.frc[a])[3] = fp;
+    if (tm.paired()) st_co(xfp + d.off + a, fp);
   }
   __syncthreads();  // every neighbour read of w done before it changes
 #pragma unroll 1
+  for (int h = tm.h0; h < tm.h1; ++h)
+#pragma unroll 1
   for (int k = 0; k < MAXPT; ++k) {
-    const int a = tm.atom(k);
-    if (a < tm.n) tm.sh.x[a].w = reinterpret_cast<const double*>(&tm.frc[a])[3];
+    const int a = tm.atom(h, k);
+    if (a >= tm.end(h)) break;
+    tm.sh.x[a].w = reinterpret_cast<const double*>(&tm.frc[a])[3];
+  }
+  if (tm.paired()) {
+    if (!pair_barrier(tm.ps, tm.sh, err)) return false;
+    const int h = tm.half ^ 1;
+#pragma unroll 1
+    for (int k = 0; k < MAXPT; ++k) {
+      const int a = tm.atom(h, k);
+      if (a >= tm.end(h)) break;
+      tm.sh.x[a].w = ld_co(xfp + d.off + a);
+    }
   }
   __syncthreads();
+  return true;
 }
 
 template <int TEAM, int MAXPT, int POT, typename T>
 __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigned short* __restrict__ nbr,
-                           const unsigned short* __restrict__ nn, int kb, double (&r)[6]) {
+                           const unsigned short* __restrict__ nn, int kb, double (&rA)[4], double (&rB)[4],
+                           double (&mx)[2]) {
   const SysDesc& d = tm.d;
   const size_t base = (size_t)d.off * kb;
   const Img img(d);
   const double k3 = tm.sh.k3;
 #pragma unroll 1
+  for (int h = tm.h0; h < tm.h1; ++h)
+#pragma unroll 1
   for (int k = 0; k < MAXPT; ++k) {
-    const int a = tm.atom(k);
-    if (a >= tm.n) continue;
+    const int a = tm.atom(h, k);
+    if (a >= tm.end(h)) break;
     const double4 pa = tm.sh.x[a];
     T ax = 0, ay = 0, az = 0, ae = 0;
     const int m = nn[d.off + a];  // list length (entries past it are padding)
@@ -513,32 +646,70 @@ __device__ void force_pass(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigne
       tm.vel[a] = v;
     }
     const double f2 = fx * fx + fy * fy + fz * fz, v2 = v.x * v.x + v.y * v.y + v.z * v.z;
-    r[0] += (double)ae;
-    r[1] += fx * v.x + fy * v.y + fz * v.z;
-    r[2] += f2;
-    r[3] += v2;
-    r[4] = fmax(r[4], f2);
-    r[5] = fmax(r[5], v2);
+    auto acc = [&](double (&r)[4]) {
+      r[0] += (double)ae;
+      r[1] += fx * v.x + fy * v.y + fz * v.z;
+      r[2] += f2;
+      r[3] += v2;
+    };
+    if (h) acc(rB);
+    else acc(rA);
+    mx[0] = fmax(mx[0], f2);
+    mx[1] = fmax(mx[1], v2);
   }
 }
 
+// One force evaluation of the team's system and the FIRE control that
+// follows it, on the control record in LDS.  Returns false when a pair
+// barrier timed out.
 template <int TEAM, int MAXPT, int POT>
-__device__ void evaluate(Team<TEAM, MAXPT>& tm, Ctrl* __restrict__ c, const PotDev& P,
-                         const unsigned short* __restrict__ nbr, const unsigned short* __restrict__ nn, int kb) {
-  double r[6] = {0, 0, 0, 0, 0, 0};
-  double emb = 0.0;
+__device__ bool evaluate(Team<TEAM, MAXPT>& tm, const PotDev& P, const unsigned short* __restrict__ nbr,
+                         const unsigned short* __restrict__ nn, int kb, double* __restrict__ xfp, int* err) {
+  double rA[4] = {0, 0, 0, 0}, rB[4] = {0, 0, 0, 0}, mx[2] = {0, 0};
+  double embA = 0.0, embB = 0.0;
   const int prec = tm.sh.prec;
   if constexpr (POT == FIRE_POT_GUPTA) {
-    if (prec) density_pass<TEAM, MAXPT, float>(tm, P, nbr, nn, kb, emb);
-    else density_pass<TEAM, MAXPT, double>(tm, P, nbr, nn, kb, emb);
+    const bool ok = prec ? density_pass<TEAM, MAXPT, float>(tm, P, nbr, nn, kb, xfp, err, embA, embB)
+                         : density_pass<TEAM, MAXPT, double>(tm, P, nbr, nn, kb, xfp, err, embA, embB);
+    if (!ok) return false;
   }
-  if (prec) force_pass<TEAM, MAXPT, POT, float>(tm, P, nbr, nn, kb, r);
-  else force_pass<TEAM, MAXPT, POT, double>(tm, P, nbr, nn, kb, r);
-  r[0] += emb;
-  team_reduce<TEAM>(r, tm.sh.red);
+  if (prec) force_pass<TEAM, MAXPT, POT, float>(tm, P, nbr, nn, kb, rA, rB, mx);
+  else force_pass<TEAM, MAXPT, POT, double>(tm, P, nbr, nn, kb, rA, rB, mx);
+  rA[0] += embA;
+  rB[0] += embB;
+  // the record: E, P, |F|^2, |v|^2 summed over each half of the atoms
+  // separately, then added; max |F|^2 and max |v|^2
+  double t[6];
+  if (tm.paired()) {
+    // a pair's block accumulated its half in the record of that half
+    double v[6];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = tm.half ? rB[k] : rA[k];
+    v[4] = mx[0];
+    v[5] = mx[1];
+    team_reduce<TEAM, 4, 2>(v, tm.sh.red);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) st_co(&tm.ps->rec[tm.half][k], v[k]);
+    if (!pair_barrier(tm.ps, tm.sh, err)) return false;
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const double a = ld_co(&tm.ps->rec[0][k]), b = ld_co(&tm.ps->rec[1][k]);
+        t[k] = k < 4 ? a + b : fmax(a, b);
+      }
+  } else {
+    double v[10] = {rA[0], rA[1], rA[2], rA[3], rB[0], rB[1], rB[2], rB[3], mx[0], mx[1]};
+    team_reduce<TEAM, 8, 2>(v, tm.sh.red);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = v[k] + v[4 + k];
+    t[4] = v[8];
+    t[5] = v[9];
+  }
   if (threadIdx.x == 0) {
+    Ctrl* c = &tm.sh.mine;
     // unit masses: the mass-weighted sums are P and |F|^2
-    const double q[kCtl] = {r[0], r[1], r[2], r[3], r[4], r[5], r[1], r[2]};
+    const double q[kCtl] = {t[0], t[1], t[2], t[3], t[4], t[5], t[1], t[2]};
     fire_control(*c, c, q, nullptr);
     if (c->status == ST_PAUSED && c->pause == PAUSE_PRECISION) {
       c->status = ST_RUNNING;  // the team switches its own pair precision
@@ -557,52 +728,79 @@ __device__ void evaluate(Team<TEAM, MAXPT>& tm, Ctrl* __restrict__ c, const PotD
     tm.sh.dtx = c->dtx;
   }
   __syncthreads();
+  return true;
 }
 
-// Persistent team kernel: pull systems from the queue, advance each by up to
-// `chunk` iterations.  Arrays are indexed by the concatenated atom index.
+// Persistent team kernel: pull systems from the queues, advance each by up
+// to `chunk` iterations.  Arrays are indexed by the concatenated atom index.
+// order[0, nheavy) are the large systems, taken by the first 2 npairs blocks
+// as pairs; once those are all taken the pairs split and, with the other
+// blocks, take order[nheavy, nsys) one block each.  queue: [0] head of the
+// second queue, [2] list-capacity flag, [4] head of the first, [5] set when a
+// pair barrier timed out.
 template <int TEAM, int MAXPT, int POT>
 __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ desc, Ctrl* __restrict__ ctrl,
-                                                  const int* __restrict__ order, int nsys, int* __restrict__ queue,
-                                                  double4* __restrict__ pos, double4* __restrict__ vel,
-                                                  double4* __restrict__ frc, double4* __restrict__ xref,
-                                                  unsigned short* __restrict__ nbr, unsigned short* __restrict__ nn,
-                                                  int kb, PotDev P, int chunk, int* __restrict__ flags) {
+                                                  const int* __restrict__ order, int nsys, int nheavy, int npairs,
+                                                  PairSlot* __restrict__ pslots, double* __restrict__ xfp,
+                                                  int* __restrict__ queue, double4* __restrict__ pos,
+                                                  double4* __restrict__ vel, double4* __restrict__ frc,
+                                                  double4* __restrict__ xref, unsigned short* __restrict__ nbr,
+                                                  unsigned short* __restrict__ nn, int kb, PotDev P, int chunk) {
   __shared__ TeamShared sh;
   exp_table_fill(sh.etab);  // published by the loop's first barrier
+  int* const flags = queue + 2;
+  int* const err = queue + 5;
+  PairSlot* slot = (int)blockIdx.x < 2 * npairs ? pslots + (blockIdx.x >> 1) : nullptr;
+  const int half = blockIdx.x & 1;
+  if (threadIdx.x == 0) {
+    sh.phase = 0;
+    sh.fetch = 0;
+  }
   for (;;) {
-    if (threadIdx.x == 0) {
-      const int q = atomicAdd(queue, 1);
+    // ---- the next system: a pair's first block fetches and publishes it
+    if (slot) {
+      if (threadIdx.x == 0 && half == 0) {
+        const int q = atomicAdd(queue + 4, 1);
+        st_co_i(&slot->sys[sh.fetch & 1], q < nheavy ? order[q] : -1);
+      }
+      if (!pair_barrier(slot, sh, err)) return;
+      if (threadIdx.x == 0) sh.sys = ld_co_i(&slot->sys[sh.fetch++ & 1]);
+    } else if (threadIdx.x == 0) {
+      const int q = nheavy + atomicAdd(queue, 1);
       sh.sys = q < nsys ? order[q] : -1;
-      sh.status = sh.sys >= 0 ? __hip_atomic_load(&ctrl[sh.sys].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                              : -1;
     }
     __syncthreads();
     const int s = sh.sys;
-    if (s < 0) return;
-    if (sh.status != ST_RUNNING) {
-      __syncthreads();
+    if (s < 0) {
+      if (!slot) return;
+      slot = nullptr;  // no large system left: both blocks go on alone
       continue;
     }
-    const SysDesc d = desc[s];
     Ctrl* c = &ctrl[s];
-    Team<TEAM, MAXPT> tm(sh, d, vel, frc, xref);
+    copy_ctrl(&sh.mine, c);
+    __syncthreads();
+    if (sh.mine.status != ST_RUNNING) continue;
+    const SysDesc d = desc[s];
+    Team<TEAM, MAXPT> tm(sh, d, vel, frc, xref, slot, half);
     for (int a = threadIdx.x; a < d.n; a += TEAM) sh.x[a] = pos[d.off + a];
     if (threadIdx.x == 0) {
-      sh.viol = c->viol;
-      sh.prec = c->precision;
-      sh.neg = c->neg;
-      sh.mix_first = c->mix_first;
-      sh.hsb = c->hsb;
-      sh.k1 = c->kick1;
-      sh.k2 = c->kick2;
-      sh.k3 = c->kick3;
-      sh.cv = c->cv;
-      sh.cf = c->cf;
-      sh.dtx = c->dtx;
+      const Ctrl& m = sh.mine;
+      sh.status = m.status;
+      sh.viol = m.viol;
+      sh.prec = m.precision;
+      sh.neg = m.neg;
+      sh.mix_first = m.mix_first;
+      sh.hsb = m.hsb;
+      sh.k1 = m.kick1;
+      sh.k2 = m.kick2;
+      sh.k3 = m.kick3;
+      sh.cv = m.cv;
+      sh.cf = m.cf;
+      sh.dtx = m.dtx;
     }
     __syncthreads();
-    if (c->evals == 0) {
+    bool ok = true, resume = true;
+    if (sh.mine.evals == 0) {
       // first visit: a non-finite input position fails this system alone
       // (its positions stay as given; the queue moves on)
       int bad = 0;
@@ -611,83 +809,126 @@ __global__ __launch_bounds__(TEAM) void k_batched(const SysDesc* __restrict__ de
         bad |= !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z));
       }
       if (__syncthreads_or(bad)) {
-        if (threadIdx.x == 0) c->status = FIRE_E_NONFINITE;
+        if (threadIdx.x == 0) sh.mine.status = FIRE_E_NONFINITE;
+        resume = false;
+      }
+    }
+    if (resume) {
+      if (sh.viol) {  // first visit (or after a capacity change): build the list
+        if (!tm.build(nbr, nn, kb, P.rc2, err)) return;
+        if (sh.overflow) ok = false;
+      }
+      if (ok && sh.mine.evals == 0) {  // evaluation 0 and the set-up of iteration 1
+        if (threadIdx.x == 0) sh.k3 = 0.0;
         __syncthreads();
-        continue;
+        if (!evaluate<TEAM, MAXPT, POT>(tm, P, nbr, nn, kb, xfp, err)) return;
       }
-    }
-    bool ok = true;
-    if (sh.viol) {  // first visit (or after a capacity change): build the list
-      tm.build(nbr, nn, kb, P.rc2);
-      if (sh.overflow) ok = false;
-    }
-    if (ok && c->evals == 0) {  // evaluation 0 and the set-up of iteration 1
-      if (threadIdx.x == 0) sh.k3 = 0.0;
-      __syncthreads();
-      evaluate<TEAM, MAXPT, POT>(tm, c, P, nbr, nn, kb);
-    }
-    for (int it = 0; ok && it < chunk && sh.status == ST_RUNNING; ++it) {
-      // ---- update (same step as the single-system update kernel)
-      int viol = 0;
+      const double skin_half2 = sh.mine.skin_half2;
+      for (int it = 0; ok && it < chunk && sh.status == ST_RUNNING; ++it) {
+        // ---- update (same step as the single-system update kernel)
+        int viol = 0;
+#pragma unroll 1
+        for (int h = tm.h0; h < tm.h1; ++h)
 #pragma unroll
-      for (int k = 0; k < MAXPT; ++k) {
-        const int a = tm.atom(k);
-        if (a >= d.n) continue;
-        const double4 p = sh.x[a];
-        const double4 v0 = tm.vel[a], f0 = tm.frc[a], xr = tm.xref[a];
-        double vv[3] = {v0.x, v0.y, v0.z};
-        const double ff[3] = {f0.x, f0.y, f0.z};
-        double xx[3] = {p.x, p.y, p.z};
-        for (int q = 0; q < 3; ++q) {
-          double vd = vv[q], xd = xx[q];
-          if (sh.neg) {
-            xd -= sh.hsb * vd;
-            vd = 0.0;
+        for (int k = 0; k < MAXPT; ++k) {
+          const int a = tm.atom(h, k);
+          if (a >= tm.end(h)) break;
+          const double4 p = sh.x[a];
+          const double4 v0 = tm.vel[a], f0 = tm.frc[a], xr = tm.xref[a];
+          double vv[3] = {v0.x, v0.y, v0.z};
+          const double ff[3] = {f0.x, f0.y, f0.z};
+          double xx[3] = {p.x, p.y, p.z};
+          for (int q = 0; q < 3; ++q) {
+            double vd = vv[q], xd = xx[q];
+            if (sh.neg) {
+              xd -= sh.hsb * vd;
+              vd = 0.0;
+            }
+            if (sh.mix_first) vd = sh.cv * vd + sh.cf * ff[q];
+            vd = vd + sh.k1 * ff[q];
+            if (!sh.mix_first) vd = sh.cv * vd + sh.cf * ff[q];
+            xd = xd + sh.dtx * vd;
+            vd = vd + sh.k2 * ff[q];
+            vv[q] = vd;
+            xx[q] = xd;
           }
-          if (sh.mix_first) vd = sh.cv * vd + sh.cf * ff[q];
-          vd = vd + sh.k1 * ff[q];
-          if (!sh.mix_first) vd = sh.cv * vd + sh.cf * ff[q];
-          xd = xd + sh.dtx * vd;
-          vd = vd + sh.k2 * ff[q];
-          vv[q] = vd;
-          xx[q] = xd;
+          tm.vel[a] = make_double4(vv[0], vv[1], vv[2], 0.0);
+          sh.x[a] = make_double4(xx[0], xx[1], xx[2], p.w);
+          if (slot) {
+            double* g = reinterpret_cast<double*>(pos + d.off + a);
+            st_co(g, xx[0]);
+            st_co(g + 1, xx[1]);
+            st_co(g + 2, xx[2]);
+          }
+          const double ex = xx[0] - xr.x, ey = xx[1] - xr.y, ez = xx[2] - xr.z;
+          if (ex * ex + ey * ey + ez * ez > skin_half2) viol = 1;
         }
-        tm.vel[a] = make_double4(vv[0], vv[1], vv[2], 0.0);
-        sh.x[a] = make_double4(xx[0], xx[1], xx[2], p.w);
-        const double ex = xx[0] - xr.x, ey = xx[1] - xr.y, ez = xx[2] - xr.z;
-        if (ex * ex + ey * ey + ez * ez > c->skin_half2) viol = 1;
+        if (threadIdx.x == 0) sh.viol = 0;
+        __syncthreads();
+        if (viol) sh.viol = 1;
+        if (slot) {  // share the skin flags and the new positions
+          __syncthreads();
+          if (threadIdx.x == 0) st_co_i(&slot->vflag[half], sh.viol);
+          if (!pair_barrier(slot, sh, err)) return;
+          if (threadIdx.x == 0) sh.viol |= ld_co_i(&slot->vflag[half ^ 1]);
+          const int h = half ^ 1;
+#pragma unroll 1
+          for (int k = 0; k < MAXPT; ++k) {
+            const int a = tm.atom(h, k);
+            if (a >= tm.end(h)) break;
+            const double* g = reinterpret_cast<const double*>(pos + d.off + a);
+            double4& x = sh.x[a];
+            x.x = ld_co(g);
+            x.y = ld_co(g + 1);
+            x.z = ld_co(g + 2);
+          }
+        }
+        __syncthreads();
+        if (sh.viol) {
+          if (!tm.build(nbr, nn, kb, P.rc2, err)) return;
+          if (sh.overflow) {
+            ok = false;
+            break;
+          }
+        }
+        if (!evaluate<TEAM, MAXPT, POT>(tm, P, nbr, nn, kb, xfp, err)) return;
       }
-      if (threadIdx.x == 0) sh.viol = 0;
-      __syncthreads();
-      if (viol) sh.viol = 1;
-      __syncthreads();
-      if (sh.viol) {
-        tm.build(nbr, nn, kb, P.rc2);
-        if (sh.overflow) {
-          ok = false;
-          break;
+      if (!ok && threadIdx.x == 0) {
+        // list capacity exceeded or atoms coincide: hand the system to the host
+        if (sh.overflow & 2) sh.mine.status = FIRE_E_OVERLAP;
+        else {
+          sh.mine.status = ST_PAUSED;
+          sh.mine.pause = PAUSE_REBUILD;
+          if (half == 0 || !slot) atomicMax(&flags[0], 1);
         }
       }
-      evaluate<TEAM, MAXPT, POT>(tm, c, P, nbr, nn, kb);
-    }
-    if (!ok && threadIdx.x == 0) {
-      // list capacity exceeded or atoms coincide: hand the system to the host
-      if (sh.overflow & 2) c->status = FIRE_E_OVERLAP;
-      else {
-        c->status = ST_PAUSED;
-        c->pause = PAUSE_REBUILD;
-        atomicMax(&flags[0], 1);
+      // write this block's positions back (v, F and the skin reference are in place)
+#pragma unroll 1
+      for (int h = tm.h0; h < tm.h1; ++h)
+#pragma unroll 1
+      for (int k = 0; k < MAXPT; ++k) {
+        const int a = tm.atom(h, k);
+        if (a >= tm.end(h)) break;
+        pos[d.off + a] = sh.x[a];
       }
+      if (threadIdx.x == 0) sh.mine.viol = ok ? 0 : 1;
     }
-    // write the positions back (v, F and the skin reference are in place)
-    for (int a = threadIdx.x; a < d.n; a += TEAM) pos[d.off + a] = sh.x[a];
-    if (threadIdx.x == 0) c->viol = ok ? 0 : 1;
+    // the control record back to global memory (by a pair's first block, once
+    // the second has taken its copy)
+    __syncthreads();
+    if (slot && !pair_barrier(slot, sh, err)) return;
+    if (!slot || half == 0) copy_ctrl(c, &sh.mine);
     __syncthreads();
   }
 }
 
-__global__ void k_reset_queue(int* queue) {
-  if (threadIdx.x == 0) *queue = 0;
+// Queue heads and pair barriers of one launch back to zero.
+__global__ void k_reset_queue(int* queue, PairSlot* pslots, int npairs) {
+  if (threadIdx.x == 0) {
+    queue[0] = 0;
+    queue[4] = 0;
+  }
+  for (int p = threadIdx.x; p < npairs; p += blockDim.x) pslots[p].bar = 0;
 }
 
 __global__ void k_zero_ints(int* p, int n) {
@@ -750,8 +991,8 @@ struct Config {
   int team, chunk;
 };
 
-using KernelFn = void (*)(const SysDesc*, Ctrl*, const int*, int, int*, double4*, double4*, double4*, double4*,
-                          unsigned short*, unsigned short*, int, PotDev, int, int*);
+using KernelFn = void (*)(const SysDesc*, Ctrl*, const int*, int, int, int, PairSlot*, double*, int*, double4*,
+                          double4*, double4*, double4*, unsigned short*, unsigned short*, int, PotDev, int);
 
 KernelFn kernel_for(int team, int pot) {
   if (pot == FIRE_POT_LJ) return team == 1024 ? k_batched<1024, 4, FIRE_POT_LJ> : k_batched<512, 8, FIRE_POT_LJ>;
@@ -764,8 +1005,10 @@ struct Workspace {
   SysDesc* desc = nullptr;
   Ctrl* ctrl = nullptr;
   int* order = nullptr;
-  int* queue = nullptr;  // [0] queue head, [1] running count, [2..3] flags
+  int* queue = nullptr;  // [0] queue head, [1] running count, [2] flag, [4] queue head, [5] error
   int* h_small = nullptr;
+  PairSlot* pslots = nullptr;  // kMaxPairs barriers of pairs of teams
+  double* xfp = nullptr;       // F'(rho) exchange of pairs, per atom
   double* stage = nullptr;
   double4 *pos = nullptr, *vel = nullptr, *frc = nullptr, *xref = nullptr;
   unsigned short *nbr = nullptr, *nn = nullptr;
@@ -776,6 +1019,7 @@ void release(Workspace* w) {
   if (!w) return;
   hipFree(w->desc); hipFree(w->ctrl); hipFree(w->order); hipFree(w->queue); hipFree(w->stage);
   hipFree(w->pos); hipFree(w->vel); hipFree(w->frc); hipFree(w->xref); hipFree(w->nbr); hipFree(w->nn);
+  hipFree(w->pslots); hipFree(w->xfp);
   if (w->h_small) hipHostFree(w->h_small);
   delete w;
 }
@@ -821,7 +1065,9 @@ int ensure(fire_ctx* ctx, Workspace* w, int nsys, int ntot, int kb) {
   }
   if (ntot > w->cap_atoms) {
     hipFree(w->stage); hipFree(w->pos); hipFree(w->vel); hipFree(w->frc); hipFree(w->xref); hipFree(w->nn);
+    hipFree(w->xfp);
     BCHK(balloc(&w->stage, 3 * (size_t)ntot));
+    BCHK(balloc(&w->xfp, ntot));
     BCHK(balloc(&w->pos, ntot));
     BCHK(balloc(&w->vel, ntot));
     BCHK(balloc(&w->frc, ntot));
@@ -836,6 +1082,7 @@ int ensure(fire_ctx* ctx, Workspace* w, int nsys, int ntot, int kb) {
     w->cap_kb = kb;
   }
   if (!w->queue) {
+    BCHK(balloc(&w->pslots, kMaxPairs));
     BCHK(balloc(&w->queue, 8));
     BCHK(hipHostMalloc((void**)&w->h_small, 8 * sizeof(int), hipHostMallocDefault));
   }
@@ -851,13 +1098,63 @@ int reset_state(fire_ctx* ctx, Workspace* w, const std::vector<Ctrl>& c0, hipStr
   return FIRE_OK;
 }
 
-// One replay unit: reset the queue and run the persistent kernel once.
+// Blocks of the persistent launch and the share of its systems taken by
+// pairs of blocks.  A pair halves a system's atoms per block at the price of
+// three barriers across CUs per iteration (1.7-1.8 times faster than a block
+// alone above 1.5 team widths, no faster below), so only systems of more
+// than 1.5 team widths are candidates.  With no more systems than CUs, spare
+// CUs become the partners of the candidates of most work; with more, 3/8 of
+// the CUs form pairs and take the 2.6 candidates each of most work, which
+// brings the longest relaxations toward the mean load of a CU.
+// FIRE_BATCH_PAIRS=0: no pairs; =force: every system a candidate; =P,H: P
+// pairs for the H candidates of most work.  `order` is the queue order
+// (decreasing work); `launch_order` receives the pairs' systems first, then
+// the others in queue order.  Pairing changes no result: a system gets the
+// same bits from a pair and from a block alone.
+struct Launch {
+  int nteams, npairs, nheavy;
+};
+
+Launch plan_launch(const SysDesc* desc, const int* order, int nsys, int ncu, int team, bool allow_pairs,
+                   int* launch_order) {
+  Launch l{std::min(nsys, ncu), 0, 0};
+  const char* e = getenv("FIRE_BATCH_PAIRS");
+  const bool off = !allow_pairs || (e && strcmp(e, "0") == 0) || ncu < 2;
+  const bool force = e && strcmp(e, "force") == 0;
+  auto candidate = [&](int q) { return force || desc[q].n > team * 3 / 2; };
+  int cand = 0;
+  for (int k = 0; k < nsys && !off; ++k) cand += candidate(order[k]);
+  int fp = 0, fh = 0;
+  if (off) {
+  } else if (e && sscanf(e, "%d,%d", &fp, &fh) == 2) {
+    l.npairs = std::max(0, std::min({fp, cand, ncu / 2}));
+    l.nheavy = std::max(l.npairs, std::min(fh, cand));
+  } else if (nsys <= ncu) {
+    l.npairs = std::min(cand, ncu - nsys);
+    l.nheavy = l.npairs;
+  } else {
+    l.npairs = std::min(cand, ncu * 3 / 8);
+    l.nheavy = std::min(cand, l.npairs * 13 / 5);
+  }
+  l.npairs = std::min(l.npairs, kMaxPairs);
+  l.nteams = std::min(ncu, std::max(2 * l.npairs, nsys + l.npairs));
+  int h = 0, r = l.nheavy;
+  for (int k = 0; k < nsys; ++k) {
+    const int q = order[k];
+    if (h < l.nheavy && candidate(q)) launch_order[h++] = q;
+    else launch_order[r++] = q;
+  }
+  return l;
+}
+
+// One replay unit: reset the queues and run the persistent kernel once.
 template <typename B>
-void launch_chunk(const B* w, const PotDev& P, const Config& cf, hipStream_t s, int nteams) {
-  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, w->queue);
+void launch_chunk(const B* w, const PotDev& P, const Config& cf, const Launch& l, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(256), 0, s, w->queue, w->pslots, l.npairs);
   KernelFn fn = kernel_for(cf.team, P.kind);
-  hipLaunchKernelGGL(fn, dim3(nteams), dim3(cf.team), 0, s, w->desc, w->ctrl, w->order, w->nsys, w->queue, w->pos,
-                     w->vel, w->frc, w->xref, w->nbr, w->nn, w->kb, P, cf.chunk, w->queue + 2);
+  hipLaunchKernelGGL(fn, dim3(l.nteams), dim3(cf.team), 0, s, w->desc, w->ctrl, w->order, w->nsys, l.nheavy,
+                     l.npairs, w->pslots, w->xfp, w->queue, w->pos, w->vel, w->frc, w->xref, w->nbr, w->nn, w->kb,
+                     P, cf.chunk);
   hipLaunchKernelGGL(k_count_running, dim3(1), dim3(1024), 0, s, w->ctrl, w->nsys, w->queue + 1);
 }
 
@@ -888,13 +1185,21 @@ void save_cache(Workspace* w) {
   for (auto& kv : w->tuned) f << kv.first << " " << kv.second.team << " " << kv.second.chunk << "\n";
 }
 
-// Systems in decreasing size, equal sizes in index order (a counting sort:
-// no allocation, sizes are at most kMaxAtoms).
-void order_by_size(const SysDesc* desc, int nsys, int* order) {
-  int count[kMaxAtoms + 2] = {0};
-  for (int q = 0; q < nsys; ++q) count[kMaxAtoms - desc[q].n + 1] += 1;
-  for (int k = 1; k <= kMaxAtoms + 1; ++k) count[k] += count[k - 1];
-  for (int q = 0; q < nsys; ++q) order[count[kMaxAtoms - desc[q].n]++] = q;
+// Systems in decreasing estimated work, equal estimates in index order: the
+// atom count times (3 + free axes) / 3, since a free surface lengthens a
+// relaxation (the 512-system EAM-form batch: clusters 477 iterations on
+// average, periodic boxes 235).  Longest first keeps the queue's tail short.
+// Allocates nothing.
+void order_by_work(const SysDesc* desc, int nsys, int* order) {
+  auto work = [&](int q) {
+    const SysDesc& d = desc[q];
+    return (long long)d.n * (3 + !d.box.per[0] + !d.box.per[1] + !d.box.per[2]);
+  };
+  for (int q = 0; q < nsys; ++q) order[q] = q;
+  std::sort(order, order + nsys, [&](int a, int b) {
+    const long long wa = work(a), wb = work(b);
+    return wa != wb ? wa > wb : a < b;
+  });
 }
 
 struct BatchPlan {
@@ -959,7 +1264,7 @@ int prepare_batch(fire_ctx* ctx, int nsys, const long long* offsets, const fire_
   }
   int kb = (int)(4.18879 * std::max(max_dens_vol, 0.1 * 1.0) * 1.6) + 24;
   kb = (std::max(kb, 32) + 3) & ~3;  // lists are read in groups of four
-  order_by_size(desc, nsys, order);
+  order_by_work(desc, nsys, order);
   plan->nsys = nsys;
   plan->ntot = (int)ntot_ll;
   plan->maxn = maxn;
@@ -1019,7 +1324,7 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     return fire_ctx_error(ctx, FIRE_E_ARG, "batched: nsys >= 1 and non-NULL arrays are required");
   std::vector<SysDesc> desc(nsys);
   std::vector<Ctrl> c0(nsys);
-  std::vector<int> order(nsys);
+  std::vector<int> order(nsys), lorder(nsys);
   BatchPlan plan;
   int rc = prepare_batch(ctx, nsys, offsets, boxes, pot, per_sys, tol, max_steps, desc.data(), c0.data(),
                          order.data(), &plan);
@@ -1041,7 +1346,6 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     w->ntot = ntot;
     w->kb = kb;
     BCHK(hipMemcpyAsync(w->desc, desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, s));
-    BCHK(hipMemcpyAsync(w->order, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, s));
     BCHK(hipMemcpyAsync(w->stage, pos, sizeof(double) * 3 * ntot,
                         host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
     BCHK(hipMemsetAsync(w->queue, 0, 8 * sizeof(int), s));
@@ -1052,13 +1356,12 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     BCHK(hipGetDevice(&dev));
     int ncu = 256;
     BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int nteams = std::min(nsys, ncu);
 
     // ---- team shape: the cached choice, else timed on this batch (state reset afterwards)
     const int prec0 = c0[0].precision;
     bool found = false;
     Config cfg = config_for(w, plan, prec0, &found);
-    char info[192];
+    char info[320];
     snprintf(info, sizeof info, "batched: %d-thread teams, chunks of %d iterations (%s)", cfg.team, cfg.chunk,
              getenv("FIRE_BATCH_TEAM") ? "FIRE_BATCH_TEAM" : "cached");
     if (!found) {
@@ -1070,9 +1373,11 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
         hipEvent_t e0, e1;
         BCHK(hipEventCreate(&e0));
         BCHK(hipEventCreate(&e1));
-        launch_chunk(w, P, cand, s, nteams);  // includes the list build; not timed
+        const Launch l = plan_launch(desc.data(), order.data(), nsys, ncu, team, true, lorder.data());
+        BCHK(hipMemcpyAsync(w->order, lorder.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, s));
+        launch_chunk(w, P, cand, l, s);  // includes the list build; not timed
         BCHK(hipEventRecord(e0, s));
-        launch_chunk(w, P, cand, s, nteams);
+        launch_chunk(w, P, cand, l, s);
         BCHK(hipEventRecord(e1, s));
         BCHK(hipEventSynchronize(e1));
         float ms = 0;
@@ -1092,6 +1397,11 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
       snprintf(info, sizeof info, "batched: %d-thread teams, chunks of %d iterations (tuned: a 32-iteration chunk took "
                "%.2f ms with 1024-thread teams, %.2f with 512)", cfg.team, cfg.chunk, t[0], t[1]);
     }
+    const Launch lau = plan_launch(desc.data(), order.data(), nsys, ncu, cfg.team, true, lorder.data());
+    BCHK(hipMemcpyAsync(w->order, lorder.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, s));
+    const size_t used = strlen(info);
+    snprintf(info + used, sizeof info - used, "; %d blocks, %d pairs of them for %d systems of most work", lau.nteams,
+             lau.npairs, lau.nheavy);
     fire_ctx_set_tuning_info(ctx, info);
 
     // ---- graph: queue reset, persistent kernel, running count, poll copy
@@ -1100,8 +1410,8 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     hipStream_t cap;
     BCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     BCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
-    launch_chunk(w, P, cfg, cap, nteams);
-    BCHK(hipMemcpyAsync(w->h_small, w->queue, 4 * sizeof(int), hipMemcpyDeviceToHost, cap));
+    launch_chunk(w, P, cfg, lau, cap);
+    BCHK(hipMemcpyAsync(w->h_small, w->queue, 6 * sizeof(int), hipMemcpyDeviceToHost, cap));
     BCHK(hipStreamEndCapture(cap, &graph));
     BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     hipGraphDestroy(graph);
@@ -1111,6 +1421,10 @@ extern "C" int fire_batched_run(fire_ctx* ctx, int nsys, const long long* offset
     for (long long r = 0; r <= max_replays; ++r) {
       BCHK(hipGraphLaunch(exec, s));
       BCHK(hipStreamSynchronize(s));
+      if (w->h_small[5]) {
+        hipGraphExecDestroy(exec);
+        return fire_ctx_error(ctx, FIRE_E_DEVICE, "batched: a pair of teams timed out at a barrier");
+      }
       if (w->h_small[2]) {  // a list outgrew its capacity
         need_more = true;
         break;
@@ -1190,6 +1504,8 @@ struct Carve {
   double* stage = nullptr;
   double4 *pos = nullptr, *vel = nullptr, *frc = nullptr, *xref = nullptr;
   unsigned short *nn = nullptr, *nbr = nullptr;
+  PairSlot* pslots = nullptr;  // no pairs here: every block works alone
+  double* xfp = nullptr;
   size_t bytes = 0;
 };
 
@@ -1274,7 +1590,8 @@ extern "C" int fire_batched_run_noalloc(fire_ctx* ctx, void* slot, int nsys, con
                                 na->h_ctrl[0].precision, &found);
   int ncu = 256;
   BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int nteams = std::min(nsys, ncu);
+  // no pairs here, so the launch order is the queue order
+  const Launch lau = plan_launch(na->h_desc, na->h_order, nsys, ncu, cfg.team, false, na->h_order);
   int kb = plan.kb;
   for (int attempt = 0; attempt < 4; ++attempt) {
     if (carve(nullptr, nsys, plan.ntot, kb).bytes > kScratchBytes)
@@ -1294,7 +1611,7 @@ extern "C" int fire_batched_run_noalloc(fire_ctx* ctx, void* slot, int nsys, con
     const long long max_rounds = max_steps / cfg.chunk + 4;
     bool need_more = false;
     for (long long r = 0; r <= max_rounds; ++r) {
-      launch_chunk(&w, P, cfg, s, nteams);
+      launch_chunk(&w, P, cfg, lau, s);
       BCHK(hipMemcpyAsync(na->h_poll, w.queue, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
       BCHK(hipStreamSynchronize(s));
       if (na->h_poll[2]) {  // a list outgrew its capacity

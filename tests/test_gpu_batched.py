@@ -211,3 +211,100 @@ def test_tuning_info_names_the_batched_team_shape(api):
     info = c.fire_tuning_info()
     c.close()
     assert info.startswith("batched: ") and "-thread teams" in info and "chunks of" in info
+
+
+def _run_batched(api, monkeypatch, systems, pairs, team=None, precision="fp64", chunk=None, per_sys=None,
+                 pos_in=None):
+    if pairs is None:
+        monkeypatch.delenv("FIRE_BATCH_PAIRS", raising=False)
+    else:
+        monkeypatch.setenv("FIRE_BATCH_PAIRS", pairs)
+    if team:
+        monkeypatch.setenv("FIRE_BATCH_TEAM", str(team))
+    else:
+        monkeypatch.delenv("FIRE_BATCH_TEAM", raising=False)
+    if chunk:
+        monkeypatch.setenv("FIRE_BATCH_CHUNK", str(chunk))
+    else:
+        monkeypatch.delenv("FIRE_BATCH_CHUNK", raising=False)
+    c = api.Context(0, systems[0].fire, precision=precision)
+    pos = pos_in if pos_in is not None else [s.pos for s in systems]
+    out = c.fire_minimize_batched([(p, s.box) for p, s in zip(pos, systems)], systems[0].potential, 1e-6, 20000,
+                                  per_sys=per_sys)
+    info = c.fire_tuning_info()
+    c.close()
+    return out, info
+
+
+def _assert_same_bits(a, b):
+    (pa, ra), (pb, rb) = a, b
+    for x, y, u, v in zip(pa, pb, ra, rb):
+        np.testing.assert_array_equal(x, y)
+        for k in ("stop", "iterations", "force_evals", "energy", "fmax", "dt", "alpha", "iterations_low"):
+            assert u[k] == v[k], (k, u[k], v[k])
+
+
+@pytest.mark.parametrize("team", [1024, 512])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pairs_of_blocks_give_the_bits_of_teams_alone(api, monkeypatch, team, precision):
+    """Every system split over a pair of blocks (two CUs exchanging
+    positions, F'(rho) and records at barriers) ends with the bits of the same
+    system relaxed by one block: the records of the two halves are reduced and
+    added the same way in both cases."""
+    systems = small_batch(nsys=6, seed=15, nmin=150, nmax=2600)
+    (alone, info0) = _run_batched(api, monkeypatch, systems, "0", team, precision)
+    (paired, info1) = _run_batched(api, monkeypatch, systems, "force", team, precision)
+    assert "0 pairs" in info0 and "6 pairs of them for 6 systems of most work" in info1, (info0, info1)
+    _assert_same_bits(alone, paired)
+    for r in paired[1]:
+        assert r["stop"] == "converged"
+
+
+def test_pairs_on_lj_systems(api, monkeypatch):
+    systems = [inputs.lj_box(k, nvac=k, noise=0.05, seed=40 + k) for k in (4, 5, 6)]
+    (alone, _), (paired, info) = (_run_batched(api, monkeypatch, systems, "0"),
+                                  _run_batched(api, monkeypatch, systems, "force"))
+    assert "3 pairs" in info
+    _assert_same_bits(alone, paired)
+    for s, p, r in zip(systems, paired[0], paired[1]):
+        ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 1e-6, 20000)
+        n = len(s.pos)
+        assert r["stop"] == ref["stop"] == "converged"
+        assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
+
+
+def test_large_systems_are_paired_by_default_and_match_the_oracle(api, monkeypatch):
+    """Systems of more than 1.5 team widths get a partner block when CUs are
+    spare: the default plan pairs them, with the bits of blocks alone, and the
+    relaxations agree with the oracle's."""
+    systems = inputs.batched(nsys=2, seed=16, nmin=2000, nmax=2600)
+    (paired, info) = _run_batched(api, monkeypatch, systems, None, team=1024)
+    assert "2 pairs of them for 2 systems of most work" in info, info
+    (alone, _) = _run_batched(api, monkeypatch, systems, "0", team=1024)
+    _assert_same_bits(alone, paired)
+    for s, p, r in zip(systems, paired[0], paired[1]):
+        ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 1e-6, 20000)
+        n = len(s.pos)
+        assert r["stop"] == ref["stop"] == "converged"
+        assert abs(r["energy_per_atom"] - ref["energy"] / n) <= 1e-10 * abs(ref["energy"] / n)
+        e_x, f_x = oracle.energy_forces(p, s.box, s.potential)
+        assert abs(e_x - r["energy"]) <= 1e-12 * abs(e_x)
+
+
+def test_pairs_resume_across_chunks_and_keep_failures_apart(api, monkeypatch):
+    """Forced pairs with 7-iteration chunks (every system suspended and
+    resumed many times), one system with a NaN coordinate and one with two
+    coinciding atoms: the failing systems end with their errors, the others
+    with the bits of one long chunk of blocks alone."""
+    systems = small_batch(nsys=6, seed=17, nmin=300, nmax=1800)
+    pos_in = [s.pos.copy() for s in systems]
+    pos_in[1][5, 0] = np.nan
+    pos_in[3][2] = pos_in[3][11]
+    (alone, _) = _run_batched(api, monkeypatch, systems, "0", pos_in=pos_in)
+    (paired, _) = _run_batched(api, monkeypatch, systems, "force", chunk=7, pos_in=pos_in)
+    assert paired[1][1]["stop"] == "nonfinite" and paired[1][3]["stop"] == "overlap"
+    for k in (0, 2, 4, 5):
+        np.testing.assert_array_equal(alone[0][k], paired[0][k])
+        assert alone[1][k]["iterations"] == paired[1][k]["iterations"]
+        assert alone[1][k]["energy"] == paired[1][k]["energy"]
+        assert paired[1][k]["stop"] == "converged"
