@@ -258,9 +258,12 @@ int fire_lowest_curvature(fire_ctx* ctx, long long n, const double* pos, const f
  * non-finite position or force -- stops with out[s].stop_reason set to
  * FIRE_E_OVERLAP or FIRE_E_NONFINITE and its positions as they were at its
  * last force evaluation; every other system runs to its own stop exactly as
- * without it (the same bits), and the call returns FIRE_OK.  Errors of the
- * call itself (arguments, the device) are returned as usual and then no
- * output is written. */
+ * without it (the same bits), and the call returns FIRE_OK.  How the launch
+ * shares out the work -- a system of more than 1.5 team widths of atoms may
+ * be split over a pair of workgroups on two CUs -- changes no result either.
+ * Errors of the call itself (arguments, the device, FIRE_E_DEVICE if the two
+ * workgroups of a pair lose each other at a barrier for more than two
+ * seconds) are returned as usual and then no output is written. */
 int fire_minimize_batched(fire_ctx* ctx, int nsys, const long long* offsets, double* pos,
                           const fire_box* boxes, const fire_potential* pot, const fire_params* per_sys,
                           double tol, long long max_steps, fire_result* out);

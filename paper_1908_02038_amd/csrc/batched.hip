@@ -2,15 +2,18 @@
 //
 // One workgroup ("team") relaxes one system at a time: the system's positions
 // live in LDS (up to 4096 atoms), velocities, forces and the skin reference in
-// registers, its neighbour list (16-bit system-local indices) in global
-// memory.  Every iteration -- update, EAM density, force pass, team reduction,
-// FIRE control -- runs inside the team with workgroup barriers only, and the
-// team rebuilds its own cell and neighbour list when an atom leaves its skin.
+// per-atom global arrays, its neighbour list (16-bit system-local indices) in
+// global memory.  Every iteration -- update, EAM density, force pass, team
+// reduction, FIRE control -- runs inside the team with workgroup barriers
+// only, and the team rebuilds its own cell and neighbour list when an atom
+// leaves its skin.  The systems of most work go first to pairs of teams on
+// two CUs, which split the atoms and meet at barriers across the two CUs.
 // Each system keeps its own FIRE state (dt, alpha, N_P>0, N_P<=0, counters) in
 // a control record, advanced by the same scalar FIRE 2.0 step as the
 // single-system path.  Teams take systems from a queue ordered by decreasing
-// size and advance each by at most `chunk` iterations per launch; the launch
-// is captured in a hipGraph and replayed until every system has stopped.
+// estimated work and advance each by at most `chunk` iterations per launch;
+// the launch is captured in a hipGraph and replayed until every system has
+// stopped.
 // A small autotuner picks the team shape (and chunk length) by timing the
 // candidates on the batch itself.
 #include <hip/hip_runtime.h>
@@ -40,8 +43,8 @@ constexpr int kMaxAtoms = 4096;  // per system (LDS holds its positions)
 // Iterations per system and launch.  A launch ends when every system has
 // advanced by up to kChunk iterations, so every launch waits for its slowest
 // system: 1,024 instead of 256 lets teams carry on with further systems while
-// a long relaxation runs (512 EAM-form systems: 283 instead of 341 ms; the
-// bound is the longest single relaxation on one CU, about 240 ms there).
+// a long relaxation runs (512 EAM-form systems, one CU per system: 283
+// instead of 341 ms).
 constexpr int kChunk = 1024;
 constexpr int kMaxCells = 1024;  // per-system cell grid in LDS
 constexpr int kRedWidth = 10;    // values per wave in a team reduction
