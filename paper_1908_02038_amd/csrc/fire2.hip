@@ -261,9 +261,12 @@ __global__ void k_ghost_count(double4* __restrict__ pos, int n, BoxDev box, doub
   gcount[i] = choices - 1;
 }
 
-// Ghost positions (slots n + goff[i] ...) with their source slot and shift code.
+// Ghost positions (slots n + goff[i] ...) with their source slot and shift
+// code; ghosts numbered gmax or above (beyond the slot capacity) are not
+// written: the host, which learns the count at the end of the build, then
+// grows the capacity and builds again.
 __global__ void k_ghost_fill(double4* __restrict__ pos, int n, BoxDev box, double rcs, const int* __restrict__ goff,
-                             int* __restrict__ gsrc, int* __restrict__ gcode) {
+                             int* __restrict__ gsrc, int* __restrict__ gcode, int gmax) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 p = pos[i];
@@ -281,6 +284,7 @@ __global__ void k_ghost_fill(double4* __restrict__ pos, int n, BoxDev box, doubl
     if (((m & 1) && !opt[0]) || ((m & 2) && !opt[1]) || ((m & 4) && !opt[2])) continue;
     const int code = ((m & 1) ? opt[0] : 0) | (((m & 2) ? opt[1] : 0) << 2) | (((m & 4) ? opt[2] : 0) << 4);
     const int g = goff[i] + k++;
+    if (g >= gmax) continue;
     pos[n + g] = make_double4(r[0] + ghost_shift(code, 0, box), r[1] + ghost_shift(code, 1, box),
                               r[2] + ghost_shift(code, 2, box), p.w);
     gsrc[g] = i;
@@ -288,14 +292,21 @@ __global__ void k_ghost_fill(double4* __restrict__ pos, int n, BoxDev box, doubl
   }
 }
 
+// Slots of the current build: the real atoms and the ghosts counted on the
+// device (goff[n]), at most gmax of them.  The kernels of a rebuild read the
+// count here, so the host need not wait for it before launching them.
+__device__ __forceinline__ int slot_count(int n, const int* __restrict__ gtot, int gmax) {
+  return n + min(*gtot, gmax);
+}
+
 // Cell of every slot (real and ghost) and per-cell counts.  Ordering key
 // inside a cell: caller index times 64, plus the ghost's shift code.
-__global__ void k_cell_count(const double4* __restrict__ pos, int n, int nt, Grid g,
+__global__ void k_cell_count(const double4* __restrict__ pos, int n, const int* __restrict__ gtot, int gmax, Grid g,
                              const int* __restrict__ cell_rank, const int* __restrict__ id,
                              const int* __restrict__ gsrc, const int* __restrict__ gcode,
                              int* __restrict__ cell_of, long long* __restrict__ key, int* __restrict__ count) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nt) return;
+  if (i >= slot_count(n, gtot, gmax)) return;
   const double4 p = pos[i];
   int cc[3];
   if (i < n) {
@@ -390,10 +401,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int* __restri
   if (i + 3 < m) start[i + 3] = e + c.x + c.y + c.z;
 }
 
-__global__ void k_cell_fill(const int* __restrict__ cell_of, int n, const int* __restrict__ start,
-                            int* __restrict__ cursor, int* __restrict__ order) {
+__global__ void k_cell_fill(const int* __restrict__ cell_of, int n, const int* __restrict__ gtot, int gmax,
+                            const int* __restrict__ start, int* __restrict__ cursor, int* __restrict__ order) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= slot_count(n, gtot, gmax)) return;
   int c = cell_of[i];
   order[start[c] + atomicAdd(&cursor[c], 1)] = i;
 }
@@ -401,10 +412,10 @@ __global__ void k_cell_fill(const int* __restrict__ cell_of, int n, const int* _
 // Deterministic order inside each cell: by key.  One thread per slot ranks
 // its atom among the cell's members.
 __global__ void k_cell_rank(const int* __restrict__ cell_of, const int* __restrict__ start,
-                            const int* __restrict__ bucket, int nt, const long long* __restrict__ key,
-                            int* __restrict__ order) {
+                            const int* __restrict__ bucket, int n, const int* __restrict__ gtot, int gmax,
+                            const long long* __restrict__ key, int* __restrict__ order) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nt) return;
+  if (s >= slot_count(n, gtot, gmax)) return;
   const int a = bucket[s], c = cell_of[a];
   const long long k = key[a];
   const int b = start[c], e = start[c + 1];
@@ -415,7 +426,8 @@ __global__ void k_cell_rank(const int* __restrict__ cell_of, const int* __restri
 
 // Gather every slot into its sorted place.  Real atoms (old slots < n) land
 // in new slots < n and carry v, F, id; ghosts carry their source and shift.
-__global__ void k_permute(const int* __restrict__ order, int n, int nt, int ncap, const double4* __restrict__ pos,
+__global__ void k_permute(const int* __restrict__ order, int n, const int* __restrict__ gtot, int gmax, int ncap,
+                          const double4* __restrict__ pos,
                           const double* __restrict__ vel, const double* __restrict__ frc,
                           const int* __restrict__ id, const int* __restrict__ cell_of,
                           const int* __restrict__ gsrc, const int* __restrict__ gcode,
@@ -423,7 +435,7 @@ __global__ void k_permute(const int* __restrict__ order, int n, int nt, int ncap
                           int* __restrict__ id2, int* __restrict__ srank, int* __restrict__ new_of_old,
                           int* __restrict__ gsrc2, int* __restrict__ gcode2) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nt) return;
+  if (s >= slot_count(n, gtot, gmax)) return;
   const int o = order[s];
   pos2[s] = pos[o];
   srank[s] = cell_of[o];
@@ -444,13 +456,14 @@ __global__ void k_permute(const int* __restrict__ order, int n, int nt, int ncap
 // Copy the sorted slots back into the arrays the captured graphs read (their
 // addresses must not change), and record the build positions for the skin
 // test: one launch over max(nt, n) slots instead of one copy per array.
-__global__ void k_commit(int n, int nt, int ng, int ncap, const double4* __restrict__ pos2,
+__global__ void k_commit(int n, const int* __restrict__ gtot, int gmax, int ncap, const double4* __restrict__ pos2,
                          const int* __restrict__ gsrc2, const int* __restrict__ gcode2,
                          const int* __restrict__ id2, const double* __restrict__ vel2,
                          const double* __restrict__ frc2, double4* __restrict__ pos, int* __restrict__ gsrc,
                          int* __restrict__ gcode, int* __restrict__ id, double* __restrict__ vel,
                          double* __restrict__ frc, double4* __restrict__ xref) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nt = slot_count(n, gtot, gmax), ng = nt - n;
   if (s < nt) pos[s] = pos2[s];
   if (s < ng) {
     gsrc[s] = gsrc2[s];
@@ -469,11 +482,12 @@ __global__ void k_commit(int n, int nt, int ng, int ncap, const double4* __restr
 
 // Link ghosts to the new slots of their sources: real_of[] (slot -> real
 // slot, identity for real atoms) and the per-atom ghost lists (at most 7).
-__global__ void k_ghost_link(int n, int ng, const int* __restrict__ new_of_old, int* __restrict__ gsrc,
-                             int* __restrict__ real_of, int* __restrict__ gcnt, int* __restrict__ glist) {
+__global__ void k_ghost_link(int n, const int* __restrict__ gtot, int gmax, const int* __restrict__ new_of_old,
+                             int* __restrict__ gsrc, int* __restrict__ real_of, int* __restrict__ gcnt,
+                             int* __restrict__ glist) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < n) real_of[s] = s;
-  if (s >= ng) return;
+  if (s >= slot_count(n, gtot, gmax) - n) return;
   const int src = new_of_old[gsrc[s]];
   gsrc[s] = src;
   real_of[n + s] = src;
@@ -499,10 +513,11 @@ __device__ __forceinline__ size_t lidx(int w, int k, int lane, int kcap) {
 
 // FP32 copy of the slot positions relative to the grid origin, for the
 // neighbour search's distance tests.
-__global__ __launch_bounds__(kBlock) void k_pos_f32(const double4* __restrict__ pos, int nt, Grid g,
+__global__ __launch_bounds__(kBlock) void k_pos_f32(const double4* __restrict__ pos, int n,
+                                                    const int* __restrict__ gtot, int gmax, Grid g,
                                                     float4* __restrict__ posf) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < nt) {
+  if (j < slot_count(n, gtot, gmax)) {
     const double4 p = pos[j];
     posf[j] = make_float4((float)(p.x - g.lo[0]), (float)(p.y - g.lo[1]), (float)(p.z - g.lo[2]), 0.0f);
   }
@@ -2209,7 +2224,8 @@ struct fire_ctx {
   int* flags = nullptr;       // device: [0] error bits, [1] max neighbour count
   int* scan_part = nullptr;   // chunk totals of the prefix sums
   int scan_cap = 0;
-  int* h_flags = nullptr;     // pinned
+  int* h_flags = nullptr;     // pinned; [4]: the ghost count read with the list flags
+  bool ghosts_known = false;  // a build finished: ng holds its ghost count
   Ctrl* h_ctrl = nullptr;     // pinned
   unsigned long long* h_poll = nullptr;  // pinned, coherent: status | pause << 32, written by k_poll
   unsigned long long* d_poll = nullptr;  // its device address
@@ -2711,8 +2727,8 @@ int build_lists(fire_ctx* ctx) {
   const bool classes = ctx->pot.kind == FIRE_POT_GUPTA && ctx->list_classes;
   const float split2f = classes ? (float)(ctx->pot.r_in * ctx->pot.r_in) : rcs2f;
   const float cut2f = classes ? (float)ctx->pot.rc2 : rcs2f;
-  hipLaunchKernelGGL(k_pos_f32, dim3(nblocks(n + ctx->ng)), dim3(kBlock), 0, s, ctx->pos, n + ctx->ng, ctx->grid,
-                     ctx->posf);
+  hipLaunchKernelGGL(k_pos_f32, dim3(nblocks(ctx->tcap)), dim3(kBlock), 0, s, ctx->pos, n, ctx->goff + n,
+                     ctx->tcap - 1 - n, ctx->grid, ctx->posf);
   const bool was = ctx->use_lds;
   const size_t limit = lds_budget(ctx, tile);
   // no LDS tiles for the three-body potential (its force pass reads the
@@ -2746,6 +2762,7 @@ int build_lists(fire_ctx* ctx) {
                            ctx->rank_cell, ctx->cell_rank, n, ctx->grid, ctx->nbr, ctx->wcnt, ctx->kcap, hcap, dummy,
                            ctx->tile_h, ctx->hslot, ctx->hsrc, ctx->real_of, ctx->nbr16, ctx->flags);
     }
+    HIPCHK(hipMemcpyAsync(ctx->h_flags + 4, ctx->goff + n, sizeof(int), hipMemcpyDeviceToHost, s));
     int rc = read_flags(ctx);
     if (rc) return rc;
     if (ctx->h_flags[0] & ERR_OVERLAP) return set_err(ctx, FIRE_E_OVERLAP, "two atoms coincide");
@@ -2820,19 +2837,28 @@ int rebuild(fire_ctx* ctx) {
     return FIRE_OK;
   }
   const int nb = nblocks(n);
-  // ---- periodic images
+  // ---- periodic images.  Their number is counted on the device (goff[n]);
+  // the kernels below read it there.  After a first build, while the slot
+  // capacity holds the last count and a quarter more, the host launches the
+  // whole rebuild without waiting for the count, and checks it with the
+  // list flags at the end (a count beyond the capacity: larger arrays and
+  // the build again, waiting this time).
   hipLaunchKernelGGL(k_ghost_count, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, ctx->rcs, ctx->gcount);
   int rc = launch_scan(ctx, s, ctx->gcount, n, ctx->goff);
   if (rc) return rc;
-  HIPCHK(hipMemcpyAsync(ctx->h_flags, ctx->goff + n, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const int ng = ctx->h_flags[0];
-  rc = ensure_slots(ctx, n + ng, n);
-  if (rc) return rc;
-  ctx->ng = ng;
-  const int nt = n + ng;
+  const bool ahead = ctx->ghosts_known && ctx->tcap - 1 - n >= ctx->ng + std::max(ctx->ng / 4, 256);
+  int ng_est = ctx->ng;  // the count, or (launching ahead) the last one
+  if (!ahead) {
+    HIPCHK(hipMemcpyAsync(ctx->h_flags, ctx->goff + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ng_est = ctx->h_flags[0];
+    rc = ensure_slots(ctx, n + ng_est, n);
+    if (rc) return rc;
+  }
+  const int gmax = ctx->tcap - 1 - n;  // ghost slots before the dummy slot
+  const int* gtot = ctx->goff + n;
   hipLaunchKernelGGL(k_ghost_fill, dim3(nb), dim3(kBlock), 0, s, ctx->pos, n, ctx->box, ctx->rcs, ctx->goff,
-                     ctx->gsrc, ctx->gcode);
+                     ctx->gsrc, ctx->gcode, gmax);
   // ---- cell sort of all slots
   rc = make_grid(ctx, n);
   if (rc) return rc;
@@ -2840,22 +2866,22 @@ int rebuild(fire_ctx* ctx) {
   HIPCHK(hipMemsetAsync(ctx->cell_count, 0, sizeof(int) * (g.ncell + 1), s));
   HIPCHK(hipMemsetAsync(ctx->cell_cursor, 0, sizeof(int) * (g.ncell + 1), s));
   HIPCHK(hipMemsetAsync(ctx->gcnt, 0, sizeof(int) * ctx->ncap, s));
-  const int nbt = nblocks(nt);
-  hipLaunchKernelGGL(k_cell_count, dim3(nbt), dim3(kBlock), 0, s, ctx->pos, n, nt, g, ctx->cell_rank, ctx->id,
-                     ctx->gsrc, ctx->gcode, ctx->cell_of, ctx->key, ctx->cell_count);
+  const int nbt = nblocks(ctx->tcap);
+  hipLaunchKernelGGL(k_cell_count, dim3(nbt), dim3(kBlock), 0, s, ctx->pos, n, gtot, gmax, g, ctx->cell_rank,
+                     ctx->id, ctx->gsrc, ctx->gcode, ctx->cell_of, ctx->key, ctx->cell_count);
   rc = launch_scan(ctx, s, ctx->cell_count, g.ncell, ctx->cell_start);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_cell_fill, dim3(nbt), dim3(kBlock), 0, s, ctx->cell_of, nt, ctx->cell_start,
+  hipLaunchKernelGGL(k_cell_fill, dim3(nbt), dim3(kBlock), 0, s, ctx->cell_of, n, gtot, gmax, ctx->cell_start,
                      ctx->cell_cursor, ctx->bucket);
-  hipLaunchKernelGGL(k_cell_rank, dim3(nbt), dim3(kBlock), 0, s, ctx->cell_of, ctx->cell_start, ctx->bucket, nt,
-                     ctx->key, ctx->order);
-  hipLaunchKernelGGL(k_permute, dim3(nbt), dim3(kBlock), 0, s, ctx->order, n, nt, ctx->ncap, ctx->pos, ctx->vel,
-                     ctx->frc, ctx->id, ctx->cell_of, ctx->gsrc, ctx->gcode, ctx->pos2, ctx->vel2, ctx->frc2,
+  hipLaunchKernelGGL(k_cell_rank, dim3(nbt), dim3(kBlock), 0, s, ctx->cell_of, ctx->cell_start, ctx->bucket, n, gtot,
+                     gmax, ctx->key, ctx->order);
+  hipLaunchKernelGGL(k_permute, dim3(nbt), dim3(kBlock), 0, s, ctx->order, n, gtot, gmax, ctx->ncap, ctx->pos,
+                     ctx->vel, ctx->frc, ctx->id, ctx->cell_of, ctx->gsrc, ctx->gcode, ctx->pos2, ctx->vel2, ctx->frc2,
                      ctx->id2, ctx->srank, ctx->new_of_old, ctx->gsrc2, ctx->gcode2);
-  hipLaunchKernelGGL(k_ghost_link, dim3(nblocks(std::max(n, ng))), dim3(kBlock), 0, s, n, ng, ctx->new_of_old,
-                     ctx->gsrc2, ctx->real_of, ctx->gcnt, ctx->glist);
+  hipLaunchKernelGGL(k_ghost_link, dim3(nblocks(std::max(n, gmax))), dim3(kBlock), 0, s, n, gtot, gmax,
+                     ctx->new_of_old, ctx->gsrc2, ctx->real_of, ctx->gcnt, ctx->glist);
   // copy back (not swap): captured graphs hold these buffers' addresses
-  hipLaunchKernelGGL(k_commit, dim3(nbt), dim3(kBlock), 0, s, n, nt, ng, ctx->ncap, ctx->pos2, ctx->gsrc2,
+  hipLaunchKernelGGL(k_commit, dim3(nbt), dim3(kBlock), 0, s, n, gtot, gmax, ctx->ncap, ctx->pos2, ctx->gsrc2,
                      ctx->gcode2, ctx->id2, ctx->vel2, ctx->frc2, ctx->pos, ctx->gsrc, ctx->gcode, ctx->id, ctx->vel,
                      ctx->frc, ctx->xref);
   const int dummy = ctx->tcap - 1;
@@ -2868,12 +2894,20 @@ int rebuild(fire_ctx* ctx) {
     for (int k = 0; k < 3; ++k) vol *= (ctx->box.per[k] ? g.n[k] - 2 : g.n[k]) / std::max(g.inv[k], 1e-300);
     const double dens = n / std::max(vol, 1e-300);
     const int guess = (int)(1.4 * dens * 4.18879 * rcs2 * ctx->rcs) + 16;
-    ctx->kcap = std::min((guess + 3) & ~3, std::max(4, ((nt + 3) & ~3)));
+    ctx->kcap = std::min((guess + 3) & ~3, std::max(4, ((n + ng_est + 3) & ~3)));
     HIPCHK(dalloc(&ctx->nbr, (size_t)ctx->kcap * ctx->ncap));
     ctx->layout_version++;
   }
   rc = build_lists(ctx);
+  if (ahead && (rc || ctx->h_flags[4] > gmax)) {
+    // more ghosts than the slots held (or a failure that might follow from
+    // that): the build again, waiting for the count
+    ctx->ghosts_known = false;
+    return rebuild(ctx);
+  }
   if (rc) return rc;
+  ctx->ng = ctx->h_flags[4];
+  ctx->ghosts_known = true;
   if (ctx->pot.kind == FIRE_POT_SW) {
     const size_t need = (size_t)ctx->kcap * ctx->ncap;
     if (need > ctx->sw_cap) {
