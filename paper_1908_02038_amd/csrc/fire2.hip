@@ -2902,6 +2902,9 @@ int rebuild(fire_ctx* ctx) {
   if (ahead && (rc || ctx->h_flags[4] > gmax)) {
     // more ghosts than the slots held (or a failure that might follow from
     // that): the build again, waiting for the count
+    if (getenv("FIRE_DEBUG"))
+      fprintf(stderr, "[fire] rebuild: %d ghosts beyond the %d ghost slots of a build launched ahead; again\n",
+              ctx->h_flags[4], gmax);
     ctx->ghosts_known = false;
     return rebuild(ctx);
   }

@@ -124,6 +124,32 @@ def test_context_reused_across_growing_and_shrinking_systems(api):
         assert r["energy"] == fresh["energy"]
 
 
+def test_rebuild_launched_ahead_with_too_few_ghost_slots(api, capfd, monkeypatch):
+    """After a first build the host launches a rebuild without waiting for the
+    number of periodic images, which the kernels read on the device.  A free
+    cluster (no images) followed, in the same context, by a periodic box of
+    the same size (about 5,800 images) sends the box's first build past the
+    slots it was launched with: it must be detected, built again, and give
+    the bits of a fresh context."""
+    monkeypatch.setenv("FIRE_DEBUG", "1")
+    cluster = inputs.lj_box(10, nvac=0, noise=0.03, seed=31, periodic=(0, 0, 0))
+    box = inputs.lj_box(10, nvac=0, noise=0.03, seed=32)
+    assert len(cluster.pos) == len(box.pos) == 4000
+    c = api.Context(0, box.fire)
+    c.fire_minimize(cluster.pos, cluster.box, cluster.potential, 0.0, 5)
+    capfd.readouterr()
+    got = c.fire_minimize(box.pos, box.box, box.potential, 1e-6, 20000)
+    err = capfd.readouterr().err
+    c.close()
+    assert "ghost slots of a build launched ahead; again" in err, err[-2000:]
+    f = api.Context(0, box.fire)
+    fresh = f.fire_minimize(box.pos, box.box, box.potential, 1e-6, 20000)
+    f.close()
+    np.testing.assert_array_equal(got["pos"], fresh["pos"])
+    assert got["iterations"] == fresh["iterations"] and got["energy"] == fresh["energy"]
+    assert got["stop"] == "converged"
+
+
 @pytest.mark.parametrize("case", ["wide_box", "far_cluster", "cutoff_shell"])
 def test_fp32_neighbour_search_misses_no_pair(api, case):
     """The neighbour search tests distances in FP32 (coordinates relative to
