@@ -1677,9 +1677,11 @@ __global__ __launch_bounds__(TILE) void k_gupta_density(double4* __restrict__ po
 }
 
 // Gupta force pass: F_i = -sum_j [c phi_t'(r) + (F'_i + F'_j) rho_t'(r)] d/r,
-// e_i = w_e sum_j phi_t(r).
+// e_i = w_e sum_j phi_t(r).  512-atom tiles run two blocks per CU (their LDS
+// reservation is sized for that), which needs four waves per SIMD: at most
+// 128 VGPRs per lane.
 template <typename T, bool LDS, bool WE, int TILE = kBlock>
-__global__ __launch_bounds__(TILE) void k_gupta_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
+__global__ __launch_bounds__(TILE, LDS && TILE >= 512 ? 4 : 1) void k_gupta_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
                                                         Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
                                                         int ncap, PotDev pot, double* __restrict__ frc,
                                                         double* __restrict__ vel, double* __restrict__ part,
@@ -2204,6 +2206,7 @@ struct fire_ctx {
   size_t lds_atoms = 0, lds_limit = 0;  // halo capacity per tile block; byte limit per block
   bool lds_default = true;              // no explicit limit: the LJ pass's 512-atom tiles get kLdsLj
   size_t lds_cap = 0;                   // the device's LDS per block, less a margin for static LDS
+  int ncu = 256;                        // compute units of the device
   size_t lds_boost = 0;                 // default reservation raised for halos that outgrew it (per call)
   int tile = kBlock;                    // atoms per tile of the current lists' halos
   double *part = nullptr, *part_emb = nullptr, *bbox_part = nullptr;
@@ -2670,21 +2673,21 @@ size_t halo_bytes_per_atom(const fire_ctx* ctx) { return ctx->pot.kind == FIRE_P
 //
 // The EAM form has three layouts.  256-atom tiles reserve 52 KB (three
 // force-pass blocks per CU) or 56 KB (two; the density pass keeps three);
-// 512-atom tiles reserve 78 KB.  While an XCD's share of the per-atom state
-// (about 96 B per atom: positions, velocities, forces, F'(rho), the
-// staged-update reads) fits its 4 MB L2, three 256-atom blocks per CU are
-// fastest (253,440-atom bulk: 85.8 us per FP64 evaluation against 91.7 with
-// 512-atom tiles); beyond, the passes stream their halos from beyond the L2,
-// and 512-atom tiles, which stage fewer halo atoms per atom, are fastest
-// (2,037,760-atom slab: 581 against 638 us per FP32 evaluation with two
-// 256-atom blocks per CU, 673 against 705 in FP64).  That size rule is the
-// default; the single-system tuner times all three.
+// 512-atom tiles reserve 78 KB, two blocks per CU, whose force pass is held
+// to 128 VGPRs so that both fit (at 129, as compiled without that bound,
+// only one did).  Once every CU gets a 512-atom tile, those are fastest:
+// they stage fewer halo atoms per atom, and at two blocks per CU the
+// 253,440-atom bulk's 495 tiles run in one round where 990 256-atom tiles
+// take 1.3 rounds of three per CU (81.1 against 86.7 us per FP64
+// evaluation; 2,037,760-atom slab, FP32: 472 against 638 us with two
+// 256-atom blocks per CU).  Smaller systems keep 256-atom tiles, which
+// spread over more CUs.  That size rule is the default; the single-system
+// tuner times all three.
 constexpr size_t kLdsLj = 78 * 1024;
 constexpr size_t kLdsEamLarge = 56 * 1024;
-constexpr long long kL2Atoms = 8LL * (4 << 20) / 96;
 
 int eam_layout(const fire_ctx* ctx) {
-  return ctx->eam_layout >= 0 ? ctx->eam_layout : (ctx->n > kL2Atoms ? 2 : 0);
+  return ctx->eam_layout >= 0 ? ctx->eam_layout : ((long long)ctx->n >= (long long)ctx->ncu * kMaxTile ? 2 : 0);
 }
 
 int tile_atoms(const fire_ctx* ctx) {
@@ -3739,6 +3742,7 @@ int fire_init(fire_ctx** out, int device, const fire_params* params) {
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FIRE_E_DEVICE;
   fire_ctx* ctx = new fire_ctx();
   ctx->device = device;
+  ctx->ncu = std::max(1, prop.multiProcessorCount);
   if (params) ctx->params = *params;
   else fire_params_default(&ctx->params);
   int rc = FIRE_OK;
