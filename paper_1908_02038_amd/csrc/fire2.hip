@@ -1534,13 +1534,12 @@ __device__ __forceinline__ void group_terms(const double4& pi, const double4& p0
 // UPD: the pass first applies the pending update (halo atoms on the fly in
 // LDS, own atoms written to ua.dst) and reads and writes ua's state sets
 // instead of pos / frc / vel; requires LDS.
-template <typename T, bool LDS, bool WE, bool UPD = false>
-__global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
-                                                     Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
-                                                     int ncap, PotDev pot, double* __restrict__ frc,
-                                                     double* __restrict__ vel, double* __restrict__ part,
-                                                     Ctrl* __restrict__ ctrl, double* __restrict__ trace,
-                                                     UpdArgs ua, Props pr) {
+template <typename T, bool LDS, bool WE, bool UPD>
+__device__ __forceinline__ void lj_force_pass(const double4* __restrict__ pos, const int* __restrict__ nbr, Tiles tl,
+                                              const int* __restrict__ wcnt, int n, int kcap, int ncap, PotDev pot,
+                                              double* __restrict__ frc, double* __restrict__ vel,
+                                              double* __restrict__ part, Ctrl* __restrict__ ctrl,
+                                              double* __restrict__ trace, const UpdArgs& ua, const Props& pr) {
   static_assert(!UPD || LDS, "the update is applied while staging the LDS halo");
   if (!pass_gate<UPD>(ctrl)) return;
   const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -1594,6 +1593,30 @@ __global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict
                              });
   force_epilogue<kMaxTile>(i, valid, (double)ax, (double)ay, (double)az, (double)ae, ep, frc, vel, ncap, part, 0.0,
                            b, ctrl, trace, pr, UPD);
+}
+
+template <typename T, bool LDS, bool WE, bool UPD = false>
+__global__ __launch_bounds__(kMaxTile) void k_lj_force(const double4* __restrict__ pos, const int* __restrict__ nbr,
+                                                     Tiles tl, const int* __restrict__ wcnt, int n, int kcap,
+                                                     int ncap, PotDev pot, double* __restrict__ frc,
+                                                     double* __restrict__ vel, double* __restrict__ part,
+                                                     Ctrl* __restrict__ ctrl, double* __restrict__ trace,
+                                                     UpdArgs ua, Props pr) {
+  lj_force_pass<T, LDS, WE, UPD>(pos, nbr, tl, wcnt, n, kcap, ncap, pot, frc, vel, part, ctrl, trace, ua, pr);
+}
+
+// The same pass compiled for four waves per SIMD (at most 128 VGPRs, a few
+// spills outside the pair loop), so that two 512-atom tile blocks share a CU
+// when there are more tiles than CUs (1,043,333 atoms: 179 against 231 us per
+// pass).  With one tile per CU at most (the 130,417-atom box) k_lj_force,
+// which keeps every value in registers, is a little faster (28.1 against
+// 28.4 us).
+template <typename T, bool LDS, bool WE, bool UPD = false>
+__global__ __launch_bounds__(kMaxTile, 4) void k_lj_force_two_per_cu(
+    const double4* __restrict__ pos, const int* __restrict__ nbr, Tiles tl, const int* __restrict__ wcnt, int n,
+    int kcap, int ncap, PotDev pot, double* __restrict__ frc, double* __restrict__ vel, double* __restrict__ part,
+    Ctrl* __restrict__ ctrl, double* __restrict__ trace, UpdArgs ua, Props pr) {
+  lj_force_pass<T, LDS, WE, UPD>(pos, nbr, tl, wcnt, n, kcap, ncap, pot, frc, vel, part, ctrl, trace, ua, pr);
 }
 
 // Gupta density pass: rho_i = sum_j exp(-2q (r/r0 - 1)) S(r); stores
@@ -2973,8 +2996,12 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
     if (parity >= 0) {
       const StateBuf d = ua.dst;
       if (P.kind == FIRE_POT_LJ) {
-        hipLaunchKernelGGL((k_lj_force<T, true, WE, true>), dim3(nt), dim3(tile), sm, s, ua.src.pos, ctx->nbr, tl,
-                           ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
+        if (nt > ctx->ncu)
+          hipLaunchKernelGGL((k_lj_force_two_per_cu<T, true, WE, true>), dim3(nt), dim3(tile), sm, s, ua.src.pos, ctx->nbr,
+                             tl, ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
+        else
+          hipLaunchKernelGGL((k_lj_force<T, true, WE, true>), dim3(nt), dim3(tile), sm, s, ua.src.pos, ctx->nbr, tl,
+                             ctx->wcnt, n, kc, nc, P, d.frc, d.vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
       } else if (tile == kMaxTile) {
         hipLaunchKernelGGL((k_gupta_density<T, true, true, kMaxTile>), dim3(nt), dim3(tile), sm, s, ua.src.pos,
                            ctx->nbr, tl, ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);
@@ -2992,8 +3019,14 @@ void launch_pair_passes(fire_ctx* ctx, hipStream_t s, int parity) {
     }
   }
   if (P.kind == FIRE_POT_LJ) {
-    hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nt), dim3(tile), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt, n,
-                       kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
+    bool two_per_cu = false;
+    if constexpr (LDS) two_per_cu = nt > ctx->ncu;
+    if (two_per_cu)
+      hipLaunchKernelGGL((k_lj_force_two_per_cu<T, true, WE>), dim3(nt), dim3(tile), sm, s, ctx->pos, ctx->nbr, tl,
+                         ctx->wcnt, n, kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
+    else
+      hipLaunchKernelGGL((k_lj_force<T, LDS, WE>), dim3(nt), dim3(tile), sm, s, ctx->pos, ctx->nbr, tl, ctx->wcnt, n,
+                         kc, nc, P, ctx->frc, ctx->vel, ctx->part, ctx->ctrl, ctx->trace, ua, pr);
   } else if (tile == kMaxTile) {
     hipLaunchKernelGGL((k_gupta_density<T, LDS, false, kMaxTile>), dim3(nt), dim3(tile), sm, s, ctx->pos, ctx->nbr,
                        tl, ctx->wcnt, n, kc, nc, P, ctx->gcnt, ctx->glist, ctx->part_emb, ctx->ctrl, ua);

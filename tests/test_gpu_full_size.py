@@ -165,3 +165,28 @@ def test_slab_relaxation_is_a_minimum(api):
     c.close()
     print(f"slab with an atom on a vacancy hop: lowest Ritz value {lam_h:.6e} eV/A^2, residual {res_h:.3e}")
     assert lam_h < 0
+
+
+def test_lj_beyond_one_tile_per_cu_matches_oracle(api):
+    """A 156,430-atom LJ crystal (the benchmark recipe at 34 cells per axis)
+    has 306 tiles of 512 atoms, more than the device's 256 CUs: the LJ pass
+    compiled for two blocks per CU runs.  Forces of the input over the whole
+    system, and the first ten FP64 iterations (folded update, graph replays),
+    against the oracle."""
+    s = inputs.lj_bulk(ncell=34)
+    assert len(s.pos) // 512 + 1 > 256
+    c = api.Context(0, s.fire, precision="fp64")
+    e, f = c.fire_energy_forces(s.pos, s.box, s.potential)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 10)
+    c.close()
+    with oracle.cells():
+        e_ref, f_ref = oracle.energy_forces(s.pos, s.box, s.potential)
+        ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 0.0, 10)
+    assert abs(e - e_ref) <= 1e-12 * abs(e_ref)
+    assert np.abs(f - f_ref).max() <= 1e-12 * np.abs(f_ref).max()
+    assert r["stop"] == ref["stop"] == "max_steps" and r["iterations"] == 10
+    d = r["pos"] - ref["pos"]
+    L = np.array(s.box.length)
+    d -= L * np.rint(d / L)
+    print(f"n {len(s.pos)}: 10 iterations, max|dx| {np.abs(d).max():.3e}")
+    assert np.abs(d).max() <= 1e-12
