@@ -201,8 +201,10 @@ const char* fire_last_error(const fire_ctx* ctx);
  * cached per context and in $FIRE_TUNE_CACHE.single (default
  * ~/.cache/fire2_tune_single.txt).  After a batched call: the team size of
  * the persistent kernel and its chunk length, timed or from
- * $FIRE_TUNE_CACHE.  Results differ between choices only by summation
- * order.  The pointer stays valid until the next call on ctx. */
+ * $FIRE_TUNE_CACHE, and the launch plan (workgroups, and how many pairs of
+ * them share the systems of most estimated work).  Single-system results
+ * differ between choices only by summation order; batched results do not
+ * depend on the plan.  The pointer stays valid until the next call on ctx. */
 const char* fire_tuning_info(const fire_ctx* ctx);
 const char* fire_stop_name(int stop_reason);
 
