@@ -588,6 +588,8 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
             cells[b] = up ? hi : lo;
           }
         }
+    // this lane's list: entry k at lb[(k / 4) * 256 + k % 4] (lidx)
+    int* const lb = nbr + (size_t)w * (kcap >> 2) * 256 + lane * 4;
     for (int q = 0; q < nc; ++q) {
       const int cell = cells[q];
       // candidates in groups of 8: all loads issued before the tests, so
@@ -597,23 +599,24 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double4* __restrict_
         float4 pj[kG];
 #pragma unroll
         for (int u = 0; u < kG; ++u) pj[u] = posf[min(j0 + u, e - 1)];
+        // the tests as masks rather than branches (the exec-mask bookkeeping
+        // of nested divergent branches had cost more than the tests)
 #pragma unroll
         for (int u = 0; u < kG; ++u) {
           const int j = j0 + u;
-          if (j >= e) break;
-          if (j == i) continue;
           const float dx = pf.x - pj[u].x, dy = pf.y - pj[u].y, dz = pf.z - pj[u].z;
           const float r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == 0.0f) {  // equal in FP32: compare the FP64 positions
+          const bool cand = j < e && j != i;
+          if (cand && r2 == 0.0f) {  // equal in FP32: compare the FP64 positions
             const double4 q = pos[j];
             if (q.x == pi.x && q.y == pi.y && q.z == pi.z) overlap = true;
           }
-          if (r2 < rcs2f) {
-            const bool near = r2 < split2f, mid = !near && r2 < cut2f;
-            if (cn + cb < kcap) nbr[lidx(w, near ? cn : kcap - 1 - cb, lane, kcap)] = mid ? -(j + 1) : j;
-            cn += near;
-            cb += !near;
-          }
+          const bool acc = cand && r2 < rcs2f;
+          const bool near = r2 < split2f, mid = !near && r2 < cut2f;
+          const int k = near ? cn : kcap - 1 - cb;
+          if (acc && cn + cb < kcap) lb[((k >> 2) << 8) + (k & 3)] = mid ? -(j + 1) : j;
+          cn += acc && near;
+          cb += acc && !near;
         }
       }
     }
