@@ -776,12 +776,6 @@ __global__ __launch_bounds__(TILE) void k_tile_halo(const int* __restrict__ sran
   // group interleave their LDS reads instead of waiting on each other.
   int top = 1;
   while (2 * top <= nu) top *= 2;
-  auto run_of_slot = [&](int j) {  // last run h with cslot[h] <= j (h = 0 if none)
-    int h = 0;
-    for (int step = top; step > 0; step >>= 1)
-      if (h + step < nu && cslot[h + step] <= j) h += step;
-    return h;
-  };
   // pass 1: candidate index of every list entry, marked in the bitmap and
   // kept in nbr16 until the halo numbering is known (padding: 0xFFFF).
   // Lists are read a group of four at a time (one 16-byte load per lane,
@@ -795,13 +789,23 @@ __global__ __launch_bounds__(TILE) void k_tile_halo(const int* __restrict__ sran
     const int4 g4 = next;
     if (k + 4 < kw) next = group(k + 4);
     const int jv[4] = {g4.x, g4.y, g4.z, g4.w};
+    // for each entry the last run h with cslot[h] <= j (h = 0 if none); the
+    // four searches step together, so their LDS reads are in flight at once
+    // (padding entries search too and are ignored)
+    int hv[4] = {0, 0, 0, 0};
+    for (int step = top; step > 0; step >>= 1)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = hv[u] + step;
+        if (c < nu && cslot[min(c, nu - 1)] <= jv[u]) hv[u] = c;
+      }
     int qv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = jv[u];
       int q = 0xFFFF;
       if (j != dummy) {
-        const int h = run_of_slot(j);
+        const int h = hv[u];
         q = hoff[h] + (j - cslot[h]);
         if (j < cslot[h] || q >= hoff[h + 1]) {  // not among the candidates: cannot happen for valid lists
           atomicOr(&flags[3], 4);
