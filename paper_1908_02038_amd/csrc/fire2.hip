@@ -299,6 +299,25 @@ __device__ __forceinline__ int slot_count(int n, const int* __restrict__ gtot, i
   return n + min(*gtot, gmax);
 }
 
+// counter[c] += 1 for every active lane, with one atomic per distinct c in
+// the wave (slots follow the cells of the last build, so a wave's lanes share
+// few cells); returns each lane's place among the additions to its counter,
+// as atomicAdd would (in lane order within the wave).
+__device__ __forceinline__ int wave_add_one(int* __restrict__ counter, int c) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    const int cl = __builtin_amdgcn_readfirstlane(c);
+    const unsigned long long peers = __builtin_amdgcn_ballot_w64(c == cl);
+    if (c == cl) {
+      const int leader = __builtin_ffsll((long long)peers) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&counter[cl], __popcll(peers));
+      base = __shfl(base, leader, 64);
+      return base + __popcll(peers & ((1ull << lane) - 1));
+    }
+  }
+}
+
 // Cell of every slot (real and ghost) and per-cell counts.  Ordering key
 // inside a cell: caller index times 64, plus the ghost's shift code.
 __global__ void k_cell_count(const double4* __restrict__ pos, int n, const int* __restrict__ gtot, int gmax, Grid g,
@@ -323,7 +342,7 @@ __global__ void k_cell_count(const double4* __restrict__ pos, int n, const int* 
   cell_of[i] = c;
   // unique per slot: a ghost's shift code (1..63) follows its source's index
   key[i] = i < n ? 64LL * id[i] : 64LL * id[gsrc[i - n]] + gcode[i - n];
-  atomicAdd(&count[c], 1);
+  wave_add_one(count, c);
 }
 
 // Exclusive prefix sum start[0..m] of count[0..m) (start[m] = total) in three
@@ -405,8 +424,8 @@ __global__ void k_cell_fill(const int* __restrict__ cell_of, int n, const int* _
                             const int* __restrict__ start, int* __restrict__ cursor, int* __restrict__ order) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= slot_count(n, gtot, gmax)) return;
-  int c = cell_of[i];
-  order[start[c] + atomicAdd(&cursor[c], 1)] = i;
+  const int c = cell_of[i];
+  order[start[c] + wave_add_one(cursor, c)] = i;  // any order: k_cell_rank sorts each cell
 }
 
 // Deterministic order inside each cell: by key.  One thread per slot ranks
