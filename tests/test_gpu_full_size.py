@@ -190,3 +190,28 @@ def test_lj_beyond_one_tile_per_cu_matches_oracle(api):
     d -= L * np.rint(d / L)
     print(f"n {len(s.pos)}: 10 iterations, max|dx| {np.abs(d).max():.3e}")
     assert np.abs(d).max() <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+def test_lj_beyond_one_tile_per_cu_fp32_pair_terms(api, precision):
+    """The same 156,430-atom crystal (306 tiles, the two-blocks-per-CU pass)
+    with FP32 pair terms: forces of the input against the oracle's within
+    2e-5 max|F| + 1e-6, the energy within 1e-6 relative, and ten iterations
+    that stay finite and keep the energy within 1e-6 of the oracle's path."""
+    s = inputs.lj_bulk(ncell=34)
+    c = api.Context(0, s.fire, precision=precision)
+    e, f = c.fire_energy_forces(s.pos, s.box, s.potential)
+    r = c.fire_minimize(s.pos, s.box, s.potential, 0.0, 10)
+    c.close()
+    with oracle.cells():
+        e_ref, f_ref = oracle.energy_forces(s.pos, s.box, s.potential)
+        ref = oracle.fire_minimize(s.pos, s.box, s.potential, s.fire, 0.0, 10)
+    err = np.abs(f - f_ref).max()
+    print(f"n {len(s.pos)} {precision}: max|F| {np.abs(f_ref).max():.4g}, max err {err:.3e}, "
+          f"E after 10 iterations {r['energy']!r} against {ref['energy']!r}")
+    assert err <= 2e-5 * np.abs(f_ref).max() + 1e-6
+    assert abs(e - e_ref) <= 1e-6 * abs(e_ref)
+    assert r["stop"] == "max_steps" and r["iterations"] == 10
+    assert np.isfinite(r["pos"]).all()
+    assert abs(r["energy"] - ref["energy"]) <= 1e-6 * abs(ref["energy"])
+
