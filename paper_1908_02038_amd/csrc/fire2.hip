@@ -1309,11 +1309,12 @@ struct Tiles {
 // Position of the list padding slot: far outside any system, finite in FP32.
 constexpr double kFar = 1.0e20;
 
-// A tile's halo in LDS, S = H + 1 entries (entry H is the far padding atom).
-// Positions only: (x, y) pairs in the first 2S doubles and z in [2S, 3S), so
-// a neighbour costs one 16-byte and one 8-byte LDS read (1-2 % faster on the
-// LJ relaxations than three arrays, the same bytes).  The EAM force pass,
-// which also reads F'(rho), keeps x, y, z and F'(rho) as four arrays of S.
+// A tile's halo in LDS, S = H + 1 entries (entry H is the far padding atom):
+// (x, y) pairs in the first 2S doubles, then z in [2S, 3S) or, with F'(rho)
+// (the EAM force pass), (z, F'(rho)) pairs in [2S, 4S).  A neighbour costs
+// one 16-byte read and one 8- or 16-byte read (against three or four 8-byte
+// reads of separate arrays, the same bytes: LJ and EAM-form relaxations
+// 1-2 % faster).
 struct Halo {
   const double* a;
   int S;
@@ -1340,27 +1341,15 @@ __device__ __forceinline__ Halo stage_halo(const double4* __restrict__ pos, cons
     for (int u = 0; u < 4; ++u)
       if (idx[u] >= 0) {
         const int q = q0 + u * step;
-        if constexpr (!W) {
-          reinterpret_cast<double2*>(h)[q] = make_double2(v[u].x, v[u].y);
-          h[2 * S + q] = v[u].z;
-        } else {
-          h[q] = v[u].x;
-          h[S + q] = v[u].y;
-          h[2 * S + q] = v[u].z;
-          h[3 * S + q] = v[u].w;
-        }
+        reinterpret_cast<double2*>(h)[q] = make_double2(v[u].x, v[u].y);
+        if constexpr (W) reinterpret_cast<double2*>(h)[S + q] = make_double2(v[u].z, v[u].w);
+        else h[2 * S + q] = v[u].z;
       }
   }
   if (threadIdx.x == 0) {
-    if constexpr (!W) {
-      reinterpret_cast<double2*>(h)[H] = make_double2(kFar, kFar);
-      h[2 * S + H] = kFar;
-    } else {
-      h[H] = kFar;
-      h[S + H] = kFar;
-      h[2 * S + H] = kFar;
-      h[3 * S + H] = 0.0;
-    }
+    reinterpret_cast<double2*>(h)[H] = make_double2(kFar, kFar);
+    if constexpr (W) reinterpret_cast<double2*>(h)[S + H] = make_double2(kFar, 0.0);
+    else h[2 * S + H] = kFar;
   }
   __syncthreads();
   return Halo{h, S};
@@ -1384,17 +1373,15 @@ __device__ __forceinline__ void for_neighbours(const double4* __restrict__ pos, 
   const size_t base = (size_t)w * (kcap >> 2) * 64 + lane;
   if constexpr (LDS) {
     const ushort4* l4 = reinterpret_cast<const ushort4*>(tl.nbr16) + base;
-    const double* hx = halo.a;
-    const double* hy = halo.a + halo.S;
-    const double* hz = halo.a + 2 * halo.S;
-    const double* hw = halo.a + 3 * halo.S;
     const double2* hxy = reinterpret_cast<const double2*>(halo.a);
+    const double* hz = halo.a + 2 * halo.S;
     auto at = [&](int c) {
-      if constexpr (!W) {
-        const double2 xy = hxy[c];
-        return make_double4(xy.x, xy.y, hz[c], 0.0);
+      const double2 xy = hxy[c];
+      if constexpr (W) {
+        const double2 zw = hxy[halo.S + c];
+        return make_double4(xy.x, xy.y, zw.x, zw.y);
       } else {
-        return make_double4(hx[c], hy[c], hz[c], hw[c]);
+        return make_double4(xy.x, xy.y, hz[c], 0.0);
       }
     };
     ushort4 a = make_ushort4(0, 0, 0, 0), b = a;
